@@ -1,0 +1,471 @@
+"""Pins of the FP64 oracle against things other than itself: values the paper
+prints (Table I, Fig. 5), closed forms, invariants, library routines and
+brute force.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage
+import torch
+
+import oracle as O
+from paper_2403_11651_amd import workloads as WL
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KEYS = np.array([-0.0234375, -0.0703125, 0.2265625, 0.8671875, 0.8671875, 0.2265625, -0.0703125, -0.0234375])
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------- architecture
+def test_table1_parameter_counts():
+    """Table I prints 281 / 525 / 941 / 1925 parameters."""
+    for row in _golden("table1.json")["rows"]:
+        *_, total = O.table1_param_count(row["arm_width"], row["arm_hidden"], row["tconv_k"],
+                                         row["syn_hidden"], row["syn_res"])
+        assert total == row["params"], row
+
+
+def test_mac_counts_against_table1_and_fig5():
+    """Table I labels 300 / 545 / 1079 / 2300 MAC/pixel; Fig. 5's best-RD
+    abscissae divided by 3 N (Eq. (2)) with the common N = 102950 give the
+    decoder complexity the figure used.  The exact count at 768x512 must be
+    within 1 % of the label and within 0.5 % of the Fig. 5 value."""
+    for row in _golden("table1.json")["rows"]:
+        *_, mac = O.mac_per_pixel(row["arm_width"], row["arm_hidden"], row["tconv_k"],
+                                  row["syn_hidden"], row["syn_res"])
+        assert abs(mac - row["label_mac"]) / row["label_mac"] < 0.01, (mac, row)
+        fig5 = row["kappa_enc_best"] / (3 * 102950)
+        assert abs(mac - fig5) / fig5 < 0.005, (mac, fig5)
+
+
+def test_config_param_sizes():
+    assert O.param_sizes(O.FULL) == (1250, 96, 611)
+    assert O.param_sizes(O.LOW) == (162, 96, 263)
+    # separable per-level upsampler variant of the 2300 row: 2207.2 MAC/pixel
+    *_, mac = O.mac_per_pixel(24, 2, 8, 40, 2, separable=True)
+    assert abs(mac - 2207.236328125) < 1e-9
+
+
+# --------------------------------------------------------------- context set
+def test_context_sets():
+    s24 = O.context_offsets(24)
+    assert len(set(s24)) == 24
+    # the whole causal half of the 7x7 window
+    assert set(s24) == {(dy, dx) for dy in (-3, -2, -1) for dx in range(-3, 4)} | {(0, -3), (0, -2), (0, -1)}
+    s8 = O.context_offsets(8)
+    assert s8 == [(-2, -1), (-2, 0), (-2, 1), (-1, -1), (-1, 0), (-1, 1), (0, -2), (0, -1)]
+    for offs in (s8, s24, O.context_offsets(16)):
+        assert all(dy < 0 or (dy == 0 and dx < 0) for dy, dx in offs)  # strictly causal
+        assert offs == sorted(offs)                                       # raster order
+    d2 = sorted(dy * dy + dx * dx for dy, dx in s8)
+    assert d2 == [1, 1, 2, 2, 4, 4, 5, 5]
+
+
+# --------------------------------------------------------------- Laplace rate
+def test_laplace_mass_sums_to_one():
+    ks = np.arange(-200, 201, dtype=float)
+    P = O.laplace_mass(ks, 0.3, 0.7)
+    assert abs(P.sum() - 1.0) < 1e-14
+    assert np.all(P > 0)
+
+
+def test_laplace_partial_sum_shortfall_closed_form():
+    """Sum over k in [-K, K] telescopes to F(K+1/2) - F(-K-1/2): the shortfall
+    is exactly (1/2) e^{-(K+1/2-mu)/b} + (1/2) e^{-(K+1/2+mu)/b}."""
+    for mu, b, K in [(0.3, 0.7, 3), (-1.2, 2.5, 5), (0.0, 0.2, 1)]:
+        ks = np.arange(-K, K + 1, dtype=float)
+        short = 1.0 - O.laplace_mass(ks, mu, b).sum()
+        exact = 0.5 * math.exp(-(K + 0.5 - mu) / b) + 0.5 * math.exp(-(K + 0.5 + mu) / b)
+        assert abs(short - exact) < 1e-14 * max(1.0, 1.0 / exact) + 1e-15
+
+
+def test_rate_closed_forms():
+    for c in _golden("laplace_rate.json")["cases"]:
+        r = O.rate_bits(np.array([c["y"]]), np.array([c["mu"]]), np.array([math.log(c["b"])]))
+        assert abs(r[0] - c["bits"]) < 1e-9, c
+
+
+def test_rate_tail_closed_form_and_symmetry():
+    rng = np.random.default_rng(0)
+    mu = rng.uniform(-3, 3, 200)
+    b = np.exp(rng.uniform(math.log(0.05), math.log(20), 200))
+    y = np.rint(mu + rng.uniform(-8, 8, 200))
+    d = y - mu
+    r = O.rate_bits(y, mu, np.log(b))
+    far = np.abs(d) >= 0.5
+    closed = (np.abs(d) - 0.5) / (b * math.log(2)) + 1 - np.log2(-np.expm1(-1.0 / b))
+    assert np.allclose(r[far], closed[far], rtol=1e-11, atol=1e-11)
+    # r(mu + d) = r(mu - d): reflect y about mu (non-integer y is fine for P)
+    r2 = O.rate_bits(2 * mu - y, mu, np.log(b))
+    assert np.allclose(r, r2, rtol=1e-11, atol=1e-12)
+
+
+def test_rate_scale_clamp():
+    y, mu = np.array([2.0]), np.array([0.0])
+    assert O.rate_bits(y, mu, np.array([50.0]))[0] == O.rate_bits(y, mu, np.array([math.log(100.0)]))[0]
+    assert O.rate_bits(y, mu, np.array([-50.0]))[0] == O.rate_bits(y, mu, np.array([math.log(0.01)]))[0]
+    _, _, ds = O.rate_grads(y, mu, np.array([50.0]))
+    assert ds[0] == 0.0
+
+
+def test_rate_gradients_against_central_differences():
+    rng = np.random.default_rng(1)
+    y = np.rint(rng.uniform(-6, 6, 300))
+    mu = rng.uniform(-4, 4, 300)
+    s = rng.uniform(-3, 3, 300)
+    gy, gmu, gs = O.rate_grads(y, mu, s)
+    h = 1e-6
+    fd_mu = (O.rate_bits(y, mu + h, s) - O.rate_bits(y, mu - h, s)) / (2 * h)
+    fd_s = (O.rate_bits(y, mu, s + h) - O.rate_bits(y, mu, s - h)) / (2 * h)
+    fd_y = (O.rate_bits(y + h, mu, s) - O.rate_bits(y - h, mu, s)) / (2 * h)
+    for a, f in ((gmu, fd_mu), (gs, fd_s), (gy, fd_y)):
+        assert np.allclose(a, f, rtol=1e-6, atol=1e-6)
+
+
+# --------------------------------------------------------------- ARM
+def _arm_params(C, n_hidden, seed, zero_w=False):
+    rng = np.random.default_rng(seed)
+    hidden = []
+    for _ in range(n_hidden):
+        W = np.zeros((C, C)) if zero_w else rng.normal(0, 0.1, (C, C))
+        hidden.append((W, rng.normal(0, 0.1, C)))
+    Wo = np.zeros((2, C)) if zero_w else rng.normal(0, 0.1, (2, C))
+    return dict(hidden=hidden, Wo=Wo, bo=rng.normal(0, 0.3, 2))
+
+
+def test_all_zero_latents_closed_form_rate():
+    """All-zero y_hat: every context is 0, so (mu, s) = ARM(0) is the same for
+    all latents and R = N_lat * r(0 | mu0, b0); with zero weights (mu0, s0) = bo."""
+    arch = O.FULL
+    H, W = 64, 128
+    n_arm, n_ups, n_syn = O.param_sizes(arch)
+    n_lat = sum(h * w for h, w in O.level_shapes(H, W, 7))
+    img = np.zeros((3, H, W))
+    for zero_w in (True, False):
+        P = _arm_params(24, 2, 5, zero_w)
+        arm = np.concatenate([np.ravel(a) for hw in P["hidden"] for a in hw] + [P["Wo"].ravel(), P["bo"]])
+        out = O.forward(arch, img, np.zeros(n_lat), arm, np.zeros(n_ups), np.zeros(n_syn), 0.001)
+        h0 = np.zeros(24)
+        for (Wj, bj) in P["hidden"]:
+            h0 = np.maximum(Wj @ h0 + bj + h0, 0)
+        mu0, s0 = P["Wo"] @ h0 + P["bo"]
+        if zero_w:
+            assert (mu0, s0) == tuple(P["bo"])
+        b0 = math.exp(min(max(s0, math.log(0.01)), math.log(100)))
+        F = lambda x: 0.5 * math.exp((x - mu0) / b0) if x < mu0 else 1 - 0.5 * math.exp(-(x - mu0) / b0)  # noqa: E731
+        r0 = -math.log2(F(0.5) - F(-0.5))
+        assert abs(out["R"] - n_lat * r0) < 1e-9 * n_lat * r0
+
+
+def test_arm_causality():
+    """Perturbing a latent, any raster-later latent of its grid, or another
+    grid, leaves its (mu, s) unchanged bit for bit."""
+    rng = np.random.default_rng(2)
+    P = _arm_params(24, 2, 7)
+    offs = O.context_offsets(24)
+    lv = np.rint(rng.laplace(0, 2, (12, 16)))
+    mu, s, _ = O.arm_forward(O.gather_context(lv, offs), P)
+    for (i, j) in [(0, 0), (5, 7), (11, 15), (6, 0), (3, 15)]:
+        lv2 = lv.copy()
+        flat = lv2.ravel()
+        k = i * 16 + j
+        flat[k:] += rng.normal(0, 5, flat.size - k)      # this latent and all later ones
+        mu2, s2, _ = O.arm_forward(O.gather_context(lv2, offs), P)
+        assert np.array_equal(mu2[:k + 1], mu[:k + 1]) and np.array_equal(s2[:k + 1], s[:k + 1])
+        # and the dependence on an earlier neighbour is real
+        nb = (i, j - 1) if j > 0 else (i - 1, j)
+        if nb[0] >= 0:
+            lv3 = lv.copy()
+            lv3[nb] += 3.0
+            mu3, _, _ = O.arm_forward(O.gather_context(lv3, offs), P)
+            assert mu3[k] != mu[k]
+
+
+def test_arm_vectorised_matches_per_latent_loop():
+    rng = np.random.default_rng(3)
+    for C in (8, 24):
+        P = _arm_params(C, 2, 11)
+        offs = O.context_offsets(C)
+        lv = np.rint(rng.laplace(0, 1.5, (9, 11)))
+        mu, s, _ = O.arm_forward(O.gather_context(lv, offs), P)
+        h_, w_ = lv.shape
+        for i in range(h_):
+            for j in range(w_):
+                c = np.array([lv[i + dy, j + dx] if 0 <= i + dy < h_ and 0 <= j + dx < w_ else 0.0
+                              for dy, dx in offs])
+                h = c
+                for (Wj, bj) in P["hidden"]:
+                    h = np.array([max(0.0, sum(Wj[o, q] * h[q] for q in range(C)) + bj[o] + h[o])
+                                  for o in range(C)])
+                m = sum(P["Wo"][0, q] * h[q] for q in range(C)) + P["bo"][0]
+                sc = sum(P["Wo"][1, q] * h[q] for q in range(C)) + P["bo"][1]
+                assert abs(m - mu[i * w_ + j]) < 1e-12 and abs(sc - s[i * w_ + j]) < 1e-12
+
+
+# --------------------------------------------------------------- upsampling
+def test_tconv_matches_torch_conv_transpose():
+    """out = conv_transpose1d(replicate-pad(a, 2), w, stride 2, padding p + 4)."""
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 3, 7, 12):
+        a = rng.normal(size=(3, n))
+        w = rng.normal(size=8)
+        ours = O.tconv1d(a, w, axis=-1)
+        t = torch.from_numpy(a)[:, None, :]
+        tp = torch.nn.functional.pad(t, (2, 2), mode="replicate")
+        ref = torch.nn.functional.conv_transpose1d(tp, torch.from_numpy(w)[None, None], stride=2, padding=7)
+        assert np.allclose(ours, ref[:, 0].numpy(), rtol=0, atol=1e-13), n
+        # 2-D separable step against conv_transpose2d with the outer-product kernel
+    a = rng.normal(size=(2, 5, 6))
+    v, h = rng.normal(size=8), rng.normal(size=8)
+    ours = O.upsample2x(a, v, h)
+    tp = torch.nn.functional.pad(torch.from_numpy(a)[:, None], (2, 2, 2, 2), mode="replicate")
+    k = torch.from_numpy(np.outer(v, h))[None, None]
+    ref = torch.nn.functional.conv_transpose2d(tp, k, stride=2, padding=7)[:, 0].numpy()
+    assert np.allclose(ours, ref, atol=1e-12)
+
+
+def test_upsample_constant_and_ramps_with_keys_kernel():
+    """Keys (a = -1/2) cubic taps have phase sums 1: a constant grid upsamples
+    to the same constant at every pixel, borders included; linear and
+    quadratic ramps are reproduced exactly away from the borders."""
+    assert KEYS[0::2].sum() == 1.0 and KEYS[1::2].sum() == 1.0
+    c = np.full((1, 6, 9), 3.25)
+    assert np.array_equal(O.upsample2x(c, KEYS, KEYS), np.full((1, 12, 18), 3.25))
+    n = 16
+    for f in (lambda x: 2.0 * x - 1.0, lambda x: 0.5 * x * x - x):
+        a = f(np.arange(n, dtype=float))
+        out = O.tconv1d(a[None], KEYS, axis=-1)[0]
+        # output sample j sits at input coordinate (j - 1/2) / 2
+        xs = (np.arange(2 * n) - 0.5) / 2.0
+        inner = slice(6, 2 * n - 6)
+        assert np.allclose(out[inner], f(xs[inner]), atol=1e-12)
+
+
+def test_tconv_adjoint_is_transpose():
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(2, 7, 5))
+    w = rng.normal(size=8)
+    g = rng.normal(size=(2, 14, 5))
+    out = O.tconv1d(a, w, axis=1)
+    ga, gw = O.tconv1d_adjoint(g, a, w, axis=1)
+    assert abs(np.sum(out * g) - np.sum(a * ga)) < 1e-11
+    eps = 1e-6
+    for k in range(8):
+        w2 = w.copy(); w2[k] += eps
+        w3 = w.copy(); w3[k] -= eps
+        fd = (np.sum(O.tconv1d(a, w2, 1) * g) - np.sum(O.tconv1d(a, w3, 1) * g)) / (2 * eps)
+        assert abs(fd - gw[k]) < 1e-7
+
+
+# --------------------------------------------------------------- synthesis
+def test_conv3x3_matches_scipy_correlate():
+    rng = np.random.default_rng(6)
+    t = rng.normal(size=(3, 9, 13))
+    W = rng.normal(size=(3, 3, 3, 3))
+    b = rng.normal(size=3)
+    ours = O.conv3x3_replicate(t, W, b)
+    for o in range(3):
+        ref = b[o] + sum(scipy.ndimage.correlate(t[c], W[o, c], mode="nearest") for c in range(3))
+        assert np.allclose(ours[o], ref, atol=1e-12)
+
+
+def test_synthesis_zero_input_closed_form():
+    """z = 0: a = ReLU(b1), t0 = ReLU(W2 a + b2); a constant image goes through
+    each residual conv as t <- phi(t + (sum over taps of W) t + b)."""
+    rng = np.random.default_rng(7)
+    arch = O.FULL
+    _, _, n_syn = O.param_sizes(arch)
+    P = O.unpack(arch, np.zeros(1250), np.zeros(96), rng.normal(0, 0.3, n_syn))
+    xhat, _ = O.synthesis(np.zeros((7, 5, 6)), P)
+    t = np.maximum(P["W2"] @ np.maximum(P["b1"], 0) + P["b2"], 0)
+    for r, (Wr, br) in enumerate(P["res"]):
+        pre = t + Wr.sum(axis=(2, 3)) @ t + br
+        t = np.maximum(pre, 0) if r < len(P["res"]) - 1 else pre
+    assert np.allclose(xhat, t[:, None, None] * np.ones((3, 5, 6)), atol=1e-13)
+
+
+# --------------------------------------------------------------- quantisation
+def test_quantise_rounds_half_to_even():
+    y = np.array([0.5, 1.5, 2.5, -0.5, -1.5, 0.49999997, 2.5000002], dtype=np.float32)
+    assert np.array_equal(O.quantise(y), [0.0, 2.0, 2.0, -0.0, -2.0, 0.0, 3.0])
+
+
+# --------------------------------------------------------------- gradients
+def _fd_instance():
+    arch = O.FD16
+    sd = WL.SEEDS["fd16"]
+    H = W = 16
+    n_lat = sum(h * w for h, w in O.level_shapes(H, W, arch.n_levels))
+    n_arm, n_ups, n_syn = O.param_sizes(arch)
+    img = WL.image(sd["image"], H, W, 4).astype(np.float64)
+    y = WL.latents(sd["latents"], H, W, arch.n_levels).astype(np.float64)
+    u = WL.noise(sd["noise"], n_lat).astype(np.float64)
+    w = WL.weights(sd["weights"], n_arm + n_ups + n_syn).astype(np.float64)
+    return arch, img, y, u, w[:n_arm], w[n_arm:n_arm + n_ups], w[n_arm + n_ups:]
+
+
+def _kink_margin(arch, img, y, u, arm, ups, syn):
+    """Smallest distance of any ReLU / clamp input to its kink."""
+    P = O.unpack(arch, arm, ups, syn)
+    yq = O.quantise(y, u)
+    H, W = img.shape[1:]
+    levels = O.split_levels(yq, H, W, arch.n_levels)
+    offs = O.context_offsets(arch.arm_ctx)
+    m = np.inf
+    for lv in levels:
+        h = O.gather_context(lv, offs)
+        for (Wj, bj) in P["hidden"]:
+            pre = h @ Wj.T + bj + h
+            m = min(m, np.min(np.abs(pre)))
+            h = np.maximum(pre, 0)
+    z, _ = O.upsample_pyramid(levels, P["ups"])
+    _, c = O.synthesis(z, P)
+    for k in ("pre_a", "pre_t"):
+        m = min(m, np.min(np.abs(c[k])))
+    for pre in c["pres"][:-1]:
+        m = min(m, np.min(np.abs(pre)))
+    return m
+
+
+def test_backward_matches_central_differences_16x16():
+    """Every latent and every parameter of the 16x16, 5-level instance:
+    central differences (h = 1e-6) of the FP64 loss vs the hand adjoint."""
+    arch, img, y, u, arm, ups, syn = _fd_instance()
+    # no ReLU / clamp input may sit within reach of a +-h step: the largest
+    # sensitivity of a pre-activation to one input here is below 10, so a
+    # margin of 1e-5 keeps every kink out of the +-1e-6 stencil
+    assert _kink_margin(arch, img, y, u, arm, ups, syn) > 1e-5
+    lam = 0.001
+    out = O.backward(arch, img, y, arm, ups, syn, lam, u=u)
+    f = lambda yy, a, p, s: O.forward(arch, img, yy, a, p, s, lam, u=u)["loss"]  # noqa: E731
+    h = 1e-6
+    checks = [("g_y", y, lambda v: (v, arm, ups, syn)),
+              ("g_arm", arm, lambda v: (y, v, ups, syn)),
+              ("g_ups", ups, lambda v: (y, arm, v, syn)),
+              ("g_syn", syn, lambda v: (y, arm, ups, v))]
+    for name, base, mk in checks:
+        g = out[name]
+        fd = np.empty_like(base)
+        for i in range(base.size):
+            vp = base.copy(); vp[i] += h
+            vm = base.copy(); vm[i] -= h
+            fd[i] = (f(*mk(vp)) - f(*mk(vm))) / (2 * h)
+        scale = np.max(np.abs(g))
+        assert np.max(np.abs(fd - g)) <= 1e-6 * scale + 1e-12, (name, np.max(np.abs(fd - g)), scale)
+
+
+def _torch_forward(arch, img, y, arm, ups, syn, lam, u=None):
+    """Independent torch float64 formulation (library ops only) of Eq. (1)."""
+    F = torch.nn.functional
+    H, W = img.shape[1:]
+    L, C, K, Hs = arch.n_levels, arch.arm_ctx, arch.ups_taps, arch.syn_hidden
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    yv = t(y).requires_grad_(True)
+    aw, uw, sw = (t(a).requires_grad_(True) for a in (arm, ups, syn))
+    yq = yv + (torch.round(yv) - yv).detach() if u is None else yv + t(u)
+    # ARM parameters
+    o, hidden = 0, []
+    for _ in range(arch.arm_layers):
+        Wj = aw[o:o + C * C].view(C, C); o += C * C
+        bj = aw[o:o + C]; o += C
+        hidden.append((Wj, bj))
+    Wo = aw[o:o + 2 * C].view(2, C); o += 2 * C
+    bo = aw[o:o + 2]
+    offs = O.context_offsets(C)
+    R = 0.0
+    levels, o = [], 0
+    for l in range(L):
+        h_, w_ = H >> l, W >> l
+        lv = yq[o:o + h_ * w_].view(h_, w_); o += h_ * w_
+        levels.append(lv)
+        Pd = F.pad(lv[None, None], (3, 3, 3, 3))[0, 0]
+        ctx = torch.stack([Pd[3 + dy:3 + dy + h_, 3 + dx:3 + dx + w_].reshape(-1) for dy, dx in offs], 1)
+        hcur = ctx
+        for (Wj, bj) in hidden:
+            hcur = torch.relu(hcur @ Wj.T + bj + hcur)
+        out = hcur @ Wo.T + bo
+        mu, s = out[:, 0], out[:, 1]
+        b = torch.exp(torch.clamp(s, math.log(0.01), math.log(100)))
+        q = lv.reshape(-1)
+        # Laplace CDF below the mean, survival function above it, each as a
+        # single exponential so that tails keep their relative precision
+        cdf = lambda x: 0.5 * torch.exp(torch.clamp((x - mu) / b, max=0.0))  # noqa: E731
+        sf = lambda x: 0.5 * torch.exp(torch.clamp(-(x - mu) / b, max=0.0))  # noqa: E731
+        lo, hi = q - 0.5, q + 0.5
+        Pm = torch.where(lo >= mu, sf(lo) - sf(hi),
+                         torch.where(hi <= mu, cdf(hi) - cdf(lo), 1.0 - sf(hi) - cdf(lo)))
+        R = R + torch.sum(-torch.log2(Pm))
+    # upsampling via conv_transpose on replicate-padded grids
+    U = uw.view(L - 1, 2, K)
+    stack = levels[L - 1][None, None]
+    for s_ in range(L - 2, -1, -1):
+        kern = torch.outer(U[s_, 0], U[s_, 1])[None, None]
+        n = stack.shape[1]
+        xp = F.pad(stack.reshape(n, 1, *stack.shape[2:]), (2, 2, 2, 2), mode="replicate")
+        up = F.conv_transpose2d(xp, kern, stride=2, padding=K // 2 - 1 + 4).reshape(1, n, *levels[s_].shape)
+        stack = torch.cat([levels[s_][None, None], up], 1)
+    z = stack
+    o = 0
+    W1 = sw[o:o + Hs * L].view(Hs, L, 1, 1); o += Hs * L
+    b1 = sw[o:o + Hs]; o += Hs
+    W2 = sw[o:o + 3 * Hs].view(3, Hs, 1, 1); o += 3 * Hs
+    b2 = sw[o:o + 3]; o += 3
+    x = torch.relu(F.conv2d(torch.relu(F.conv2d(z, W1, b1)), W2, b2))
+    for r in range(arch.syn_res):
+        Wr = sw[o:o + 81].view(3, 3, 3, 3); o += 81
+        br = sw[o:o + 3]; o += 3
+        pre = x + F.conv2d(F.pad(x, (1, 1, 1, 1), mode="replicate"), Wr, br)
+        x = torch.relu(pre) if r < arch.syn_res - 1 else pre
+    D = torch.mean((x[0] - t(img)) ** 2)
+    loss = D + lam * R / (H * W)
+    loss.backward()
+    return float(loss.detach()), yv.grad.numpy(), aw.grad.numpy(), uw.grad.numpy(), sw.grad.numpy()
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_backward_matches_torch_autograd_64x64(noise):
+    """The 64x64, 7-level small instance in both quantisation modes."""
+    arch = O.TINY
+    sd = WL.SEEDS["tiny"]
+    H = W = 64
+    n_lat = sum(h * w for h, w in O.level_shapes(H, W, 7))
+    n_arm, n_ups, n_syn = O.param_sizes(arch)
+    img = WL.image(sd["image"], H, W, 12)
+    y = WL.latents(sd["latents"], H, W, 7, rounded=not noise)
+    w = WL.weights(sd["weights"], n_arm + n_ups + n_syn)
+    u = WL.noise(sd["noise"], n_lat) if noise else None
+    arm, ups, syn = w[:n_arm], w[n_arm:n_arm + n_ups], w[n_arm + n_ups:]
+    out = O.backward(arch, img, y, arm, ups, syn, 0.001, u=u)
+    loss, gy, ga, gu, gs = _torch_forward(arch, img, y, arm, ups, syn, 0.001, u=u)
+    assert abs(out["loss"] - loss) <= 1e-10 * abs(loss)
+    for a, b in ((out["g_y"], gy), (out["g_arm"], ga), (out["g_ups"], gu), (out["g_syn"], gs)):
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+
+
+def test_straight_through_equals_noise_gradient_at_same_point():
+    """With u = rint(y) - y the noise proxy reaches the same y_hat as rounding,
+    and its (exact) gradient equals the straight-through one."""
+    arch, img, y, _, arm, ups, syn = _fd_instance()
+    u = np.rint(y) - y
+    a = O.backward(arch, img, y, arm, ups, syn, 0.001)
+    b = O.backward(arch, img, y, arm, ups, syn, 0.001, u=u)
+    assert np.array_equal(a["yq"], b["yq"]) and np.array_equal(a["g_y"], b["g_y"])
+
+
+# --------------------------------------------------------------- Adam
+def test_adam_first_steps_closed_form():
+    """At t = 1 the bias-corrected step is lr * g / (|g| + eps); a constant
+    gradient keeps the step at lr * g / (|g| + eps) for every t."""
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th, m, v = O.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    for t in range(2, 6):
+        th2, m, v = O.adam_step(th, g, m, v, t, lr=0.01)
+        assert np.allclose(th2 - th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15)
+        th = th2
