@@ -1,0 +1,157 @@
+/*
+ * coolchic.h -- C ABI of the MI355X (gfx950) Cool-chic rate-distortion pass.
+ *
+ * The library computes, for one image, the loss of Eq. (1) of "Overfitted
+ * image coding at reduced complexity" (Blard et al.):
+ *
+ *     loss = D(x, x_hat) + lambda * R(y_hat) / (H * W)
+ *
+ * with x the image, y_hat = Q(y) the quantised latent pyramid (Section II,
+ * "Decoding" and "Encoding"), R = sum over latents of -log2 p_psi(y_hat) in bits
+ * (the ARM probability model, a Laplace distribution whose mean and log-scale
+ * the ARM MLP outputs, scale clamped to [0.01, 100], mass taken over
+ * [y_hat - 1/2, y_hat + 1/2]), D the mean over 3*H*W of the squared error, and
+ * x_hat = f_theta(f_upsilon(y_hat)) (upsampling, then synthesis; Table I layer
+ * types), together with its exact gradient w.r.t. y and every parameter
+ * (Section IV-A: one training iteration is one forward plus one backward).
+ *
+ * Conventions for every entry point:
+ *  - All float pointers are DEVICE pointers (HIP global memory) owned by the
+ *    caller; the library keeps none of them after the call returns.  Calls are
+ *    asynchronous: they only enqueue kernels on `stream` (a hipStream_t, NULL
+ *    for the default stream) and return; nothing is allocated and the host is
+ *    never synchronised, so a call can be captured into a HIP graph.
+ *  - `ws` is a caller-owned device workspace of at least
+ *    coolchic_workspace_bytes() bytes; its contents need not be initialised and
+ *    are clobbered.  Two calls that overlap in time must not share `ws`.
+ *  - Return value: CC_OK (0) or a negative CC_E* code; on error nothing has
+ *    been enqueued (except CC_EHIP, which reports a failed launch).
+ *  - Non-finite values do not fail a call: the kernels set loss4[3] to 1.0f
+ *    when any loss term or gradient is NaN or infinite (0.0f otherwise).
+ *
+ * Layouts (all float32):
+ *  - image x: planar [3][H][W], values in [0, 1].
+ *  - latent pyramid (y, u, g_y, rate_map, yq_out): one buffer, level-major; level
+ *    l (0 <= l < L) is row-major [H >> l][W >> l] starting at offset
+ *    sum_{m < l} (H >> m) * (W >> m).
+ *  - ARM parameters psi: for each hidden residual layer j: W_j [C][C] (out, in)
+ *    then b_j [C]; then W_o [2][C] (row 0 = mean, row 1 = log-scale), b_o [2].
+ *  - upsampling parameters upsilon: [L-1][2][K]; index s produces level s from
+ *    level s+1; [s][0] are the vertical taps, [s][1] the horizontal taps.
+ *  - synthesis parameters theta: W1 [Hs][L], b1 [Hs], W2 [3][Hs], b2 [3]; then
+ *    for each residual 3x3 conv r: W_r [3][3][3][3] (out, in, ky, kx), b_r [3].
+ */
+#ifndef COOLCHIC_H
+#define COOLCHIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Decoder architecture (Table I notation). */
+typedef struct {
+  int32_t n_levels;   /* L, number of latent grids, 2..7 */
+  int32_t arm_ctx;    /* C, causal neighbours fed to the ARM: 8, 16 or 24 (Table I
+                         widths); the C nearest causal positions of a 7x7
+                         window, ties in raster order, zero outside the grid */
+  int32_t arm_layers; /* hidden C-C-LinR layers before the C-2-Lin output, 1..3 */
+  int32_t ups_taps;   /* K of each 1-D stride-2 transposed conv; only 8 */
+  int32_t syn_hidden; /* width of the first 1x1 synthesis layer, 8..48, multiple of 8 */
+  int32_t syn_res;    /* number of residual 3x3 convs 3->3 (ConvR-3), 1..2 */
+} cc_arch;
+
+/* Quantisation proxy Q (Section II "Encoding"): rounding to nearest (ties to
+   even) with a straight-through gradient, or additive noise y + u with
+   u in [-1/2, 1/2) supplied by the caller. */
+enum { CC_QUANT_ROUND = 0, CC_QUANT_NOISE = 1 };
+
+typedef struct {
+  int32_t H, W;     /* image rows and columns; both multiples of 2^(L-1) */
+  cc_arch arch;
+  int32_t quant;    /* CC_QUANT_ROUND or CC_QUANT_NOISE */
+  float lambda;     /* rate weight of Eq. (1) */
+} cc_problem;
+
+enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,       /* null pointer, bad size, H/W not multiples of 2^(L-1) */
+  CC_EUNSUPPORTED = -2, /* architecture outside the compiled variants */
+  CC_EWORKSPACE = -3,   /* ws_bytes smaller than coolchic_workspace_bytes() */
+  CC_EHIP = -4          /* a kernel launch failed (hipGetLastError) */
+};
+
+enum { CC_WS_FORWARD = 0, CC_WS_BACKWARD = 1, CC_WS_DECODE = 2 };
+
+/* Number of parameters of each module; returns the total, or -1 for an
+   invalid architecture.  Output pointers are host pointers and may be NULL. */
+int64_t coolchic_param_count(const cc_arch* arch, int64_t* n_arm, int64_t* n_ups, int64_t* n_syn);
+
+/* Number of latents sum_l (H >> l) * (W >> l), or -1 if invalid. */
+int64_t coolchic_latent_count(const cc_problem* p);
+
+/* Device workspace bytes needed by coolchic_forward (which = CC_WS_FORWARD),
+   coolchic_backward (CC_WS_BACKWARD) or coolchic_decode_synth (CC_WS_DECODE);
+   0 if the problem is invalid. */
+size_t coolchic_workspace_bytes(const cc_problem* p, int which);
+
+/* Forward pass: Eq. (1) for one image.
+   img [3][H][W]; y [N_lat]; u [N_lat] (required for CC_QUANT_NOISE, ignored
+   otherwise, may be NULL); arm_w, ups_w, syn_w the packed parameters.
+   Outputs: loss4 [4] = {loss, D, R (bits), non-finite flag}; optional (NULL to
+   skip) rate_map [N_lat] per-latent rate in bits, yq_out [N_lat] quantised
+   latents, xhat_out [3][H][W] synthesised image (not clamped). */
+int coolchic_forward(const cc_problem* p, const float* img, const float* y, const float* u,
+                     const float* arm_w, const float* ups_w, const float* syn_w,
+                     float* loss4, float* rate_map, float* yq_out, float* xhat_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Forward and backward (adjoint) pass: writes loss4 exactly as
+   coolchic_forward does, and the gradient of dloss * loss w.r.t. y (g_y
+   [N_lat]; the quantiser's gradient is the identity in both modes) and w.r.t.
+   each parameter block (g_arm, g_ups, g_syn, laid out like the parameters).
+   Gradients are overwritten, not accumulated.  The result is deterministic:
+   repeated calls give bit-identical outputs. */
+int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u,
+                      const float* arm_w, const float* ups_w, const float* syn_w, float dloss,
+                      float* loss4, float* g_y, float* g_arm, float* g_ups, float* g_syn,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Decoder-side parallel work once the latents are known (Section II
+   "Decoding", upsampling then synthesis): yq [N_lat] integer-valued latents
+   (used as given), xhat [3][H][W] output, not clamped.  p->quant and
+   p->lambda are ignored. */
+int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups_w, const float* syn_w,
+                          float* xhat, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba; the optimiser the paper trains with) on n
+   parameters: m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2, theta <- theta -
+   lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps) with t = step[0] + 1.
+   step points to two device int32: step[0] is the number of steps already
+   taken (incremented by this call, on the device) and step[1] a counter that
+   must be 0 before the first call (the call leaves it at 0). */
+int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n,
+                       int32_t* step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Measurement hook (for profilers and benchmarks, not part of the method):
+   while set, every coolchic_forward / coolchic_backward call records the HIP
+   event ev_begin on its stream right before the launch of the named stage and
+   ev_end right after it, so hipEventElapsedTime(ev_begin, ev_end) is that
+   kernel's duration.  stage: CC_STAGE_NONE clears the hook; CC_STAGE_ARM is
+   the ARM kernel, CC_STAGE_SYNTHESIS the tiled synthesis kernel (residual
+   convs, and in the backward the 1x1 layers' adjoint).  The events are
+   hipEvent_t handles owned by the caller.  Process-wide setting: not
+   thread-safe; returns CC_EINVAL for an unknown stage or a missing event. */
+enum { CC_STAGE_NONE = 0, CC_STAGE_ARM = 1, CC_STAGE_SYNTHESIS = 2 };
+int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end);
+
+/* Static description of an error code. */
+const char* coolchic_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COOLCHIC_H */

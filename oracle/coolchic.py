@@ -46,7 +46,7 @@ __all__ = [
     "Arch", "TINY", "FULL", "LOW", "FD16", "param_sizes", "unpack", "pack",
     "table1_param_count", "mac_per_pixel", "level_shapes", "split_levels",
     "quantise", "context_offsets", "gather_context", "arm_forward", "laplace_mass",
-    "rate_bits", "rate_grads", "tconv1d", "tconv1d_adjoint", "upsample2x",
+    "rate_bits", "rate_grads", "log_laplace_mass", "tconv1d", "tconv1d_adjoint", "upsample2x",
     "upsample_pyramid", "conv3x3_replicate", "synthesis", "forward", "backward",
     "adam_step", "S_MIN", "S_MAX",
 ]
@@ -275,26 +275,51 @@ def laplace_mass(yq, mu, b):
     return P
 
 
+TAIL_LOG_BELOW = 1e-280   # masses below this are taken in log space
+
+
+def log_laplace_mass(yq, mu, b):
+    """Natural log of :func:`laplace_mass`.  Where the mass is too small for
+    float64 (far tails), the same difference is factored before taking the
+    log: both bounds on one side of mu give
+    F(hi) - F(lo) = (1/2) e^{-dist/b} (1 - e^{-1/b}), dist the distance from mu
+    to the nearer bound."""
+    yq, mu, b = np.broadcast_arrays(np.asarray(yq, float), np.asarray(mu, float), np.asarray(b, float))
+    P = laplace_mass(yq, mu, b)
+    out = np.empty(P.shape)
+    ok = P > TAIL_LOG_BELOW
+    out[ok] = np.log(P[ok])
+    t = ~ok
+    if t.any():
+        lo, hi = yq[t] - 0.5, yq[t] + 0.5
+        m, bb = mu[t], b[t]
+        dist = np.where(lo >= m, lo - m, m - hi)
+        assert np.all(dist >= 0), "a mass that straddles the mean cannot underflow"
+        out[t] = -dist / bb - math.log(2.0) + np.log1p(-np.exp(-1.0 / bb))
+    return out
+
+
 def rate_bits(yq, mu, s):
     """Rate of each latent in bits, -log2 p(y_hat) (Eq. (1)), with the Laplace
     scale b = exp(clamp(s, ln 0.01, ln 100))."""
     b = np.exp(np.clip(np.asarray(s, float), S_MIN, S_MAX))
-    return -np.log2(laplace_mass(yq, mu, b))
+    return -log_laplace_mass(yq, mu, b) / LN2
 
 
 def rate_grads(yq, mu, s):
     """(dr/dy_hat, dr/dmu, dr/ds) of r = -log2 P, from the derivatives of the
     CDF difference: dP/dy_hat = f(hi) - f(lo) with f the Laplace density,
     dP/dmu = -dP/dy_hat, dP/db = -[(hi-mu) f(hi) - (lo-mu) f(lo)] / b, and
-    db/ds = b inside the clamp range (bounds included), 0 outside."""
+    db/ds = b inside the clamp range (bounds included), 0 outside.  The
+    ratios f / P are formed as exp(log f - log P) so that tails stay finite."""
     yq, mu, s = (np.asarray(a, float) for a in (yq, mu, s))
     b = np.exp(np.clip(s, S_MIN, S_MAX))
     lo, hi = yq - 0.5, yq + 0.5
-    f = lambda x: np.exp(-np.abs(x - mu) / b) / (2.0 * b)  # noqa: E731
-    P = laplace_mass(yq, mu, b)
-    dP_dy = f(hi) - f(lo)
-    dP_db = -((hi - mu) * f(hi) - (lo - mu) * f(lo)) / b
-    k = -1.0 / (P * LN2)
+    logP = log_laplace_mass(yq, mu, b)
+    fr = lambda x: np.exp(-np.abs(x - mu) / b - np.log(2.0 * b) - logP)  # noqa: E731  f(x) / P
+    dP_dy = fr(hi) - fr(lo)
+    dP_db = -((hi - mu) * fr(hi) - (lo - mu) * fr(lo)) / b
+    k = -1.0 / LN2
     inside = (s >= S_MIN) & (s <= S_MAX)
     return k * dP_dy, -k * dP_dy, k * dP_db * b * inside
 

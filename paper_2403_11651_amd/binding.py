@@ -1,0 +1,212 @@
+"""ctypes binding of libcoolchic.so (include/coolchic.h).
+
+Argument marshalling only: every function passes device pointers of torch
+tensors and the current HIP stream to the C ABI of the same name; all the
+arithmetic runs in the library's HIP kernels.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoolchic.so")
+
+CC_OK, CC_EINVAL, CC_EUNSUPPORTED, CC_EWORKSPACE, CC_EHIP = 0, -1, -2, -3, -4
+CC_QUANT_ROUND, CC_QUANT_NOISE = 0, 1
+CC_WS_FORWARD, CC_WS_BACKWARD, CC_WS_DECODE = 0, 1, 2
+
+# every symbol the header declares
+EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_bytes", "coolchic_forward",
+           "coolchic_backward", "coolchic_decode_synth", "coolchic_adam_step", "coolchic_set_stage_events",
+           "coolchic_strerror")
+CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
+
+
+class CCArch(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("arm_ctx", ctypes.c_int32), ("arm_layers", ctypes.c_int32),
+                ("ups_taps", ctypes.c_int32), ("syn_hidden", ctypes.c_int32), ("syn_res", ctypes.c_int32)]
+
+
+class CCProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("arch", CCArch), ("quant", ctypes.c_int32),
+                ("lam", ctypes.c_float)]
+
+
+class CoolChicError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_11651_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, SZ, F, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float, ctypes.c_int
+    pa, pp = ctypes.POINTER(CCArch), ctypes.POINTER(CCProblem)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "coolchic_param_count": (I64, [pa, pi64, pi64, pi64]),
+        "coolchic_latent_count": (I64, [pp]),
+        "coolchic_workspace_bytes": (SZ, [pp, I]),
+        "coolchic_forward": (I, [pp, P, P, P, P, P, P, P, P, P, P, P, SZ, P]),
+        "coolchic_backward": (I, [pp, P, P, P, P, P, P, F, P, P, P, P, P, P, SZ, P]),
+        "coolchic_decode_synth": (I, [pp, P, P, P, P, P, SZ, P]),
+        "coolchic_adam_step": (I, [P, P, P, P, I64, P, F, F, F, F, P]),
+        "coolchic_set_stage_events": (I, [I, P, P]),
+        "coolchic_strerror": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype, fn.argtypes = res, args
+    return lib
+
+
+_lib = _load()
+
+
+def strerror(code: int) -> str:
+    return _lib.coolchic_strerror(int(code)).decode()
+
+
+@dataclass(frozen=True)
+class Arch:
+    """Table I style architecture (see include/coolchic.h, cc_arch)."""
+    n_levels: int = 7
+    arm_ctx: int = 24
+    arm_layers: int = 2
+    ups_taps: int = 8
+    syn_hidden: int = 40
+    syn_res: int = 2
+
+    def c(self) -> CCArch:
+        return CCArch(self.n_levels, self.arm_ctx, self.arm_layers, self.ups_taps, self.syn_hidden, self.syn_res)
+
+
+FULL = Arch(7, 24, 2, 8, 40, 2)
+LOW = Arch(7, 8, 2, 8, 16, 1)
+
+
+@dataclass(frozen=True)
+class Problem:
+    H: int
+    W: int
+    arch: Arch = FULL
+    quant: int = CC_QUANT_ROUND
+    lam: float = 1e-3
+
+    def c(self) -> CCProblem:
+        return CCProblem(self.H, self.W, self.arch.c(), self.quant, self.lam)
+
+
+def param_count(arch: Arch):
+    a, u, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    tot = _lib.coolchic_param_count(ctypes.byref(arch.c()), ctypes.byref(a), ctypes.byref(u), ctypes.byref(s))
+    if tot < 0:
+        raise CoolChicError(CC_EUNSUPPORTED, "coolchic_param_count")
+    return a.value, u.value, s.value
+
+
+def latent_count(p: Problem) -> int:
+    n = _lib.coolchic_latent_count(ctypes.byref(p.c()))
+    if n < 0:
+        raise CoolChicError(CC_EINVAL, "coolchic_latent_count")
+    return n
+
+
+def workspace_bytes(p: Problem, which: int) -> int:
+    return int(_lib.coolchic_workspace_bytes(ctypes.byref(p.c()), int(which)))
+
+
+def workspace(p: Problem, which: int, device="cuda") -> torch.Tensor:
+    n = workspace_bytes(p, which)
+    if n == 0:
+        raise CoolChicError(CC_EINVAL, "coolchic_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _ptr(t, n=None, name="tensor"):
+    """Device pointer of a contiguous float32 GPU tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype not in (torch.float32, torch.int32, torch.uint8) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check(rc, where):
+    if rc != CC_OK:
+        raise CoolChicError(rc, where)
+
+
+def coolchic_forward(p: Problem, img, y, u, arm_w, ups_w, syn_w, loss4, rate_map=None, yq_out=None, xhat_out=None,
+                     ws=None, stream=None):
+    n_lat = latent_count(p)
+    na, nu, ns = param_count(p.arch)
+    hw3 = 3 * p.H * p.W
+    if ws is None:
+        ws = workspace(p, CC_WS_FORWARD, device=y.device)
+    rc = _lib.coolchic_forward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"), _ptr(u, n_lat, "u"),
+                               _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
+                               _ptr(loss4, 4, "loss4"), _ptr(rate_map, n_lat, "rate_map"),
+                               _ptr(yq_out, n_lat, "yq_out"), _ptr(xhat_out, hw3, "xhat_out"),
+                               _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_forward")
+
+
+def coolchic_backward(p: Problem, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, g_y, g_arm, g_ups, g_syn, ws=None,
+                      stream=None):
+    n_lat = latent_count(p)
+    na, nu, ns = param_count(p.arch)
+    hw3 = 3 * p.H * p.W
+    if ws is None:
+        ws = workspace(p, CC_WS_BACKWARD, device=y.device)
+    rc = _lib.coolchic_backward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"), _ptr(u, n_lat, "u"),
+                                _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
+                                float(dloss), _ptr(loss4, 4, "loss4"), _ptr(g_y, n_lat, "g_y"),
+                                _ptr(g_arm, na, "g_arm"), _ptr(g_ups, nu, "g_ups"), _ptr(g_syn, ns, "g_syn"),
+                                _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_backward")
+
+
+def coolchic_decode_synth(p: Problem, yq, ups_w, syn_w, xhat, ws=None, stream=None):
+    n_lat = latent_count(p)
+    _, nu, ns = param_count(p.arch)
+    if ws is None:
+        ws = workspace(p, CC_WS_DECODE, device=yq.device)
+    rc = _lib.coolchic_decode_synth(ctypes.byref(p.c()), _ptr(yq, n_lat, "yq"), _ptr(ups_w, nu, "ups_w"),
+                                    _ptr(syn_w, ns, "syn_w"), _ptr(xhat, 3 * p.H * p.W, "xhat"),
+                                    _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_decode_synth")
+
+
+def coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = theta.numel()
+    if step.dtype != torch.int32 or step.numel() != 2:
+        raise TypeError("step must be a device int32 tensor of 2 elements")
+    rc = _lib.coolchic_adam_step(_ptr(theta, n, "theta"), _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
+                                 n, _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
+    _check(rc, "coolchic_adam_step")
+
+
+def coolchic_set_stage_events(stage: int, ev_begin=None, ev_end=None):
+    """ev_begin / ev_end: raw hipEvent_t handles (ints) or None."""
+    _check(_lib.coolchic_set_stage_events(int(stage), ev_begin, ev_end), "coolchic_set_stage_events")
+
+
+# raw access for tests of the C ABI itself
+lib = _lib

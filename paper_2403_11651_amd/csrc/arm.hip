@@ -1,0 +1,321 @@
+// ARM (auto-regressive probability model) kernels for gfx950.
+//
+// Per latent y_hat[l][i][j] (Section II "Decoding"): gather the C causal
+// neighbours of the same grid (zero outside it), run the residual MLP
+// h <- ReLU(W h + b + h) (Table I "C-C-LinR", one ARM shared by all levels),
+// read (mu, s) from the C-2 output layer, and take the rate -log2 of the
+// Laplace mass over [y_hat - 1/2, y_hat + 1/2] (Eq. (1) rate term).  The
+// backward kernel also runs the adjoint of all of it (Section IV-A).
+//
+// Work layout.  A work-group owns a 4 x 64 tile of one grid and stages the
+// quantised latents of the tile plus its causal halo (3 rows above, 3 columns
+// each side) in LDS.  Each wave processes 32 latents at a time with the
+// v_mfma_f32_32x32x2f32 matrix core: latents sit on the 32 columns of the MFMA,
+// features on its rows, so a layer's output accumulators are directly the
+// next layer's B operand (the K order of every product is permuted to the
+// accumulator row order, and the weights are loaded in that order).  Weight
+// gradients are X^T Y products over latents: the wave stages its 32 latents'
+// feature rows in LDS and reads them back as MFMA operands.
+//
+// The context gradient of a latent goes back to its C causal neighbours.  To
+// keep the result deterministic without atomics, each tile writes the
+// gradient of every latent of its extended frame (tile + causal halo) as a
+// gathered sum in fixed order; a fold kernel later adds, for each latent, the
+// frames of the (at most 6) tiles that cover it, in fixed order.
+#include "common.hpp"
+#include "rate.hpp"
+#include "kernels.hpp"
+
+namespace cc {
+
+// Causal neighbour sets (dy, dx), raster order: the C positions of the 7x7
+// window that precede the latent, nearest first (ties in raster order).
+__constant__ signed char c_ctx8[8][2] = {{-2, -1}, {-2, 0}, {-2, 1}, {-1, -1}, {-1, 0}, {-1, 1}, {0, -2}, {0, -1}};
+__constant__ signed char c_ctx16[16][2] = {{-3, -1}, {-3, 0}, {-3, 1}, {-2, -2}, {-2, -1}, {-2, 0}, {-2, 1}, {-2, 2},
+                                           {-1, -2}, {-1, -1}, {-1, 0}, {-1, 1}, {-1, 2}, {0, -3}, {0, -2}, {0, -1}};
+__constant__ signed char c_ctx24[24][2] = {{-3, -3}, {-3, -2}, {-3, -1}, {-3, 0}, {-3, 1}, {-3, 2}, {-3, 3}, {-2, -3},
+                                           {-2, -2}, {-2, -1}, {-2, 0},  {-2, 1}, {-2, 2}, {-2, 3}, {-1, -3}, {-1, -2},
+                                           {-1, -1}, {-1, 0},  {-1, 1},  {-1, 2}, {-1, 3}, {0, -3}, {0, -2},  {0, -1}};
+
+template <int C>
+__device__ __forceinline__ int ctx_dy(int k) {
+  return C == 8 ? c_ctx8[k][0] : (C == 16 ? c_ctx16[k][0] : c_ctx24[k][0]);
+}
+template <int C>
+__device__ __forceinline__ int ctx_dx(int k) {
+  return C == 8 ? c_ctx8[k][1] : (C == 16 ? c_ctx16[k][1] : c_ctx24[k][1]);
+}
+
+constexpr int STG = 36;  // row stride of the per-wave staging matrices
+
+template <int C, int NH, bool BWD>
+__global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
+  constexpr int NR = C / 2;            // accumulator rows holding features < C
+  constexpr int CS = C + 1;            // row stride of the context-gradient buffer
+  constexpr int NW = NH * (C * C + C) + 2 * C + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 31, g = lane >> 5;
+
+  __shared__ float s_yq[ARM_EXT];
+  // context gradients of the tile; reused at the end for per-wave partials
+  constexpr int GC_SIZE = ARM_TH * ARM_TW * CS > ARM_WAVES * NW ? ARM_TH * ARM_TW * CS : ARM_WAVES * NW;
+  __shared__ float s_gc[BWD ? GC_SIZE : 4 * 64];
+  __shared__ float s_own[BWD ? ARM_TH * ARM_TW : 1];
+  __shared__ float s_stage[BWD ? ARM_WAVES * 2 * 32 * STG : 1];
+
+  // MFMA A operands of every layer, per lane and k-step, in the order the
+  // accumulators hold the features: [0] forward W (A[m = out][k = in]),
+  // [1] transpose (A[m = in][k = out]) for the input gradient
+  __shared__ float s_A[BWD ? 2 : 1][NH][NR][64];
+
+  const float* __restrict__ w = a.w;
+  for (int idx = tid; idx < (BWD ? 2 : 1) * NH * NR * 64; idx += ARM_THREADS) {
+    const int ln = idx & 63, t = (idx >> 6) % NR, j = (idx / (64 * NR)) % NH, tr = idx / (64 * NR * NH);
+    const int nn = ln & 31, f = dfeat(t, ln >> 5);
+    const float* Wj = w + j * (C * C + C);
+    s_A[tr][j][t][ln] = nn < C ? (tr ? Wj[f * C + nn] : Wj[nn * C + f]) : 0.0f;
+  }
+  // per-lane constants: context offsets in the LDS frame, biases and output
+  // weights of the features this lane holds
+  int ctxoff[NR];
+  float bias[NH][NR], wo0[NR], wo1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int f = dfeat(r, g);
+    ctxoff[r] = ctx_dy<C>(f) * ARM_EW + ctx_dx<C>(f);
+#pragma unroll
+    for (int j = 0; j < NH; ++j) bias[j][r] = w[j * (C * C + C) + C * C + f];
+    wo0[r] = w[NH * (C * C + C) + f];
+    wo1[r] = w[NH * (C * C + C) + C + f];
+  }
+  const float bo0 = w[NH * (C * C + C) + 2 * C], bo1 = w[NH * (C * C + C) + 2 * C + 1];
+
+  float* X = s_stage + wave * 2 * 32 * STG;
+  float* Y = X + 32 * STG;
+  if (BWD) {
+    // constant columns of the staging matrices: X pads with zeros, Y holds
+    // the bias column (ones) at C and zeros after it
+    for (int idx = lane; idx < 32 * STG; idx += 64) {
+      const int col = idx % STG;
+      X[idx] = 0.0f;
+      Y[idx] = col == C ? 1.0f : 0.0f;
+    }
+  }
+
+  float rate_acc = 0.0f;
+  f32x16 accW[NH];
+  float accWo0[NR], accWo1[NR], accbo0 = 0.0f, accbo1 = 0.0f;
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accW[j][r] = 0.0f;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { accWo0[r] = 0.0f; accWo1[r] = 0.0f; }
+
+  for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
+    int l = 0;
+    while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
+    const int local = tile - a.tiles.base[l];
+    const int i0 = (local / a.tiles.ntw[l]) * ARM_TH, j0 = (local % a.tiles.ntw[l]) * ARM_TW;
+    const int h = a.geo.lh[l], wl = a.geo.lw[l], base = a.geo.loff[l];
+
+    for (int idx = tid; idx < ARM_EXT; idx += ARM_THREADS) {
+      const int ii = i0 - 3 + idx / ARM_EW, jj = j0 - 3 + idx % ARM_EW;
+      float v = 0.0f;
+      if (ii >= 0 && ii < h && jj >= 0 && jj < wl) v = quantise(a.y, a.u, base + ii * wl + jj, a.quant);
+      s_yq[idx] = v;
+    }
+    __syncthreads();
+
+    for (int c = wave; c < ARM_TH * ARM_TW / 32; c += ARM_WAVES) {
+      const int rr = c / (ARM_TW / 32), cc0 = (c % (ARM_TW / 32)) * 32;
+      const int i = i0 + rr, j = j0 + cc0 + n;
+      const bool valid = i < h && j < wl;
+      const int own = (3 + rr) * ARM_EW + 3 + cc0 + n;
+      float H[NH + 1][NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) H[0][r] = s_yq[own + ctxoff[r]];
+      const float yq = s_yq[own];
+#pragma unroll
+      for (int jl = 0; jl < NH; ++jl) {
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < NR; ++t) acc = mfma32x32x2(s_A[0][jl][t][lane], H[jl][t], acc);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) H[jl + 1][r] = fmaxf(acc[r] + bias[jl][r] + H[jl][r], 0.0f);
+      }
+      float mu = 0.0f, sg = 0.0f;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) { mu += wo0[r] * H[NH][r]; sg += wo1[r] * H[NH][r]; }
+      mu += __shfl_xor(mu, 32, 64) + bo0;
+      sg += __shfl_xor(sg, 32, 64) + bo1;
+      const Rate ro = laplace_rate<BWD>(yq, mu, sg);
+      if (valid && g == 0) {
+        rate_acc += ro.r;
+        const int q = base + i * wl + j;
+        if (a.rate_map) a.rate_map[q] = ro.r;
+        if (a.yq_out) a.yq_out[q] = yq;
+      }
+      if (BWD) {
+        const float gmu = valid ? -a.scale * ro.dd : 0.0f;
+        const float gsg = valid ? a.scale * ro.ds : 0.0f;
+        float gH[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          gH[r] = wo0[r] * gmu + wo1[r] * gsg;
+          accWo0[r] += gmu * H[NH][r];
+          accWo1[r] += gsg * H[NH][r];
+        }
+        if (g == 0) { accbo0 += gmu; accbo1 += gsg; }
+#pragma unroll
+        for (int jl = NH - 1; jl >= 0; --jl) {
+          float gp[NR];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) gp[r] = H[jl + 1][r] > 0.0f ? gH[r] : 0.0f;
+          // weight gradient: accW[jl][o][i] += sum over the 32 latents of gp[o] * [H_jl, 1][i]
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            X[n * STG + dfeat(r, g)] = gp[r];
+            Y[n * STG + dfeat(r, g)] = H[jl][r];
+          }
+          wave_lds_sync();
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            const int row = (2 * t + g) * STG + n;
+            accW[jl] = mfma32x32x2(X[row], Y[row], accW[jl]);
+          }
+          wave_lds_sync();
+          // input gradient: W^T gp + gp (residual)
+          f32x16 acc;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+          for (int t = 0; t < NR; ++t) acc = mfma32x32x2(s_A[BWD ? 1 : 0][jl][t][lane], gp[t], acc);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) gH[r] = acc[r] + gp[r];
+        }
+        const int li = rr * ARM_TW + cc0 + n;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s_gc[li * CS + dfeat(r, g)] = gH[r];
+        if (g == 0) s_own[li] = valid ? a.scale * ro.dd : 0.0f;
+      }
+    }
+    __syncthreads();
+    if (BWD) {
+      float* ge = a.gext + (size_t)tile * ARM_EXT;
+      for (int idx = tid; idx < ARM_EXT; idx += ARM_THREADS) {
+        const int fa = idx / ARM_EW, fb = idx % ARM_EW;
+        float G = 0.0f;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          const int pr = fa - 3 - ctx_dy<C>(k), pc = fb - 3 - ctx_dx<C>(k);
+          if (pr >= 0 && pr < ARM_TH && pc >= 0 && pc < ARM_TW) G += s_gc[(pr * ARM_TW + pc) * CS + k];
+        }
+        if (fa >= 3 && fb >= 3 && fb < ARM_TW + 3) G += s_own[(fa - 3) * ARM_TW + fb - 3];
+        ge[idx] = G;
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- block partials: rate, and (backward) the ARM weight gradients
+  rate_acc = wave_sum(rate_acc);
+  float* red = s_gc;  // reused: [ARM_WAVES][NW] per-wave partial gradients
+  if (BWD) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      float v0 = accWo0[r], v1 = accWo1[r];
+#pragma unroll
+      for (int m = 16; m >= 1; m >>= 1) { v0 += __shfl_xor(v0, m, 64); v1 += __shfl_xor(v1, m, 64); }
+      accWo0[r] = v0; accWo1[r] = v1;
+    }
+    accbo0 = wave_sum(accbo0);
+    accbo1 = wave_sum(accbo1);
+    float* rw = red + wave * NW;
+#pragma unroll
+    for (int jl = 0; jl < NH; ++jl) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int o = dfeat(r, g);
+        if (o < C) {
+          if (n < C) rw[jl * (C * C + C) + o * C + n] = accW[jl][r];
+          else if (n == C) rw[jl * (C * C + C) + C * C + o] = accW[jl][r];
+        }
+      }
+    }
+    if (n == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        rw[NH * (C * C + C) + dfeat(r, g)] = accWo0[r];
+        rw[NH * (C * C + C) + C + dfeat(r, g)] = accWo1[r];
+      }
+    }
+    if (lane == 0) { rw[NH * (C * C + C) + 2 * C] = accbo0; rw[NH * (C * C + C) + 2 * C + 1] = accbo1; }
+  }
+  __syncthreads();
+  __shared__ float s_rate[ARM_WAVES];
+  if (lane == 0) s_rate[wave] = rate_acc;
+  __syncthreads();
+  if (tid == 0) {
+    float s = 0.0f;
+    for (int k = 0; k < ARM_WAVES; ++k) s += s_rate[k];
+    a.rpart[blockIdx.x] = s;
+  }
+  if (BWD) {
+    for (int p = tid; p < NW; p += ARM_THREADS) {
+      float s = 0.0f;
+      for (int k = 0; k < ARM_WAVES; ++k) s += red[k * NW + p];
+      a.wpart[(size_t)blockIdx.x * NW + p] = s;
+    }
+  }
+}
+
+// g_y[q] += sum of the extended-frame gradients of every ARM tile whose frame
+// contains latent q (own tile, left / right neighbours, and the three tiles of
+// the next tile row), in fixed order; also flags non-finite results.
+__global__ __launch_bounds__(256) void arm_fold_kernel(FoldArgs a) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  if (q < a.geo.n_lat) {
+    int l = 0;
+    while (l + 1 < a.geo.L && q >= a.geo.loff[l + 1]) ++l;
+    const int wl = a.geo.lw[l], local = q - a.geo.loff[l];
+    const int i = local / wl, j = local % wl;
+    const int ti = i / ARM_TH, tj = j / ARM_TW;
+    float G = 0.0f;
+    for (int da = 0; da <= 1; ++da) {
+      const int ta = ti + da;
+      if (ta >= a.tiles.nth[l]) continue;
+      for (int db = -1; db <= 1; ++db) {
+        const int tb = tj + db;
+        if (tb < 0 || tb >= a.tiles.ntw[l]) continue;
+        const int fa = i - (ta * ARM_TH - 3), fb = j - (tb * ARM_TW - 3);
+        if (fa < 0 || fa >= ARM_EH || fb < 0 || fb >= ARM_EW) continue;
+        const int tile = a.tiles.base[l] + ta * a.tiles.ntw[l] + tb;
+        G += a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb];
+      }
+    }
+    const float v = a.g_y[q] + G;
+    a.g_y[q] = v;
+    bad = !finitef(v);
+  }
+  const bool any = __syncthreads_or(bad);
+  if (threadIdx.x == 0) a.flags[blockIdx.x] = any ? 1.0f : 0.0f;
+}
+
+// ---- instantiation table
+template <bool BWD>
+static ArmKernelFn pick(int C, int NH) {
+#define CC_ARM_CASE(CC, HH) \
+  if (C == CC && NH == HH) return arm_kernel<CC, HH, BWD>;
+  CC_ARM_CASE(8, 1) CC_ARM_CASE(8, 2) CC_ARM_CASE(8, 3)
+  CC_ARM_CASE(16, 1) CC_ARM_CASE(16, 2) CC_ARM_CASE(16, 3)
+  CC_ARM_CASE(24, 1) CC_ARM_CASE(24, 2) CC_ARM_CASE(24, 3)
+#undef CC_ARM_CASE
+  return nullptr;
+}
+
+ArmKernelFn arm_kernel_for(int C, int NH, bool bwd) { return bwd ? pick<true>(C, NH) : pick<false>(C, NH); }
+
+}  // namespace cc

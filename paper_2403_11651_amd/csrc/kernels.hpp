@@ -1,0 +1,143 @@
+// Kernel argument blocks and entry points shared by the kernel sources and
+// the host-side C ABI.
+#pragma once
+
+#include "common.hpp"
+
+namespace cc {
+
+// ---------------------------------------------------------------- ARM
+constexpr int ARM_TH = 4, ARM_TW = 64;               // latents per tile: rows x columns
+constexpr int ARM_EH = ARM_TH + 3, ARM_EW = ARM_TW + 6;  // tile + causal halo frame
+constexpr int ARM_EXT = ARM_EH * ARM_EW;
+constexpr int ARM_THREADS = 256, ARM_WAVES = 4;
+
+struct ArmTiles {
+  int n_tiles;
+  int base[MAXL + 1];  // first tile of level l
+  int nth[MAXL + 1];   // tile rows of level l
+  int ntw[MAXL + 1];   // tile columns of level l
+};
+
+struct ArmArgs {
+  Geo geo;
+  ArmTiles tiles;
+  const float* y;
+  const float* u;
+  int quant;
+  const float* w;      // packed ARM parameters
+  float scale;         // dloss * lambda / (H W): gradient of the loss per bit
+  float* rate_map;     // optional [N_lat]
+  float* yq_out;       // optional [N_lat]
+  float* gext;         // backward: [n_tiles][ARM_EXT] gathered context gradients
+  float* wpart;        // backward: [gridDim][n_arm] weight-gradient partials
+  float* rpart;        // [gridDim] rate partial sums (bits)
+};
+typedef void (*ArmKernelFn)(ArmArgs);
+ArmKernelFn arm_kernel_for(int C, int NH, bool bwd);
+
+struct FoldArgs {
+  Geo geo;
+  ArmTiles tiles;
+  const float* gext;
+  float* g_y;
+  float* flags;        // [gridDim] 1 if any result of the block is not finite
+};
+__global__ void arm_fold_kernel(FoldArgs a);
+
+// ---------------------------------------------------------------- upsampling
+struct UpsFwdArgs {
+  Geo geo;
+  int s;               // step: produces U_s(stack_{s+1}) at level s
+  const float* y;
+  const float* u;
+  int quant;
+  const float* taps;   // [2][K] taps of step s
+  const float* up_in;  // U_{s+1} output (channels 1.. of stack_{s+1}); null when s = L-2
+  float* up_out;       // [(L-1-s)][h_s][w_s]
+};
+__global__ void ups_fwd_kernel(UpsFwdArgs a);
+
+struct UpsBwdArgs {
+  Geo geo;
+  int s;               // adjoint of step s: g_stack_s[1..] (level s) -> g_stack_{s+1} (level s+1)
+  const float* y;
+  const float* u;
+  int quant;
+  const float* taps;   // [2][K]
+  const float* up_in;  // forward U_{s+1} output (channels 1.. of stack_{s+1}); null when s = L-2
+  const float* g_in;   // [(L-1-s)][h_s][w_s]: gradient of U_s's output
+  float* g_y;          // level s+1 of the packed latent gradient (channel 0 of g_stack_{s+1})
+  float* g_out;        // [(L-2-s)][h_{s+1}][w_{s+1}]: channels 1.. of g_stack_{s+1}; null when s = L-2
+  float* part;         // [gridDim][2K] tap-gradient partials
+};
+__global__ void ups_bwd_kernel(UpsBwdArgs a);
+
+// ---------------------------------------------------------------- synthesis
+constexpr int SYN_T = 16;                  // output tile side (pixels)
+constexpr int SYN_THREADS = 256;
+constexpr int SYN_MAXRES = 2;              // residual 3x3 convs supported
+constexpr int SYN_FMAX = SYN_T + 4 * SYN_MAXRES;  // largest LDS frame side
+
+struct SynArgs {
+  Geo geo;
+  const float* y;
+  const float* u;
+  int quant;
+  const float* ups0;   // [2][K] taps of step 0
+  const float* up1;    // U_1 output (channels 1.. of stack_1); null when L = 2
+  const float* w;      // packed synthesis parameters
+  int n_res;
+  int res_off;         // offset of the first residual conv inside w
+  const float* img;    // [3][H][W] (may be null for decoding)
+  float* t0;           // [3][H][W] output of the two 1x1 layers
+  float* xhat;         // optional [3][H][W]
+  float dscale;        // backward: dloss * 2 / (3 H W)
+  float* g_y;          // backward: level 0 of the packed latent gradient
+  float* gz;           // backward: [(L-1)][H][W] gradient of U_0's output
+  float* wpart;        // backward: [gridDim][n_syn]
+  float* spart;        // [gridDim] squared-error partial sums
+  int n_tiles_x, n_tiles;
+};
+typedef void (*SynKernelFn)(SynArgs);
+SynKernelFn syn_t0_kernel_for(int Hs);
+SynKernelFn syn_res_fwd_kernel_for(int Hs);
+SynKernelFn syn_bwd_kernel_for(int Hs);
+
+// ---------------------------------------------------------------- reductions, optimiser
+constexpr int RED_MAXSEG = 12;
+struct RedSeg {
+  const float* src;    // [rows][ld]
+  int rows, cols, ld;
+  float* dst;          // [cols]
+};
+struct ReduceArgs {
+  RedSeg seg[RED_MAXSEG];
+  int nseg;
+  int col_start[RED_MAXSEG + 1];
+  float* flags;        // [gridDim]
+};
+__global__ void reduce_cols_kernel(ReduceArgs a);
+
+struct FinalArgs {
+  const float* rpart; int nr;    // rate partials (bits)
+  const float* spart; int ns;    // squared-error partials
+  const float* flags; int nflags;
+  float lambda, inv_hw, inv_3hw;
+  int have_rate, have_sse;
+  float* loss4;
+};
+__global__ void finalize_kernel(FinalArgs a);
+
+struct AdamArgs {
+  float* theta;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  int32_t* step;
+  float lr, beta1, beta2, eps;
+};
+__global__ void adam_kernel(AdamArgs a);
+
+}  // namespace cc

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/coolchic.h declares, and rejects invalid arguments with
+the documented codes before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2403_11651_amd import binding
+    return binding
+
+
+def test_exports_every_declared_symbol(B):
+    hdr = open(os.path.join(ROOT, "include", "coolchic.h")).read()
+    declared = set(re.findall(r"\b(coolchic_\w+)\s*\(", hdr))
+    assert declared == set(B.EXPORTS)
+    for name in declared:
+        assert hasattr(B.lib, name), name
+
+
+def test_param_counts_match_oracle(B):
+    for arch in [(7, 24, 2, 8, 40, 2), (7, 8, 2, 8, 16, 1), (5, 16, 3, 8, 48, 2), (2, 8, 1, 8, 8, 1)]:
+        assert B.param_count(B.Arch(*arch)) == O.param_sizes(O.Arch(*arch))
+
+
+def test_latent_count_and_workspace(B):
+    p = B.Problem(512, 768)
+    assert B.latent_count(p) == 524256
+    f, b, d = (B.workspace_bytes(p, w) for w in (0, 1, 2))
+    assert 0 < d <= f < b
+    assert B.workspace_bytes(p, 7) == 0
+
+
+@pytest.mark.parametrize("H,W,arch,quant,code", [
+    (100, 768, (7, 24, 2, 8, 40, 2), 0, -1),   # H not a multiple of 2^(L-1)
+    (512, 760, (7, 24, 2, 8, 40, 2), 0, -1),
+    (0, 768, (7, 24, 2, 8, 40, 2), 0, -1),
+    (512, 768, (7, 24, 2, 8, 40, 2), 5, -1),   # unknown quantiser
+    (512, 768, (7, 12, 2, 8, 40, 2), 0, -2),   # context width not compiled
+    (512, 768, (7, 24, 2, 4, 40, 2), 0, -2),   # 4-tap upsampler not compiled
+    (512, 768, (7, 24, 2, 8, 44, 2), 0, -2),   # hidden width not a multiple of 8
+    (512, 768, (7, 24, 2, 8, 40, 3), 0, -2),   # three residual convs
+    (1024, 1024, (9, 24, 2, 8, 40, 2), 0, -2),  # more than 7 levels
+])
+def test_invalid_problems_rejected(B, H, W, arch, quant, code):
+    p = B.Problem(H, W, B.Arch(*arch), quant)
+    pc = p.c()
+    assert B.lib.coolchic_workspace_bytes(ctypes.byref(pc), 1) == 0
+    dummy = ctypes.c_void_p(0x1000)
+    rc = B.lib.coolchic_forward(ctypes.byref(pc), dummy, dummy, dummy, dummy, dummy, dummy, dummy, None, None, None,
+                                dummy, 1 << 30, None)
+    assert rc == code
+
+
+def test_null_pointers_and_small_workspace(B):
+    p = B.Problem(64, 64, B.LOW)
+    pc = p.c()
+    d = ctypes.c_void_p(0x1000)
+    need = B.workspace_bytes(p, 0)
+    # null image
+    assert B.lib.coolchic_forward(ctypes.byref(pc), None, d, None, d, d, d, d, None, None, None, d, need, None) == -1
+    # workspace too small
+    assert B.lib.coolchic_forward(ctypes.byref(pc), d, d, None, d, d, d, d, None, None, None, d, need - 4, None) == -3
+    # noise quantiser without u
+    pn = B.Problem(64, 64, B.LOW, B.CC_QUANT_NOISE).c()
+    assert B.lib.coolchic_forward(ctypes.byref(pn), d, d, None, d, d, d, d, None, None, None, d, need, None) == -1
+    needb = B.workspace_bytes(p, 1)
+    assert B.lib.coolchic_backward(ctypes.byref(pc), d, d, None, d, d, d, 1.0, d, d, d, d, d, d, needb - 1, None) == -3
+    assert B.lib.coolchic_backward(ctypes.byref(pc), d, d, None, d, d, d, 1.0, d, None, d, d, d, d, needb, None) == -1
+    assert B.lib.coolchic_decode_synth(ctypes.byref(pc), d, d, d, None, d, B.workspace_bytes(p, 2), None) == -1
+    assert B.lib.coolchic_decode_synth(None, d, d, d, d, d, 1 << 20, None) == -1
+    assert B.lib.coolchic_adam_step(d, d, d, d, 0, d, 0.01, 0.9, 0.999, 1e-8, None) == -1
+    assert B.lib.coolchic_adam_step(d, d, d, d, 10, d, 0.01, 1.0, 0.999, 1e-8, None) == -1
+    assert B.strerror(-3).startswith("workspace")

@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: quantised latents bit-exact; loss within 1e-5 relative; per-latent rate
+within 1e-4 bits (1e-6 relative above 100 bits, the FP32 resolution there);
+every gradient tensor within 1e-3 relative in the 2-norm and within
+1e-3 * max|g| element by element."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from tests import cases as CS
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_11651_amd import binding
+    return binding
+
+
+def _dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _problem(B, c):
+    L, C, NH, K, Hs, R = c.arch
+    return B.Problem(c.H, c.W, B.Arch(L, C, NH, K, Hs, R), B.CC_QUANT_NOISE if c.u is not None else B.CC_QUANT_ROUND,
+                     c.lam)
+
+
+def gpu_forward(B, c):
+    p = _problem(B, c)
+    n = CS.n_latents(c.H, c.W, c.arch[0])
+    loss4 = torch.zeros(4, device="cuda")
+    rate = torch.zeros(n, device="cuda")
+    yq = torch.zeros(n, device="cuda")
+    xhat = torch.zeros(3 * c.H * c.W, device="cuda")
+    B.coolchic_forward(p, _dev(c.img), _dev(c.y), _dev(c.u), _dev(c.arm), _dev(c.ups), _dev(c.syn), loss4, rate, yq,
+                       xhat)
+    torch.cuda.synchronize()
+    return dict(loss4=loss4.cpu().numpy(), rate=rate.cpu().numpy(), yq=yq.cpu().numpy(),
+                xhat=xhat.cpu().numpy().reshape(3, c.H, c.W))
+
+
+def gpu_backward(B, c, dloss=1.0):
+    p = _problem(B, c)
+    n = CS.n_latents(c.H, c.W, c.arch[0])
+    na, nu, ns = CS.sizes(c.arch)
+    loss4 = torch.zeros(4, device="cuda")
+    g = [torch.full((k,), float("nan"), device="cuda") for k in (n, na, nu, ns)]
+    B.coolchic_backward(p, _dev(c.img), _dev(c.y), _dev(c.u), _dev(c.arm), _dev(c.ups), _dev(c.syn), dloss, loss4, *g)
+    torch.cuda.synchronize()
+    return dict(loss4=loss4.cpu().numpy(), g_y=g[0].cpu().numpy(), g_arm=g[1].cpu().numpy(),
+                g_ups=g[2].cpu().numpy(), g_syn=g[3].cpu().numpy())
+
+
+def oracle_backward(c):
+    return O.backward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=c.u)
+
+
+def assert_grad_close(name, g, go, tol=1e-3):
+    g = np.asarray(g, np.float64)
+    nrm = np.linalg.norm(go)
+    assert np.all(np.isfinite(g)), name
+    assert np.linalg.norm(g - go) <= tol * nrm + 1e-30, (name, np.linalg.norm(g - go) / max(nrm, 1e-30))
+    assert np.max(np.abs(g - go)) <= tol * np.max(np.abs(go)) + 1e-30, (name, np.max(np.abs(g - go)), np.max(np.abs(go)))
+
+
+def assert_rate_close(r, ro):
+    tol = np.maximum(1e-4, 1e-6 * np.abs(ro))
+    bad = np.abs(r - ro) > tol
+    assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(r - ro))))
+
+
+def check_forward(B, c):
+    out = gpu_forward(B, c)
+    ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=c.u)
+    if c.u is None:
+        assert np.array_equal(out["yq"], np.rint(c.y.astype(np.float64)).astype(np.float32))
+    else:
+        assert np.allclose(out["yq"], ref["yq"], rtol=0, atol=4e-7 * np.max(np.abs(ref["yq"])))
+    assert_rate_close(out["rate"], ref["rate"])
+    L4 = out["loss4"]
+    assert L4[3] == 0.0
+    assert abs(L4[0] - ref["loss"]) <= 1e-5 * abs(ref["loss"]), (L4, ref["loss"])
+    assert abs(L4[1] - ref["D"]) <= 1e-5 * abs(ref["D"])
+    assert abs(L4[2] - ref["R"]) <= 1e-5 * abs(ref["R"])
+    assert np.allclose(out["xhat"], ref["xhat"], rtol=0, atol=1e-5 * max(1.0, np.max(np.abs(ref["xhat"]))))
+
+
+def check_backward(B, c):
+    out = gpu_backward(B, c)
+    ref = oracle_backward(c)
+    L4 = out["loss4"]
+    assert L4[3] == 0.0
+    assert abs(L4[0] - ref["loss"]) <= 1e-5 * abs(ref["loss"]), (L4, ref["loss"])
+    for k in ("g_y", "g_arm", "g_ups", "g_syn"):
+        assert_grad_close(k, out[k], ref[k])
+    # the latent gradient level by level as well
+    o = 0
+    for l in range(c.arch[0]):
+        n = (c.H >> l) * (c.W >> l)
+        assert_grad_close(f"g_y[level {l}]", out["g_y"][o:o + n], ref["g_y"][o:o + n])
+        o += n
+
+
+def test_tiny_forward(B):
+    check_forward(B, CS.tiny())
+
+
+def test_tiny_backward(B):
+    check_backward(B, CS.tiny())
+
+
+def test_tiny_noise_mode(B):
+    c = CS.make("tiny64_noise", 64, 64, CS.TINY, seeds=(0, 1, 2, 4), noise=True)
+    check_forward(B, c)
+    check_backward(B, c)
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_small_variants(B, idx):
+    c = CS.small_variants()[idx]
+    check_forward(B, c)
+    check_backward(B, c)
+
+
+def test_low_768x512(B):
+    c = CS.low()
+    check_forward(B, c)
+    check_backward(B, c)
+
+
+def test_full_768x512(B):
+    c = CS.full()
+    check_forward(B, c)
+    check_backward(B, c)
+
+
+def test_decode_synth_matches_oracle(B):
+    c = CS.low()
+    p = _problem(B, c)
+    yq = np.rint(c.y.astype(np.float64)).astype(np.float32)
+    xhat = torch.zeros(3 * c.H * c.W, device="cuda")
+    B.coolchic_decode_synth(p, _dev(yq), _dev(c.ups), _dev(c.syn), xhat)
+    torch.cuda.synchronize()
+    ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam)
+    x = xhat.cpu().numpy().reshape(3, c.H, c.W)
+    assert np.allclose(x, ref["xhat"], rtol=0, atol=1e-5 * max(1.0, np.max(np.abs(ref["xhat"]))))
+
+
+def test_backward_is_deterministic(B):
+    c = CS.full()
+    a = gpu_backward(B, c)
+    b = gpu_backward(B, c)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_all_zero_latents_closed_form(B):
+    """All-zero y_hat: R = N_lat * r(0 | mu0, b0) with (mu0, s0) = ARM(0)."""
+    c = CS.make("zeros", 64, 128, CS.FULL, seeds=(5, 6, 7, 8))
+    c.y = np.zeros_like(c.y)
+    out = gpu_forward(B, c)
+    ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam)
+    r0 = ref["rate"][0]
+    assert np.allclose(ref["rate"], r0)
+    assert abs(out["loss4"][2] - c.y.size * r0) <= 1e-5 * c.y.size * r0
+    assert_rate_close(out["rate"], ref["rate"])
+
+
+def test_arm_causality_on_gpu(B):
+    """Raising latents at and after a position (in raster order of its grid),
+    or in other grids, leaves the rate of every earlier latent unchanged bit
+    for bit (the rate is a function of (y_hat, mu, s) only)."""
+    c = CS.make("causal", 64, 128, CS.FULL, seeds=(5, 6, 7, 8), rounded=True)
+    base = gpu_forward(B, c)["rate"]
+    L0 = 64 * 128
+    k = 40 * 128 + 77
+    c2 = CS.make("causal", 64, 128, CS.FULL, seeds=(5, 6, 7, 8), rounded=True)
+    c2.y = c.y.copy()
+    c2.y[k:L0] += 3.0                  # this latent and all raster-later latents of level 0
+    c2.y[L0:] -= 2.0                   # and every other grid
+    pert = gpu_forward(B, c2)["rate"]
+    assert np.array_equal(pert[:k], base[:k])
+    assert not np.array_equal(pert[k:L0], base[k:L0])
+
+
+def test_nonfinite_flag(B):
+    c = CS.tiny()
+    c.y = c.y.copy()
+    c.y[5] = np.nan
+    assert gpu_forward(B, c)["loss4"][3] == 1.0
+    assert gpu_backward(B, c)["loss4"][3] == 1.0
+    c2 = CS.tiny()
+    assert gpu_backward(B, c2)["loss4"][3] == 0.0

@@ -106,6 +106,37 @@ def test_rate_tail_closed_form_and_symmetry():
     assert np.allclose(r, r2, rtol=1e-11, atol=1e-12)
 
 
+def test_rate_far_tail_is_finite_and_matches_plain_difference():
+    """Where float64 can still hold the mass (down to ~1e-300) the log-space
+    tail branch and the plain CDF difference agree; beyond it the rate keeps
+    the closed-form slope 1/(b ln 2) per unit of |y - mu|."""
+    b = np.full(5, 0.01)
+    mu = np.zeros(5)
+    # masses around 1e-250 .. 1e-290: both branches representable
+    y = np.array([5.76, 6.0, 6.2, 6.4, 6.6])
+    plain = np.log(O.laplace_mass(y, mu, b))
+    assert np.all(np.isfinite(plain))
+    import oracle.coolchic as OC
+    old = OC.TAIL_LOG_BELOW
+    try:
+        OC.TAIL_LOG_BELOW = 1.0  # force the factored branch everywhere
+        logp = OC.log_laplace_mass(y, mu, b)
+    finally:
+        OC.TAIL_LOG_BELOW = old
+    assert np.allclose(logp, plain, rtol=1e-12, atol=0)
+    # far beyond underflow: exact slope between integers, both sides
+    ys = np.array([20.0, 21.0, -20.0, -21.0])
+    r = O.rate_bits(ys, np.zeros(4), np.full(4, math.log(0.01)))
+    assert np.all(np.isfinite(r))
+    assert abs((r[1] - r[0]) - 1.0 / (0.01 * math.log(2))) < 1e-9 * r[1]
+    assert abs((r[3] - r[2]) - 1.0 / (0.01 * math.log(2))) < 1e-9 * r[3]
+    gy, gmu, gs = O.rate_grads(ys, np.zeros(4), np.full(4, math.log(0.02)))
+    assert np.allclose(gy, np.sign(ys) / (0.02 * math.log(2)), rtol=1e-12)
+    # dr/ds in the tail: (1/b)(1/(e^{1/b} - 1) - (|d| - 1/2)) / ln 2
+    exp_gs = (1 / 0.02) * (1 / np.expm1(1 / 0.02) - (np.abs(ys) - 0.5)) / math.log(2)
+    assert np.allclose(gs, exp_gs, rtol=1e-12)
+
+
 def test_rate_scale_clamp():
     y, mu = np.array([2.0]), np.array([0.0])
     assert O.rate_bits(y, mu, np.array([50.0]))[0] == O.rate_bits(y, mu, np.array([math.log(100.0)]))[0]
