@@ -70,10 +70,17 @@ def assert_grad_close(name, g, go, tol=1e-3):
     assert np.max(np.abs(g - go)) <= tol * np.max(np.abs(go)) + 1e-30, (name, np.max(np.abs(g - go)), np.max(np.abs(go)))
 
 
-def assert_rate_close(r, ro):
-    tol = np.maximum(1e-4, 1e-6 * np.abs(ro))
+def assert_rate_close(r, ref):
+    """1e-4 bits (1e-6 relative above 100 bits), plus the first-order effect of
+    a 1e-5 perturbation of the FP32 mean and log-scale: with the scale
+    clamped at 0.01 the rate turns an error in mu into 144x as many bits."""
+    ro = ref["rate"]
+    _, gmu, gs = O.rate_grads(ref["yq"], ref["mu"], ref["s"])
+    tol = np.maximum(1e-4, 1e-6 * np.abs(ro)) + 1e-5 * (np.abs(gmu) + np.abs(gs))
     bad = np.abs(r - ro) > tol
-    assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(r - ro))))
+    assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(r - ro))), float(np.max(np.abs(r - ro) / tol)))
+    plain = np.abs(gmu) < 15.0  # scale >= 0.1: the plain 1e-4-bit bar
+    assert np.all(np.abs(r - ro)[plain] <= np.maximum(1e-4, 1e-6 * np.abs(ro[plain])))
 
 
 def check_forward(B, c):
@@ -83,7 +90,7 @@ def check_forward(B, c):
         assert np.array_equal(out["yq"], np.rint(c.y.astype(np.float64)).astype(np.float32))
     else:
         assert np.allclose(out["yq"], ref["yq"], rtol=0, atol=4e-7 * np.max(np.abs(ref["yq"])))
-    assert_rate_close(out["rate"], ref["rate"])
+    assert_rate_close(out["rate"], ref)
     L4 = out["loss4"]
     assert L4[3] == 0.0
     assert abs(L4[0] - ref["loss"]) <= 1e-5 * abs(ref["loss"]), (L4, ref["loss"])
@@ -170,7 +177,7 @@ def test_all_zero_latents_closed_form(B):
     r0 = ref["rate"][0]
     assert np.allclose(ref["rate"], r0)
     assert abs(out["loss4"][2] - c.y.size * r0) <= 1e-5 * c.y.size * r0
-    assert_rate_close(out["rate"], ref["rate"])
+    assert_rate_close(out["rate"], ref)
 
 
 def test_arm_causality_on_gpu(B):
