@@ -9,7 +9,6 @@ all through the HIP library's C ABI.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import ctypes
 import json
 import os
 import sys
@@ -47,44 +46,6 @@ def algorithmic_counts(arch, H, W):
     fwd_mac = arm_mac_per_latent * n_lat + ups_mac + syn_mac_per_px * n_px
     return dict(n_lat=n_lat, n_px=n_px, arm_flop=6.0 * arm_mac_per_latent * n_lat,
                 syn_flop=6.0 * syn_mac_per_px * n_px, iter_flop=6.0 * fwd_mac, kappa_dec=fwd_mac / n_px)
-
-
-class HipEvents:
-    """hipEventCreate / hipEventElapsedTime through the HIP runtime (timing only)."""
-
-    def __init__(self):
-        path = None
-        for cand in ("/opt/rocm/lib/libamdhip64.so", "libamdhip64.so"):
-            try:
-                self.hip = ctypes.CDLL(cand)
-                path = cand
-                break
-            except OSError:
-                continue
-        if path is None:
-            raise RuntimeError("libamdhip64.so not found")
-        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
-        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
-        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
-
-    def create(self, n):
-        out = []
-        for _ in range(n):
-            e = ctypes.c_void_p()
-            if self.hip.hipEventCreate(ctypes.byref(e)) != 0:
-                raise RuntimeError("hipEventCreate failed")
-            out.append(e.value)
-        return out
-
-    def elapsed_ms(self, a, b):
-        t = ctypes.c_float()
-        if self.hip.hipEventElapsedTime(ctypes.byref(t), a, b) != 0:
-            raise RuntimeError("hipEventElapsedTime failed")
-        return t.value
-
-    def destroy(self, evs):
-        for e in evs:
-            self.hip.hipEventDestroy(e)
 
 
 def make_inputs(arch, H=512, W=768):
@@ -185,32 +146,33 @@ def main():
     torch.cuda.synchronize()
     loss_start = loss4.clone()
 
-    # per-launch kernel timing with HIP events on the library's stream
-    ev = HipEvents()
+    # Per-launch kernel timing with HIP events on the library's stream.  The
+    # events are torch's (the same HIP runtime the library is bound to); the
+    # library records them around the named kernel's launch.
     K = args.steps
-    arm_ev = ev.create(2 * K)
-    syn_ev = ev.create(2 * K)
-    t_ev = ev.create(2)
-    hip_stream = ctypes.c_void_p(stream.cuda_stream)
-    ev.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    def events(n):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        for e in evs:
+            e.record(stream)  # creates the underlying hipEvent_t
+        return evs
+    arm_ev, syn_ev, t_ev = events(2 * K), events(2 * K), events(2)
     torch.cuda.synchronize()
-    ev.hip.hipEventRecord(t_ev[0], hip_stream)
+    t_ev[0].record(stream)
     t_wall = time.perf_counter()
     for k in range(K):
         # alternate the timed stage so both kernels are covered over the run
         if k % 2 == 0:
-            B.coolchic_set_stage_events(B.CC_STAGE_ARM, arm_ev[2 * k], arm_ev[2 * k + 1])
+            B.coolchic_set_stage_events(B.CC_STAGE_ARM, arm_ev[2 * k].cuda_event, arm_ev[2 * k + 1].cuda_event)
         else:
-            B.coolchic_set_stage_events(B.CC_STAGE_SYNTHESIS, syn_ev[2 * k], syn_ev[2 * k + 1])
+            B.coolchic_set_stage_events(B.CC_STAGE_SYNTHESIS, syn_ev[2 * k].cuda_event, syn_ev[2 * k + 1].cuda_event)
         one_step()
     B.coolchic_set_stage_events(B.CC_STAGE_NONE)
-    ev.hip.hipEventRecord(t_ev[1], hip_stream)
+    t_ev[1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    total_ms = ev.elapsed_ms(t_ev[0], t_ev[1])
-    arm_ms = [ev.elapsed_ms(arm_ev[2 * k], arm_ev[2 * k + 1]) for k in range(0, K, 2)]
-    syn_ms = [ev.elapsed_ms(syn_ev[2 * k], syn_ev[2 * k + 1]) for k in range(1, K, 2)]
-    ev.destroy(arm_ev + syn_ev + t_ev)
+    total_ms = t_ev[0].elapsed_time(t_ev[1])
+    arm_ms = [arm_ev[2 * k].elapsed_time(arm_ev[2 * k + 1]) for k in range(0, K, 2)]
+    syn_ms = [syn_ev[2 * k].elapsed_time(syn_ev[2 * k + 1]) for k in range(1, K, 2)]
     l4 = loss4.cpu().numpy()
     if l4[3] != 0.0 or not np.isfinite(l4[0]):
         print(f"non-finite loss during the timed run: {l4}", file=sys.stderr)

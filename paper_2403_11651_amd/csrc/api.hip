@@ -97,9 +97,9 @@ int make_plan(const cc_problem* p, int which, Plan* P) {
   P->syn_tiles_x = cdiv(p->W, SYN_T);
   P->syn_tiles = P->syn_tiles_x * cdiv(p->H, SYN_T);
   P->syn_grid = std::min(P->syn_tiles, MAX_GRID);
-  for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = std::min(cdiv(g.lh[s + 1] * g.lw[s + 1], 256), MAX_GRID);
+  for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);
   P->fold_grid = cdiv(g.n_lat, 256);
-  P->red_grid = cdiv((int)(P->n_arm + P->n_ups + P->n_syn), 64);
+  P->red_grid = cdiv((int)(P->n_arm + P->n_ups + P->n_syn), RED_COLS);
 
   size_t cur = 0;
   for (int s = 1; s + 1 < L; ++s) P->up[s] = take(cur, (size_t)(L - 1 - s) * g.lh[s] * g.lw[s]);
@@ -209,7 +209,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   ArmKernelFn armk = arm_kernel_for(P.C, P.NH, false);
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs), resk = syn_res_fwd_kernel_for(P.Hs);
+  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), resk = syn_res_fwd_kernel_for(P.Hs, P.nres);
   if (!armk || !t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
@@ -246,7 +246,7 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   ArmKernelFn armk = arm_kernel_for(P.C, P.NH, true);
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs), bwk = syn_bwd_kernel_for(P.Hs);
+  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), bwk = syn_bwd_kernel_for(P.Hs, P.nres);
   if (!armk || !t0k || !bwk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
@@ -319,7 +319,7 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   if (rc) return rc;
   if (!yq || !ups_w || !syn_w || !xhat || !ws) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs), resk = syn_res_fwd_kernel_for(P.Hs);
+  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), resk = syn_res_fwd_kernel_for(P.Hs, P.nres);
   if (!t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
@@ -343,6 +343,10 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
   (void)hipGetLastError();
   int rc = launch((const void*)adam_kernel, grid, 256, &a, (hipStream_t)stream);
   if (rc) return rc;
+  void* sp = step;
+  void* argv[] = {&sp};
+  if (hipLaunchKernel((const void*)adam_advance_kernel, dim3(1), dim3(64), argv, 0, (hipStream_t)stream) != hipSuccess)
+    return CC_EHIP;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 

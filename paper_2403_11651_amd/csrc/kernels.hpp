@@ -100,12 +100,13 @@ struct SynArgs {
   int n_tiles_x, n_tiles;
 };
 typedef void (*SynKernelFn)(SynArgs);
-SynKernelFn syn_t0_kernel_for(int Hs);
-SynKernelFn syn_res_fwd_kernel_for(int Hs);
-SynKernelFn syn_bwd_kernel_for(int Hs);
+SynKernelFn syn_t0_kernel_for(int Hs, int nres);
+SynKernelFn syn_res_fwd_kernel_for(int Hs, int nres);
+SynKernelFn syn_bwd_kernel_for(int Hs, int nres);
 
 // ---------------------------------------------------------------- reductions, optimiser
 constexpr int RED_MAXSEG = 12;
+constexpr int RED_COLS = 16, RED_RG = 16;  // columns per block, row groups per column
 struct RedSeg {
   const float* src;    // [rows][ld]
   int rows, cols, ld;
@@ -139,5 +140,6 @@ struct AdamArgs {
   float lr, beta1, beta2, eps;
 };
 __global__ void adam_kernel(AdamArgs a);
+__global__ void adam_advance_kernel(int32_t* step);
 
 }  // namespace cc

@@ -6,12 +6,12 @@
 
 namespace cc {
 
-// Column sums of several [rows][ld] partial matrices: 64 columns per block,
-// four row groups per column combined in fixed order.
+// Column sums of several [rows][ld] partial matrices: 16 columns per block,
+// 16 row groups per column combined in fixed order.
 __global__ __launch_bounds__(256) void reduce_cols_kernel(ReduceArgs a) {
-  __shared__ float s_p[4][64];
-  const int tid = threadIdx.x, c64 = tid & 63, rg = tid >> 6;
-  const int gc = blockIdx.x * 64 + c64;
+  __shared__ float s_p[RED_RG][RED_COLS];
+  const int tid = threadIdx.x, cl = tid % RED_COLS, rg = tid / RED_COLS;
+  const int gc = blockIdx.x * RED_COLS + cl;
   int sg = -1;
   for (int k = 0; k < a.nseg; ++k)
     if (gc >= a.col_start[k] && gc < a.col_start[k + 1]) sg = k;
@@ -19,13 +19,14 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(ReduceArgs a) {
   if (sg >= 0) {
     const RedSeg& S = a.seg[sg];
     const int col = gc - a.col_start[sg];
-    for (int r = rg; r < S.rows; r += 4) acc += S.src[(size_t)r * S.ld + col];
+    for (int r = rg; r < S.rows; r += RED_RG) acc += S.src[(size_t)r * S.ld + col];
   }
-  s_p[rg][c64] = acc;
+  s_p[rg][cl] = acc;
   __syncthreads();
   bool bad = false;
   if (rg == 0 && sg >= 0) {
-    const float v = ((s_p[0][c64] + s_p[1][c64]) + s_p[2][c64]) + s_p[3][c64];
+    float v = 0.0f;
+    for (int k = 0; k < RED_RG; ++k) v += s_p[k][cl];
     a.seg[sg].dst[gc - a.col_start[sg]] = v;
     bad = !finitef(v);
   }
@@ -64,8 +65,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) {
   }
 }
 
-// Adam (Kingma & Ba) with bias correction; t = step[0] + 1.  The last block
-// to finish advances step[0] and clears the completion counter step[1].
+// Adam (Kingma & Ba) with bias correction; t = step[0] + 1.
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const int t = a.step[0] + 1;
   const float bc1 = 1.0f - powf(a.beta1, (float)t);
@@ -79,15 +79,11 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
     a.v[i] = v;
     a.theta[i] -= a.lr * (m * k1) / (sqrtf(v * k2) + a.eps);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&a.step[1], 1);
-    if (prev == (int)gridDim.x - 1) {
-      atomicExch(&a.step[0], t);
-      atomicExch(&a.step[1], 0);
-    }
-  }
+}
+
+// Advances the step counter after the update kernel has read it.
+__global__ void adam_advance_kernel(int32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
 }
 
 }  // namespace cc

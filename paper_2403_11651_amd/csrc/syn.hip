@@ -57,59 +57,98 @@ __device__ __forceinline__ void compute_z(const SynArgs& a, int i, int j, float 
   }
 }
 
-// offsets inside the packed synthesis parameters
-struct SynOff {
-  int W1, b1, W2, b2, res0;
-  __device__ SynOff(int Hs, int L) {
-    W1 = 0;
-    b1 = Hs * L;
-    W2 = b1 + Hs;
-    b2 = W2 + 3 * Hs;
-    res0 = b2 + 3;
-  }
+// Synthesis weights staged in LDS once per work-group, laid out for 128-bit
+// broadcast reads: row f of W1 padded to 8 with b1[f] in column 7 (z[7] = 1),
+// W2 transposed to [f][4], and each residual conv as W (81) then b (3).
+template <int HS, int NRES>
+struct SynW {
+  float W1p[HS][8];
+  float W2t[HS][4];
+  float b2[4];
+  float conv[NRES][88];
 };
 
-template <int HS>
+template <int HS, int NRES>
+__device__ __forceinline__ void stage_weights(SynW<HS, NRES>& sw, const float* __restrict__ w, int L, int tid) {
+  const int b1 = HS * L, W2 = b1 + HS, b2 = W2 + 3 * HS, res0 = b2 + 3;
+  for (int i = tid; i < HS * 8; i += SYN_THREADS) {
+    const int f = i / 8, c = i % 8;
+    sw.W1p[f][c] = c < L ? w[f * L + c] : (c == 7 ? w[b1 + f] : 0.0f);
+  }
+  for (int i = tid; i < HS * 4; i += SYN_THREADS) {
+    const int f = i / 4, c = i % 4;
+    sw.W2t[f][c] = c < 3 ? w[W2 + c * HS + f] : 0.0f;
+  }
+  if (tid < 4) sw.b2[tid] = tid < 3 ? w[b2 + tid] : 0.0f;
+  for (int i = tid; i < NRES * 88; i += SYN_THREADS) {
+    const int r = i / 88, k = i % 88;
+    sw.conv[r][k] = k < 84 ? w[res0 + r * 84 + k] : 0.0f;
+  }
+}
+
+// The two 1x1 layers at one pixel: a = ReLU(W1 z + b1) (z[7] = 1 carries the
+// bias), t0 = ReLU(W2 a + b2).  Keeps a and the pre-activation sign if asked.
+template <int HS, int NRES, bool KEEP>
+__device__ __forceinline__ void layers_1x1(const SynW<HS, NRES>& sw, const float (&zz)[8], float (&t)[3],
+                                           float* av, bool* pos) {
+  t[0] = sw.b2[0]; t[1] = sw.b2[1]; t[2] = sw.b2[2];
+#pragma unroll
+  for (int f = 0; f < HS; ++f) {
+    const f32x4 w0 = *reinterpret_cast<const f32x4*>(&sw.W1p[f][0]);
+    const f32x4 w1 = *reinterpret_cast<const f32x4*>(&sw.W1p[f][4]);
+    const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] + w1.y * zz[5] +
+                      w1.z * zz[6] + w1.w * zz[7];
+    const float a = fmaxf(pre, 0.0f);
+    const f32x4 w2 = *reinterpret_cast<const f32x4*>(&sw.W2t[f][0]);
+    t[0] += w2.x * a; t[1] += w2.y * a; t[2] += w2.z * a;
+    if (KEEP) { av[f] = a; pos[f] = pre > 0.0f; }
+  }
+  t[0] = fmaxf(t[0], 0.0f); t[1] = fmaxf(t[1], 0.0f); t[2] = fmaxf(t[2], 0.0f);
+}
+
+template <int HS, int NRES>
 __global__ __launch_bounds__(256) void syn_t0_kernel(SynArgs a) {
+  __shared__ SynW<HS, NRES> sw;
   const int H = a.geo.H, W = a.geo.W, L = a.geo.L;
+  stage_weights(sw, a.w, L, threadIdx.x);
+  __syncthreads();
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= H * W) return;
   const int i = idx / W, j = idx % W;
-  const SynOff o(HS, L);
-  const float* __restrict__ w = a.w;
-  float z[MAXL];
+  float z[MAXL], zz[8], t[3];
   compute_z(a, i, j, z);
-  float t[3] = {w[o.b2 + 0], w[o.b2 + 1], w[o.b2 + 2]};
 #pragma unroll
-  for (int f = 0; f < HS; ++f) {
-    float pre = w[o.b1 + f];
+  for (int c = 0; c < 7; ++c) zz[c] = c < L ? z[c] : 0.0f;
+  zz[7] = 1.0f;
+  layers_1x1<HS, NRES, false>(sw, zz, t, nullptr, nullptr);
 #pragma unroll
-    for (int c = 0; c < MAXL; ++c)
-      if (c < L) pre += w[o.W1 + f * L + c] * z[c];
-    const float av = fmaxf(pre, 0.0f);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) t[c] += w[o.W2 + c * HS + f] * av;
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) a.t0[(size_t)c * H * W + idx] = fmaxf(t[c], 0.0f);
+  for (int c = 0; c < 3; ++c) a.t0[(size_t)c * H * W + idx] = t[c];
 }
 
 // One residual layer t_r = phi(t_{r-1} + conv(t_{r-1}) + b) on the frame region
-// [lo, hi)^2 of a tile frame of side FS whose position (0, 0) is image pixel
+// [LO, FS-LO)^2 of a tile frame of side FS whose position (0, 0) is image pixel
 // (fi0, fj0).  Values at frame positions outside the image are the values at
 // the clamped position (replicate border), so the conv reads its neighbours
-// around the clamped position.
-__device__ __forceinline__ void res_layer(const float* __restrict__ wr, const float* src, float* dst, int FS, int lo,
-                                          int hi, int fi0, int fj0, int H, int W, bool relu, int tid) {
-  const int side = hi - lo;
-  for (int p = tid; p < side * side; p += SYN_THREADS) {
-    const int fa = lo + p / side, fb = lo + p % side;
-    const int ca = clampi(fi0 + fa, 0, H - 1) - fi0, cb = clampi(fj0 + fb, 0, W - 1) - fj0;
+// around the clamped position.  INSIDE: the frame lies inside the image.
+template <int FS, int LO, bool INSIDE>
+__device__ __forceinline__ void res_layer(const float* wr, const float* src, float* dst, int fi0, int fj0, int H,
+                                          int W, bool relu, int tid) {
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
+  int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
+  asm volatile("" : "+s"(zo));
+  wr += zo;
+  for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
+    const int fa = LO + p / SIDE, fb = LO + p % SIDE;
+    int ca = fa, cb = fb;
+    if (!INSIDE) {
+      ca = clampi(fi0 + fa, 0, H - 1) - fi0;
+      cb = clampi(fj0 + fb, 0, W - 1) - fj0;
+    }
     float nb[3][9];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int d = 0; d < 9; ++d) nb[c][d] = src[c * SYN_FMAX * SYN_FMAX + (ca + d / 3 - 1) * FS + cb + d % 3 - 1];
+      for (int d = 0; d < 9; ++d) nb[c][d] = src[c * FA + (ca + d / 3 - 1) * FS + cb + d % 3 - 1];
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
       float pre = nb[o][4] + wr[81 + o];
@@ -117,20 +156,23 @@ __device__ __forceinline__ void res_layer(const float* __restrict__ wr, const fl
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int d = 0; d < 9; ++d) pre += wr[o * 27 + c * 9 + d] * nb[c][d];
-      dst[o * SYN_FMAX * SYN_FMAX + fa * FS + fb] = relu ? fmaxf(pre, 0.0f) : pre;
+      dst[o * FA + fa * FS + fb] = relu ? fmaxf(pre, 0.0f) : pre;
     }
   }
 }
 
+template <int HS, int NRES>
 __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  constexpr int FA = SYN_FMAX * SYN_FMAX, E = NRES, FS = SYN_T + 2 * E;
+  __shared__ SynW<HS, NRES> sw;
   __shared__ float s_t[2][3 * FA];
   const int H = a.geo.H, W = a.geo.W, tid = threadIdx.x;
-  const int E = a.n_res, FS = SYN_T + 2 * E;
+  stage_weights(sw, a.w, a.geo.L, tid);
   float sse = 0.0f;
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int i0 = (tile / a.n_tiles_x) * SYN_T, j0 = (tile % a.n_tiles_x) * SYN_T;
     const int fi0 = i0 - E, fj0 = j0 - E;
+    const bool inside = fi0 >= 0 && fj0 >= 0 && fi0 + FS <= H && fj0 + FS <= W;
     for (int p = tid; p < FS * FS; p += SYN_THREADS) {
       const int fa = p / FS, fb = p % FS;
       const int ii = clampi(fi0 + fa, 0, H - 1), jj = clampi(fj0 + fb, 0, W - 1);
@@ -138,10 +180,12 @@ __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
       for (int c = 0; c < 3; ++c) s_t[0][c * FA + fa * FS + fb] = a.t0[(size_t)c * H * W + ii * W + jj];
     }
     __syncthreads();
-    int cur = 0;
-    for (int r = 1; r <= E; ++r) {
-      res_layer(a.w + a.res_off + (r - 1) * 84, s_t[cur], s_t[cur ^ 1], FS, r, FS - r, fi0, fj0, H, W, r < E, tid);
-      cur ^= 1;
+    if (inside) res_layer<FS, 1, true>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
+    else res_layer<FS, 1, false>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
+    __syncthreads();
+    if constexpr (NRES >= 2) {
+      if (inside) res_layer<FS, 2, true>(sw.conv[1], s_t[1], s_t[0], fi0, fj0, H, W, false, tid);
+      else res_layer<FS, 2, false>(sw.conv[1], s_t[1], s_t[0], fi0, fj0, H, W, false, tid);
       __syncthreads();
     }
     {
@@ -150,7 +194,7 @@ __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
       if (i < H && j < W) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float xh = s_t[cur][c * FA + (E + ty) * FS + E + tx];
+          const float xh = s_t[NRES & 1][c * FA + (E + ty) * FS + E + tx];
           const size_t gi = (size_t)c * H * W + i * W + j;
           if (a.xhat) a.xhat[gi] = xh;
           if (a.img) { const float e = xh - a.img[gi]; sse += e * e; }
@@ -207,6 +251,27 @@ __device__ __forceinline__ void xty_accumulate(f32x4 (&acc)[BM][BN], float* stg,
   }
 }
 
+// acc[bm][bn] += X^T Y over the 64 rows (items) of X [64][LX] and Y [64][LY]
+// already staged in LDS by the wave (columns nx / ny and beyond read as 0).
+template <int BM, int BN>
+__device__ __forceinline__ void mfma_xty64(f32x4 (&acc)[BM][BN], const float* Xs, int LX, int nx, const float* Ys,
+                                           int LY, int ny, int lane) {
+  const int col = lane & 15;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int item = 4 * t + (lane >> 4);
+    float av[BM], bv[BN];
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm) av[bm] = (16 * bm + col < nx) ? Xs[item * LX + 16 * bm + col] : 0.0f;
+#pragma unroll
+    for (int bn = 0; bn < BN; ++bn) bv[bn] = (16 * bn + col < ny) ? Ys[item * LY + 16 * bn + col] : 0.0f;
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn) acc[bm][bn] = mfma16x16x4(av[bm], bv[bn], acc[bm][bn]);
+  }
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
 #pragma unroll
@@ -215,35 +280,112 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
     for (int bn = 0; bn < BN; ++bn) acc[bm][bn] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
-template <int HS>
+// Adjoint of one residual layer at the frame positions of region [LO, FS-LO)
+// (in-image ones; others get 0): g_{r-1}[q] = g_pre[q] + sum over padded
+// positions q' that clamp to q of sum_d W_d^T g_pre[q' - d], in-image terms
+// only (the replicate border folds the padded positions onto the edge).
+template <int FS, int LO, bool INSIDE>
+__device__ __forceinline__ void res_adjoint(const float* wr, const float* g, float* gout, int fi0, int fj0, int H,
+                                            int W, int tid) {
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
+  int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
+  asm volatile("" : "+s"(zo));
+  wr += zo;
+  for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
+    const int fa = LO + p / SIDE, fb = LO + p % SIDE;
+    const int fp = fa * FS + fb;
+    float out[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = g[c * FA + fp];
+    if (INSIDE) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d) {
+        const int sp = fp - (d / 3 - 1) * FS - (d % 3 - 1);
+        const float g0 = g[sp], g1 = g[FA + sp], g2 = g[2 * FA + sp];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] += wr[c * 9 + d] * g0 + wr[27 + c * 9 + d] * g1 + wr[54 + c * 9 + d] * g2;
+      }
+    } else {
+      const int ii = fi0 + fa, jj = fj0 + fb;
+      if (ii < 0 || ii >= H || jj < 0 || jj >= W) {
+        out[0] = out[1] = out[2] = 0.0f;
+      } else {
+        for (int ay = -1; ay <= 1; ++ay) {
+          if (ay != 0 && !((ay < 0 && ii == 0) || (ay > 0 && ii == H - 1))) continue;
+          for (int ax = -1; ax <= 1; ++ax) {
+            if (ax != 0 && !((ax < 0 && jj == 0) || (ax > 0 && jj == W - 1))) continue;
+#pragma unroll
+            for (int d = 0; d < 9; ++d) {
+              const int dy = d / 3 - 1, dx = d % 3 - 1;
+              const int si = ii + ay - dy, sj = jj + ax - dx;
+              const bool ok = si >= 0 && si < H && sj >= 0 && sj < W;
+              const int sp = ok ? (fa + ay - dy) * FS + fb + ax - dx : fp;
+              const float m = ok ? 1.0f : 0.0f;
+              const float g0 = m * g[sp], g1 = m * g[FA + sp], g2 = m * g[2 * FA + sp];
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                out[c] += wr[c * 9 + d] * g0 + wr[27 + c * 9 + d] * g1 + wr[54 + c * 9 + d] * g2;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gout[c * FA + fp] = out[c];
+  }
+}
+
+// g_pre_r = g_t_r * ReLU'(t_r) in place on region [LO, FS-LO)
+template <int FS, int LO>
+__device__ __forceinline__ void relu_mask(const float* t, float* g, int tid) {
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
+  for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
+    const int fp = (LO + p / SIDE) * FS + LO + p % SIDE;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!(t[c * FA + fp] > 0.0f)) g[c * FA + fp] = 0.0f;
+  }
+}
+
+template <int HS, int NRES>
 __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  constexpr int FA = SYN_FMAX * SYN_FMAX, E = 2 * NRES, FS = SYN_T + 2 * E;
   constexpr int BMA = (HS + 15) / 16;   // blocks of the hidden width
   constexpr int BNA = (HS + 1 + 15) / 16;
-  // widest staged product per item: (g_a, [z, 1]), (g_pre_t, [a, 1]) or
-  // (g_pre_r, 3x3x3 neighbourhood + 1)
-  constexpr int STG_W1 = (HS | 1) + ((MAXL + 1) | 1), STG_W2 = 3 + ((HS + 1) | 1), STG_R = 3 + (28 | 1);
-  constexpr int STG_ROW = STG_W1 > STG_W2 ? (STG_W1 > STG_R ? STG_W1 : STG_R) : (STG_W2 > STG_R ? STG_W2 : STG_R);
-  __shared__ float s_t[SYN_MAXRES + 1][3 * FA];
-  __shared__ float s_g[2][3 * FA];
-  __shared__ float s_stg[SYN_THREADS / 64][32 * STG_ROW];
+  // LDS pool: residual-conv frames (t_0..t_NRES, two gradient buffers) and the
+  // per-wave staging of the conv weight gradients live during phases 1-5; the
+  // per-pixel phase 6 reuses the whole pool as 64-row staging per wave.
+  constexpr int FRAMES = (NRES + 1 + 2) * 3 * FA;
+  constexpr int STG_R = 32 * (3 + (28 | 1));                 // conv staging per wave (32 items)
+  constexpr int LX1 = HS | 1, LY1 = 9, LX2 = 3, LY2 = (HS + 1) | 1;
+  constexpr int P6W = 64 * ((LX1 + LY1) > (LX2 + LY2) ? (LX1 + LY1) : (LX2 + LY2));  // phase-6 staging per wave
+  constexpr int POOL = (FRAMES + 4 * STG_R) > 4 * P6W ? (FRAMES + 4 * STG_R) : 4 * P6W;
+  __shared__ SynW<HS, NRES> sw;
+  __shared__ float pool[POOL];
+  float (*s_t)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool);
+  float (*s_g)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool + (NRES + 1) * 3 * FA);
 
-  const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nres = a.n_res, E = 2 * nres, FS = SYN_T + 2 * E;
-  const SynOff o(HS, L);
-  const float* __restrict__ w = a.w;
-  float* stg = s_stg[wave];
+  const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid0 = threadIdx.x, lane = tid0 & 63, wave = tid0 >> 6;
+  stage_weights(sw, a.w, L, tid0);
+  float* stg = pool + FRAMES + wave * STG_R;
 
-  f32x4 accW1[BMA][1], accW2[1][BNA], accR[SYN_MAXRES][1][2];
+  f32x4 accW1[BMA][1], accW2[1][BNA], accR[NRES][1][2];
   zero_acc(accW1);
   zero_acc(accW2);
 #pragma unroll
-  for (int r = 0; r < SYN_MAXRES; ++r) zero_acc(accR[r]);
+  for (int r = 0; r < NRES; ++r) zero_acc(accR[r]);
   float sse = 0.0f;
 
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int i0 = (tile / a.n_tiles_x) * SYN_T, j0 = (tile % a.n_tiles_x) * SYN_T;
     const int fi0 = i0 - E, fj0 = j0 - E;
+    const bool inside = fi0 >= 0 && fj0 >= 0 && fi0 + FS <= H && fj0 + FS <= W;
+    // opaque copy of the thread index: the per-thread address arithmetic of
+    // the unrolled frame loops is recomputed in each tile rather than hoisted
+    // out of the tile loop (where it would have to live in registers)
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int ty = tid / SYN_T, tx = tid % SYN_T;
     // 1. t0 on the frame (clamped coordinates)
     for (int p = tid; p < FS * FS; p += SYN_THREADS) {
       const int fa = p / FS, fb = p % FS;
@@ -253,169 +395,158 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
     }
     __syncthreads();
     // 2. residual layers forward, layer r on halo E - r
-    for (int r = 1; r <= nres; ++r) {
-      res_layer(w + o.res0 + (r - 1) * 84, s_t[r - 1], s_t[r], FS, r, FS - r, fi0, fj0, H, W, r < nres, tid);
+    if (inside) res_layer<FS, 1, true>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
+    else res_layer<FS, 1, false>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
+    __syncthreads();
+    if constexpr (NRES >= 2) {
+      if (inside) res_layer<FS, 2, true>(sw.conv[1], s_t[1], s_t[2], fi0, fj0, H, W, false, tid);
+      else res_layer<FS, 2, false>(sw.conv[1], s_t[1], s_t[2], fi0, fj0, H, W, false, tid);
       __syncthreads();
     }
-    // 3. dL/dx_hat on halo nres; zero outside the image
-    int cur = 0;
+    // 3. dL/dx_hat on halo NRES; zero outside the image
     {
-      const int lo = E - nres, side = SYN_T + 2 * nres;
-      for (int p = tid; p < side * side; p += SYN_THREADS) {
-        const int fa = lo + p / side, fb = lo + p % side;
+      constexpr int LO = E - NRES, SIDE = SYN_T + 2 * NRES;
+      for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
+        const int fa = LO + p / SIDE, fb = LO + p % SIDE;
         const int ii = fi0 + fa, jj = fj0 + fb;
         const bool in = ii >= 0 && ii < H && jj >= 0 && jj < W;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int fp = c * FA + fa * FS + fb;
-          s_g[0][fp] = in ? a.dscale * (s_t[nres][fp] - a.img[(size_t)c * H * W + ii * W + jj]) : 0.0f;
+          s_g[0][fp] = in ? a.dscale * (s_t[NRES][fp] - a.img[(size_t)c * H * W + ii * W + jj]) : 0.0f;
         }
       }
     }
     __syncthreads();
-    // 4. residual layers backward
-    for (int r = nres; r >= 1; --r) {
-      const float* wr = w + o.res0 + (r - 1) * 84;
-      // g_pre_r = g_t_r * ReLU'(pre_r) on halo r (identity for the last layer)
-      if (r < nres) {
-        const int lo = E - r, side = SYN_T + 2 * r;
-        for (int p = tid; p < side * side; p += SYN_THREADS) {
-          const int fp = (lo + p / side) * FS + lo + p % side;
+    // 4. residual layers backward: weight gradient over the tile's own pixels,
+    // then the adjoint one ring smaller
+    const bool own = (i0 + ty) < H && (j0 + tx) < W;
+    const int fpo = (E + ty) * FS + E + tx;
+    int cur = 0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            if (!(s_t[r][c * FA + fp] > 0.0f)) s_g[cur][c * FA + fp] = 0.0f;
-        }
+    for (int r = NRES; r >= 1; --r) {
+      if (r < NRES) {
+        relu_mask<FS, E - NRES + 1>(s_t[r], s_g[cur], tid);  // layer r < NRES: halo r = NRES - 1 here
         __syncthreads();
       }
-      // weight gradient of layer r over the tile's own pixels
       {
-        const int ty = tid / SYN_T, tx = tid % SYN_T;
-        const bool in = (i0 + ty) < H && (j0 + tx) < W;
-        const int fp = (E + ty) * FS + E + tx;
         float xv[3], yv[28];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xv[c] = in ? s_g[cur][c * FA + fp] : 0.0f;
+        for (int c = 0; c < 3; ++c) xv[c] = own ? s_g[cur][c * FA + fpo] : 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int d = 0; d < 9; ++d) yv[c * 9 + d] = in ? s_t[r - 1][c * FA + fp + (d / 3 - 1) * FS + d % 3 - 1] : 0.0f;
-        yv[27] = in ? 1.0f : 0.0f;
-        if (r == 1) xty_accumulate(accR[0], stg, xv, yv, lane);
-        else xty_accumulate(accR[SYN_MAXRES - 1], stg, xv, yv, lane);
+          for (int d = 0; d < 9; ++d) yv[c * 9 + d] = own ? s_t[r - 1][c * FA + fpo + (d / 3 - 1) * FS + d % 3 - 1] : 0.0f;
+        yv[27] = own ? 1.0f : 0.0f;
+        xty_accumulate(accR[r - 1], stg, xv, yv, lane);
       }
-      // adjoint: g_t_{r-1}[q] = g_pre[q] + sum over padded positions q' that clamp
-      // to q of sum_d W_d^T g_pre[q' - d], in-image terms only
-      {
-        const int lo = E - r + 1, side = SYN_T + 2 * (r - 1);
-        for (int p = tid; p < side * side; p += SYN_THREADS) {
-          const int fa = lo + p / side, fb = lo + p % side;
-          const int ii = fi0 + fa, jj = fj0 + fb;
-          const int fp = fa * FS + fb;
-          float out[3] = {0.0f, 0.0f, 0.0f};
-          if (ii >= 0 && ii < H && jj >= 0 && jj < W) {
-            int ay[3], ax[3], nay = 0, nax = 0;
-            ay[nay++] = 0;
-            if (ii == 0) ay[nay++] = -1;
-            if (ii == H - 1) ay[nay++] = 1;
-            ax[nax++] = 0;
-            if (jj == 0) ax[nax++] = -1;
-            if (jj == W - 1) ax[nax++] = 1;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) out[c] = s_g[cur][c * FA + fp];
-            for (int u1 = 0; u1 < nay; ++u1) {
-              for (int u2 = 0; u2 < nax; ++u2) {
-#pragma unroll
-                for (int d = 0; d < 9; ++d) {
-                  const int dy = d / 3 - 1, dx = d % 3 - 1;
-                  const int si = ii + ay[u1] - dy, sj = jj + ax[u2] - dx;
-                  if (si < 0 || si >= H || sj < 0 || sj >= W) continue;
-                  const int sp = (fa + ay[u1] - dy) * FS + fb + ax[u2] - dx;
-                  const float g0 = s_g[cur][sp], g1 = s_g[cur][FA + sp], g2 = s_g[cur][2 * FA + sp];
-#pragma unroll
-                  for (int c = 0; c < 3; ++c)
-                    out[c] += wr[0 * 27 + c * 9 + d] * g0 + wr[1 * 27 + c * 9 + d] * g1 + wr[2 * 27 + c * 9 + d] * g2;
-                }
-              }
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 3; ++c) s_g[cur ^ 1][c * FA + fp] = out[c];
-        }
+      if (r == 2) {
+        if (inside) res_adjoint<FS, E - 1, true>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
+        else res_adjoint<FS, E - 1, false>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
+      } else {
+        if (inside) res_adjoint<FS, E, true>(sw.conv[0], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
+        else res_adjoint<FS, E, false>(sw.conv[0], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
       }
       cur ^= 1;
       __syncthreads();
     }
     // 5./6. per pixel: 1x1 layers recomputed, then their adjoint down to z
     {
-      const int ty = tid / SYN_T, tx = tid % SYN_T;
       const int i = i0 + ty, j = j0 + tx;
-      const bool in = i < H && j < W;
-      const int fp = (E + ty) * FS + E + tx;
       float gpt[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float t0v = s_t[0][c * FA + fp];
-        gpt[c] = (in && t0v > 0.0f) ? s_g[cur][c * FA + fp] : 0.0f;
-        if (in) {
-          const float e = s_t[nres][c * FA + fp] - a.img[(size_t)c * H * W + i * W + j];
+        const float t0v = s_t[0][c * FA + fpo];
+        gpt[c] = (own && t0v > 0.0f) ? s_g[cur][c * FA + fpo] : 0.0f;
+        if (own) {
+          const float e = s_t[NRES][c * FA + fpo] - a.img[(size_t)c * H * W + i * W + j];
           sse += e * e;
         }
       }
-      float z[MAXL];
-      if (in) compute_z(a, i, j, z);
-      else {
+      float z[MAXL], zz[8];
+      if (own) compute_z(a, i, j, z);
 #pragma unroll
-        for (int c = 0; c < MAXL; ++c) z[c] = 0.0f;
+      for (int c = 0; c < 7; ++c) zz[c] = (own && c < L) ? z[c] : 0.0f;
+      zz[7] = own ? 1.0f : 0.0f;
+      __syncthreads();  // the frames are dead: the pool becomes phase-6 staging
+      float* P6 = pool + wave * P6W;
+      int wz = 0;  // opaque zero: weight reads stay where they are used
+      asm volatile("" : "+s"(wz));
+      const f32x4* W1q = reinterpret_cast<const f32x4*>(&sw.W1p[0][0]) + wz;
+      const f32x4* W2q = reinterpret_cast<const f32x4*>(&sw.W2t[0][0]) + wz;
+      // (a) W2, b2 from (g_pre_t, [a, 1]), one staged row per pixel
+      {
+        float* X2 = P6;
+        float* Y2 = P6 + 64 * LX2;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X2[lane * LX2 + c] = gpt[c];
+#pragma unroll 4
+        for (int f = 0; f < HS; ++f) {
+          const f32x4 w0 = W1q[2 * f], w1 = W1q[2 * f + 1];
+          const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] +
+                            w1.y * zz[5] + w1.z * zz[6] + w1.w * zz[7];
+          Y2[lane * LY2 + f] = fmaxf(pre, 0.0f);
+        }
+        Y2[lane * LY2 + HS] = own ? 1.0f : 0.0f;
+        wave_lds_sync();
+        mfma_xty64(accW2, X2, LX2, 3, Y2, LY2, HS + 1, lane);
+        wave_lds_sync();
       }
-      float av1[HS + 1], ga[HS], gz[MAXL];
+      // (b) g_a = W2^T g_pre_t masked by the first layer's ReLU; W1, b1 from
+      // (g_a, [z, 1]); dL/dz = W1^T g_a
+      {
+        int wz2 = 0;
+        asm volatile("" : "+s"(wz2));
+        W1q += wz2;
+        W2q += wz2;
+        float* X1 = P6;
+        float* Y1 = P6 + 64 * LX1;
+        float gz[8];
 #pragma unroll
-      for (int c = 0; c < MAXL; ++c) gz[c] = 0.0f;
+        for (int c = 0; c < 8; ++c) gz[c] = 0.0f;
+#pragma unroll 4
+        for (int f = 0; f < HS; ++f) {
+          const f32x4 w0 = W1q[2 * f], w1 = W1q[2 * f + 1];
+          const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] +
+                            w1.y * zz[5] + w1.z * zz[6] + w1.w * zz[7];
+          const f32x4 w2 = W2q[f];
+          float g = w2.x * gpt[0] + w2.y * gpt[1] + w2.z * gpt[2];
+          g = pre > 0.0f ? g : 0.0f;
+          X1[lane * LX1 + f] = g;
+          gz[0] += w0.x * g; gz[1] += w0.y * g; gz[2] += w0.z * g; gz[3] += w0.w * g;
+          gz[4] += w1.x * g; gz[5] += w1.y * g; gz[6] += w1.z * g;
+        }
 #pragma unroll
-      for (int f = 0; f < HS; ++f) {
-        float pre = w[o.b1 + f];
+        for (int c = 0; c < 8; ++c) Y1[lane * LY1 + c] = zz[c];
+        if (own) {
+          a.g_y[i * W + j] = gz[0];
 #pragma unroll
-        for (int c = 0; c < MAXL; ++c)
-          if (c < L) pre += w[o.W1 + f * L + c] * z[c];
-        av1[f] = in ? fmaxf(pre, 0.0f) : 0.0f;
-        float g = w[o.W2 + f] * gpt[0] + w[o.W2 + HS + f] * gpt[1] + w[o.W2 + 2 * HS + f] * gpt[2];
-        g = pre > 0.0f ? g : 0.0f;
-        ga[f] = g;
-#pragma unroll
-        for (int c = 0; c < MAXL; ++c)
-          if (c < L) gz[c] += w[o.W1 + f * L + c] * g;
+          for (int c = 1; c < MAXL; ++c)
+            if (c < L) a.gz[(size_t)(c - 1) * H * W + i * W + j] = gz[c];
+        }
+        wave_lds_sync();
+        mfma_xty64(accW1, X1, LX1, HS, Y1, LY1, 8, lane);
+        wave_lds_sync();
       }
-      av1[HS] = in ? 1.0f : 0.0f;
-      if (in) {
-        a.g_y[i * W + j] = gz[0];
-#pragma unroll
-        for (int c = 1; c < MAXL; ++c)
-          if (c < L) a.gz[(size_t)(c - 1) * H * W + i * W + j] = gz[c];
-      }
-      // weight gradients: W2, b2 from (g_pre_t, [a, 1]); W1, b1 from (g_a, [z, 1])
-      xty_accumulate(accW2, stg, gpt, av1, lane);
-      float zv[MAXL + 1];
-#pragma unroll
-      for (int c = 0; c < MAXL; ++c) zv[c] = c < L ? z[c] : 0.0f;
-      zv[MAXL] = in ? 1.0f : 0.0f;
-      xty_accumulate(accW1, stg, ga, zv, lane);
     }
     __syncthreads();
   }
 
   // ---- block partials
-  const int n_syn = HS * L + HS + 3 * HS + 3 + nres * 84;
-  static_assert(4 * (48 * MAXL + 48 + 3 * 48 + 3 + SYN_MAXRES * 84) <= (SYN_MAXRES + 1) * 3 * FA, "partials fit");
-  float* red = &s_t[0][0];  // [waves][n_syn], spans the whole s_t array
+  const int n_syn = HS * L + HS + 3 * HS + 3 + NRES * 84;
+  const int oW1 = 0, ob1 = HS * L, oW2 = ob1 + HS, ob2 = oW2 + 3 * HS, ores = ob2 + 3;
+  static_assert(4 * (HS * MAXL + HS + 3 * HS + 3 + NRES * 84) <= POOL, "partials fit");
+  float* red = pool;  // [waves][n_syn]
   float* rw = red + wave * n_syn;
   const int lg = lane >> 4, lc = lane & 15;
 #pragma unroll
   for (int bm = 0; bm < BMA; ++bm)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int f = 16 * bm + 4 * lg + r, c = lc;  // X index = hidden unit, Y index = z channel (MAXL = bias)
+      const int f = 16 * bm + 4 * lg + r, c = lc;  // X index = hidden unit, Y index = z channel (7 = bias)
       if (f < HS) {
-        if (c < L) rw[o.W1 + f * L + c] = accW1[bm][0][r];
-        else if (c == MAXL) rw[o.b1 + f] = accW1[bm][0][r];
+        if (c < L) rw[oW1 + f * L + c] = accW1[bm][0][r];
+        else if (c == 7) rw[ob1 + f] = accW1[bm][0][r];
       }
     }
 #pragma unroll
@@ -424,20 +555,20 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
     for (int r = 0; r < 4; ++r) {
       const int c = 4 * lg + r, f = 16 * bn + lc;  // X index = output channel, Y index = hidden unit (HS = bias)
       if (c < 3) {
-        if (f < HS) rw[o.W2 + c * HS + f] = accW2[0][bn][r];
-        else if (f == HS) rw[o.b2 + c] = accW2[0][bn][r];
+        if (f < HS) rw[oW2 + c * HS + f] = accW2[0][bn][r];
+        else if (f == HS) rw[ob2 + c] = accW2[0][bn][r];
       }
     }
-  for (int rr = 0; rr < nres; ++rr) {
-    const int slot = rr == 0 ? 0 : SYN_MAXRES - 1;
+#pragma unroll
+  for (int rr = 0; rr < NRES; ++rr) {
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int oc = 4 * lg + r, k = 16 * bn + lc;
         if (oc < 3) {
-          if (k < 27) rw[o.res0 + rr * 84 + oc * 27 + k] = accR[slot][0][bn][r];
-          else if (k == 27) rw[o.res0 + rr * 84 + 81 + oc] = accR[slot][0][bn][r];
+          if (k < 27) rw[ores + rr * 84 + oc * 27 + k] = accR[rr][0][bn][r];
+          else if (k == 27) rw[ores + rr * 84 + 81 + oc] = accR[rr][0][bn][r];
         }
       }
   }
@@ -445,40 +576,40 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
   sse = wave_sum(sse);
   if (lane == 0) s_red[wave] = sse;
   __syncthreads();
-  for (int p = tid; p < n_syn; p += SYN_THREADS) {
+  for (int p = tid0; p < n_syn; p += SYN_THREADS) {
     float acc = 0.0f;
     for (int k = 0; k < SYN_THREADS / 64; ++k) acc += red[k * n_syn + p];
     a.wpart[(size_t)blockIdx.x * n_syn + p] = acc;
   }
-  if (tid == 0) {
+  if (tid0 == 0) {
     float acc = 0.0f;
     for (int k = 0; k < SYN_THREADS / 64; ++k) acc += s_red[k];
     a.spart[blockIdx.x] = acc;
   }
 }
 
-SynKernelFn syn_t0_kernel_for(int Hs) {
-  switch (Hs) {
-    case 8: return syn_t0_kernel<8>;
-    case 16: return syn_t0_kernel<16>;
-    case 24: return syn_t0_kernel<24>;
-    case 32: return syn_t0_kernel<32>;
-    case 40: return syn_t0_kernel<40>;
-    case 48: return syn_t0_kernel<48>;
-  }
+#define CC_SYN_TABLE(KERNEL)                                         \
+  if (nres == 1) switch (Hs) {                                       \
+      case 8: return KERNEL<8, 1>;                                   \
+      case 16: return KERNEL<16, 1>;                                 \
+      case 24: return KERNEL<24, 1>;                                 \
+      case 32: return KERNEL<32, 1>;                                 \
+      case 40: return KERNEL<40, 1>;                                 \
+      case 48: return KERNEL<48, 1>;                                 \
+    }                                                                \
+  if (nres == 2) switch (Hs) {                                       \
+      case 8: return KERNEL<8, 2>;                                   \
+      case 16: return KERNEL<16, 2>;                                 \
+      case 24: return KERNEL<24, 2>;                                 \
+      case 32: return KERNEL<32, 2>;                                 \
+      case 40: return KERNEL<40, 2>;                                 \
+      case 48: return KERNEL<48, 2>;                                 \
+    }                                                                \
   return nullptr;
-}
-SynKernelFn syn_res_fwd_kernel_for(int Hs) { return (Hs % 8 == 0 && Hs >= 8 && Hs <= 48) ? syn_res_fwd_kernel : nullptr; }
-SynKernelFn syn_bwd_kernel_for(int Hs) {
-  switch (Hs) {
-    case 8: return syn_bwd_kernel<8>;
-    case 16: return syn_bwd_kernel<16>;
-    case 24: return syn_bwd_kernel<24>;
-    case 32: return syn_bwd_kernel<32>;
-    case 40: return syn_bwd_kernel<40>;
-    case 48: return syn_bwd_kernel<48>;
-  }
-  return nullptr;
-}
+
+SynKernelFn syn_t0_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_t0_kernel) }
+SynKernelFn syn_res_fwd_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_res_fwd_kernel) }
+SynKernelFn syn_bwd_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_bwd_kernel) }
+#undef CC_SYN_TABLE
 
 }  // namespace cc
