@@ -48,6 +48,35 @@ def algorithmic_counts(arch, H, W):
                 syn_flop=6.0 * syn_mac_per_px * n_px, iter_flop=6.0 * fwd_mac, kappa_dec=fwd_mac / n_px)
 
 
+ARM_SOURCES = ("paper_2403_11651_amd/csrc/arm.hip", "paper_2403_11651_amd/csrc/common.hpp",
+               "paper_2403_11651_amd/csrc/rate.hpp", "paper_2403_11651_amd/csrc/kernels.hpp")
+
+
+def arm_traffic_from_profile(workload):
+    """HBM bytes per ARM launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None if there is none for this workload or the kernel sources
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"arm_kernel_{workload}768x512.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ARM_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def make_inputs(arch, H=512, W=768):
     from paper_2403_11651_amd import workloads as WL
     L, C, NH, K, Hs, R = arch
@@ -105,6 +134,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (a known-size reference for "
+                         "the FETCH_SIZE / WRITE_SIZE hardware counters); not part of any timed step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path runs one image per GPU and images shard across GPUs with no "
@@ -141,6 +173,14 @@ def main():
                             stream=stream)
         B.coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, stream=stream)
 
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -203,7 +243,8 @@ def main():
                    "step": "coolchic_backward + coolchic_adam_step"},
         "roofline": {"bound": "mfma", "kernel": "arm_kernel (ARM forward+backward, fp32 MFMA 32x32x2)",
                      "achieved": round(arm_tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(arm_tflops / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(arm_tflops / FP32_PEAK_TFLOPS, 4),
+                     "traffic": arm_traffic_from_profile(args.workload),
                      "avg_launch_ms": round(arm_avg_ms, 5),
                      "algorithmic_flop_per_launch": cnt["arm_flop"]},
         "pass": {"iter_flop": cnt["iter_flop"], "achieved_tflops": round(pass_tflops, 2),

@@ -129,9 +129,10 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
 /* One Adam step (Kingma & Ba; the optimiser the paper trains with) on n
    parameters: m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2, theta <- theta -
    lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps) with t = step[0] + 1.
-   step points to one device int32, the number of steps already taken; the
-   call advances it on the device (so the call can be captured in a graph and
-   replayed).  theta, grad, m, v: device arrays of n floats. */
+   step points to two device int32: step[0] is the number of steps already
+   taken, which the call advances on the device (so a captured graph can be
+   replayed); step[1] is the call's completion counter, 0 before the first
+   call and left at 0.  theta, grad, m, v: device arrays of n floats. */
 int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n,
                        int32_t* step, float lr, float beta1, float beta2, float eps, void* stream);
 

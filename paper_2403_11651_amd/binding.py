@@ -196,10 +196,10 @@ def coolchic_decode_synth(p: Problem, yq, ups_w, syn_w, xhat, ws=None, stream=No
 
 def coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     n = theta.numel()
-    if step.dtype != torch.int32 or step.numel() < 1:
-        raise TypeError("step must be a device int32 tensor (the number of steps taken)")
+    if step.dtype != torch.int32 or step.numel() != 2:
+        raise TypeError("step must be a device int32 tensor of 2 elements: steps taken, completion counter (0)")
     rc = _lib.coolchic_adam_step(_ptr(theta, n, "theta"), _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
-                                 n, _ptr(step, None, "step"), lr, beta1, beta2, eps, _stream(stream))
+                                 n, _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
     _check(rc, "coolchic_adam_step")
 
 

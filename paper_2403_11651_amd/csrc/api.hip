@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "coolchic.h"
 #include "kernels.hpp"
@@ -22,6 +23,7 @@ struct Plan {
   int C, NH, K, Hs, nres;
   int64_t n_arm, n_ups, n_syn;
   int arm_grid, syn_grid, syn_tiles_x, syn_tiles, fold_grid, red_grid;
+  int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
@@ -97,9 +99,18 @@ int make_plan(const cc_problem* p, int which, Plan* P) {
   P->syn_tiles_x = cdiv(p->W, SYN_T);
   P->syn_tiles = P->syn_tiles_x * cdiv(p->H, SYN_T);
   P->syn_grid = std::min(P->syn_tiles, MAX_GRID);
-  for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);
+  for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);  // tiles
   P->fold_grid = cdiv(g.n_lat, 256);
-  P->red_grid = cdiv((int)(P->n_arm + P->n_ups + P->n_syn), RED_COLS);
+  // column reductions: 16 columns per block for the wide ARM / synthesis
+  // partials (at most MAX_GRID rows), one column per block for the tall
+  // upsampling partials (tiles x channels rows)
+  P->red_blocks_arm = cdiv((int)P->n_arm, 16);
+  P->red_blocks_syn = cdiv((int)P->n_syn, 16);
+  P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
+  for (int s = 0; s + 1 < L; ++s) {
+    P->red_blocks_ups[s] = 2 * UPS_K;
+    P->red_grid += P->red_blocks_ups[s];
+  }
 
   size_t cur = 0;
   for (int s = 1; s + 1 < L; ++s) P->up[s] = take(cur, (size_t)(L - 1 - s) * g.lh[s] * g.lw[s]);
@@ -112,7 +123,7 @@ int make_plan(const cc_problem* p, int which, Plan* P) {
     P->gext = take(cur, (size_t)nt * ARM_EXT);
     P->wpart_arm = take(cur, (size_t)P->arm_grid * P->n_arm);
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->n_syn);
-    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * 2 * UPS_K);
+    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * (L - 1 - s) * 2 * UPS_K);
     P->flags = take(cur, (size_t)P->red_grid + P->fold_grid);
   }
   P->total = cur;
@@ -137,20 +148,53 @@ int launch_stage(int stage, const void* fn, int grid, int block, void* args, hip
   return CC_OK;
 }
 
-// U_s for s = L-2 .. 1 (stack_1 is then complete for the fused last step).
+// Side stream per device for the ARM kernel, which is independent of the
+// upsampling / synthesis chain until the final reductions: the call forks it
+// off the caller's stream with an event and joins it back with another.
+// Created once per device on first use (default priority, non-blocking).
+struct Side {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int MAX_DEVICES = 64;
+Side g_side[MAX_DEVICES];
+std::mutex g_side_mu;  // also serialises the fork/join enqueue of concurrent calls
+
+int side_for_current_device(Side** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return CC_EHIP;
+  Side& sd = g_side[dev];
+  if (!sd.stream) {
+    if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return CC_EHIP;
+    if (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess) return CC_EHIP;
+    if (hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) return CC_EHIP;
+  }
+  *out = &sd;
+  return CC_OK;
+}
+
+int fork_to(Side* sd, hipStream_t main) {
+  if (hipEventRecord(sd->fork, main) != hipSuccess) return CC_EHIP;
+  return hipStreamWaitEvent(sd->stream, sd->fork, 0) == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+int join_from(Side* sd, hipStream_t main) {
+  if (hipEventRecord(sd->join, sd->stream) != hipSuccess) return CC_EHIP;
+  return hipStreamWaitEvent(main, sd->join, 0) == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+// U_s for s = L-2 .. 1 in one launch (stack_1 is then complete for the
+// step s = 0 fused into the synthesis kernels).
 int launch_ups_fwd(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
                    hipStream_t st) {
   const int L = P.geo.L;
-  for (int s = L - 2; s >= 1; --s) {
-    UpsFwdArgs a;
-    a.geo = P.geo; a.s = s; a.y = y; a.u = u; a.quant = quant;
-    a.taps = ups_w + (size_t)s * 2 * UPS_K;
-    a.up_in = (s + 1 <= L - 2) ? ws + P.up[s + 1] : nullptr;
-    a.up_out = ws + P.up[s];
-    int rc = launch((const void*)ups_fwd_kernel, cdiv(P.geo.lh[s] * P.geo.lw[s], 256), 256, &a, st);
-    if (rc) return rc;
-  }
-  return CC_OK;
+  if (L < 3) return CC_OK;
+  UpsFwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.geo = P.geo; a.y = y; a.u = u; a.quant = quant; a.ups_w = ups_w;
+  for (int s = 1; s + 1 < L; ++s) a.up_out[s] = ws + P.up[s];
+  const int grid = cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+  return launch((const void*)ups_fwd_kernel, grid, 256, &a, st);
 }
 
 SynArgs syn_args(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
@@ -213,7 +257,16 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   if (!armk || !t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side* sd = nullptr;
+  if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
+  ArmArgs aa;
+  std::memset(&aa, 0, sizeof(aa));
+  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
+  aa.rate_map = rate_map; aa.yq_out = yq_out; aa.rpart = W + P.rpart;
+  if ((rc = fork_to(sd, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
   if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
   sa.img = img;
@@ -221,11 +274,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   sa.spart = W + P.spart;
   if ((rc = launch((const void*)t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, (const void*)resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
-  ArmArgs aa;
-  std::memset(&aa, 0, sizeof(aa));
-  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
-  aa.rate_map = rate_map; aa.yq_out = yq_out; aa.rpart = W + P.rpart;
-  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, st))) return rc;
+  if ((rc = join_from(sd, st))) return rc;
   FinalArgs fa;
   std::memset(&fa, 0, sizeof(fa));
   fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
@@ -252,7 +301,17 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   float* W = (float*)ws;
   const int L = P.geo.L;
   const float HW = (float)p->H * p->W;
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side* sd = nullptr;
+  if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
+  ArmArgs aa;
+  std::memset(&aa, 0, sizeof(aa));
+  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
+  aa.scale = dloss * p->lambda / HW;
+  aa.gext = W + P.gext; aa.wpart = W + P.wpart_arm; aa.rpart = W + P.rpart;
+  if ((rc = fork_to(sd, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
   if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
   sa.img = img;
@@ -272,33 +331,32 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
     ua.g_y = g_y + P.geo.loff[s + 1];
     ua.g_out = (s + 1 <= L - 2) ? W + P.gb[s + 1] : nullptr;
     ua.part = W + P.upart[s];
-    if ((rc = launch((const void*)ups_bwd_kernel, P.ups_grid[s], 256, &ua, st))) return rc;
+    {
+      void* argv[] = {&ua};
+      if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], L - 1 - s), dim3(256), argv, 0, st) !=
+          hipSuccess)
+        return CC_EHIP;
+    }
   }
-  ArmArgs aa;
-  std::memset(&aa, 0, sizeof(aa));
-  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
-  aa.scale = dloss * p->lambda / HW;
-  aa.gext = W + P.gext; aa.wpart = W + P.wpart_arm; aa.rpart = W + P.rpart;
-  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, st))) return rc;
-  ReduceArgs ra;
-  std::memset(&ra, 0, sizeof(ra));
-  int ns = 0, col = 0;
-  auto add = [&](const float* src, int rows, int cols, float* dst) {
-    ra.seg[ns] = RedSeg{src, rows, cols, cols, dst};
-    ra.col_start[ns] = col;
-    col += cols;
+  if ((rc = join_from(sd, st))) return rc;
+  CombineArgs ca;
+  std::memset(&ca, 0, sizeof(ca));
+  int ns = 0, blk = 0;
+  auto add = [&](const float* src, int rows, int cols, int cpb, float* dst) {
+    ca.seg[ns] = RedSeg{src, rows, cols, cols, cpb, dst};
+    ca.block_start[ns] = blk;
+    blk += cdiv(cols, cpb);
     ++ns;
   };
-  add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, g_arm);
-  for (int s = 0; s + 1 < L; ++s) add(W + P.upart[s], P.ups_grid[s], 2 * UPS_K, g_ups + (size_t)s * 2 * UPS_K);
-  add(W + P.wpart_syn, P.syn_grid, (int)P.n_syn, g_syn);
-  ra.nseg = ns;
-  ra.col_start[ns] = col;
-  ra.flags = W + P.flags;
-  if ((rc = launch((const void*)reduce_cols_kernel, P.red_grid, 256, &ra, st))) return rc;
-  FoldArgs fo;
-  fo.geo = P.geo; fo.tiles = P.tiles; fo.gext = W + P.gext; fo.g_y = g_y; fo.flags = W + P.flags + P.red_grid;
-  if ((rc = launch((const void*)arm_fold_kernel, P.fold_grid, 256, &fo, st))) return rc;
+  add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 16, g_arm);
+  for (int s = 0; s + 1 < L; ++s)
+    add(W + P.upart[s], P.ups_grid[s] * (L - 1 - s), 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
+  add(W + P.wpart_syn, P.syn_grid, (int)P.n_syn, 16, g_syn);
+  ca.nseg = ns;
+  ca.block_start[ns] = blk;
+  ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
+  ca.flags = W + P.flags;
+  if ((rc = launch((const void*)combine_kernel, blk + P.fold_grid, 256, &ca, st))) return rc;
   FinalArgs fa;
   std::memset(&fa, 0, sizeof(fa));
   fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
@@ -339,14 +397,11 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
     return CC_EINVAL;
   AdamArgs a{theta, grad, m, v, n, step, lr, beta1, beta2, eps};
   const int64_t blocks = (n + 255) / 256;
-  const int grid = (int)std::min<int64_t>(blocks, 1024);
+  const int grid = (int)std::min<int64_t>(blocks, 256);
   (void)hipGetLastError();
   int rc = launch((const void*)adam_kernel, grid, 256, &a, (hipStream_t)stream);
   if (rc) return rc;
-  void* sp = step;
-  void* argv[] = {&sp};
-  if (hipLaunchKernel((const void*)adam_advance_kernel, dim3(1), dim3(64), argv, 0, (hipStream_t)stream) != hipSuccess)
-    return CC_EHIP;
+
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 

@@ -271,39 +271,6 @@ __global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
   }
 }
 
-// g_y[q] += sum of the extended-frame gradients of every ARM tile whose frame
-// contains latent q (own tile, left / right neighbours, and the three tiles of
-// the next tile row), in fixed order; also flags non-finite results.
-__global__ __launch_bounds__(256) void arm_fold_kernel(FoldArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  bool bad = false;
-  if (q < a.geo.n_lat) {
-    int l = 0;
-    while (l + 1 < a.geo.L && q >= a.geo.loff[l + 1]) ++l;
-    const int wl = a.geo.lw[l], local = q - a.geo.loff[l];
-    const int i = local / wl, j = local % wl;
-    const int ti = i / ARM_TH, tj = j / ARM_TW;
-    float G = 0.0f;
-    for (int da = 0; da <= 1; ++da) {
-      const int ta = ti + da;
-      if (ta >= a.tiles.nth[l]) continue;
-      for (int db = -1; db <= 1; ++db) {
-        const int tb = tj + db;
-        if (tb < 0 || tb >= a.tiles.ntw[l]) continue;
-        const int fa = i - (ta * ARM_TH - 3), fb = j - (tb * ARM_TW - 3);
-        if (fa < 0 || fa >= ARM_EH || fb < 0 || fb >= ARM_EW) continue;
-        const int tile = a.tiles.base[l] + ta * a.tiles.ntw[l] + tb;
-        G += a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb];
-      }
-    }
-    const float v = a.g_y[q] + G;
-    a.g_y[q] = v;
-    bad = !finitef(v);
-  }
-  const bool any = __syncthreads_or(bad);
-  if (threadIdx.x == 0) a.flags[blockIdx.x] = any ? 1.0f : 0.0f;
-}
-
 // ---- instantiation table
 template <bool BWD>
 static ArmKernelFn pick(int C, int NH) {

@@ -41,20 +41,17 @@ struct FoldArgs {
   ArmTiles tiles;
   const float* gext;
   float* g_y;
-  float* flags;        // [gridDim] 1 if any result of the block is not finite
 };
-__global__ void arm_fold_kernel(FoldArgs a);
+
 
 // ---------------------------------------------------------------- upsampling
 struct UpsFwdArgs {
   Geo geo;
-  int s;               // step: produces U_s(stack_{s+1}) at level s
   const float* y;
   const float* u;
   int quant;
-  const float* taps;   // [2][K] taps of step s
-  const float* up_in;  // U_{s+1} output (channels 1.. of stack_{s+1}); null when s = L-2
-  float* up_out;       // [(L-1-s)][h_s][w_s]
+  const float* ups_w;          // [L-1][2][K] all taps
+  float* up_out[MAXL];         // U_s output [(L-1-s)][h_s][w_s] for s = 1..L-2
 };
 __global__ void ups_fwd_kernel(UpsFwdArgs a);
 
@@ -106,19 +103,23 @@ SynKernelFn syn_bwd_kernel_for(int Hs, int nres);
 
 // ---------------------------------------------------------------- reductions, optimiser
 constexpr int RED_MAXSEG = 12;
-constexpr int RED_COLS = 16, RED_RG = 16;  // columns per block, row groups per column
 struct RedSeg {
   const float* src;    // [rows][ld]
   int rows, cols, ld;
+  int cpb;             // columns per block: 16 (16 row groups) or 1 (256 row groups)
   float* dst;          // [cols]
 };
-struct ReduceArgs {
+// One launch does two independent jobs: blocks [0, n_red) sum partial
+// matrices column by column (segments in order), blocks [n_red, n_red +
+// fold blocks) fold the ARM context gradients into g_y.
+struct CombineArgs {
   RedSeg seg[RED_MAXSEG];
   int nseg;
-  int col_start[RED_MAXSEG + 1];
-  float* flags;        // [gridDim]
+  int block_start[RED_MAXSEG + 1];
+  FoldArgs fold;
+  float* flags;        // [gridDim] 1 if any result of the block is not finite
 };
-__global__ void reduce_cols_kernel(ReduceArgs a);
+__global__ void combine_kernel(CombineArgs a);
 
 struct FinalArgs {
   const float* rpart; int nr;    // rate partials (bits)
@@ -140,6 +141,5 @@ struct AdamArgs {
   float lr, beta1, beta2, eps;
 };
 __global__ void adam_kernel(AdamArgs a);
-__global__ void adam_advance_kernel(int32_t* step);
 
 }  // namespace cc

@@ -6,29 +6,66 @@
 
 namespace cc {
 
-// Column sums of several [rows][ld] partial matrices: 16 columns per block,
-// 16 row groups per column combined in fixed order.
-__global__ __launch_bounds__(256) void reduce_cols_kernel(ReduceArgs a) {
-  __shared__ float s_p[RED_RG][RED_COLS];
-  const int tid = threadIdx.x, cl = tid % RED_COLS, rg = tid / RED_COLS;
-  const int gc = blockIdx.x * RED_COLS + cl;
-  int sg = -1;
-  for (int k = 0; k < a.nseg; ++k)
-    if (gc >= a.col_start[k] && gc < a.col_start[k + 1]) sg = k;
-  float acc = 0.0f;
-  if (sg >= 0) {
-    const RedSeg& S = a.seg[sg];
-    const int col = gc - a.col_start[sg];
-    for (int r = rg; r < S.rows; r += RED_RG) acc += S.src[(size_t)r * S.ld + col];
+// g_y[q] += sum of the extended-frame gradients of every ARM tile whose frame
+// contains latent q (own tile, left / right neighbours, and the three tiles of
+// the next tile row), in fixed order.
+__device__ bool arm_fold_one(const FoldArgs& a, int q) {
+  if (q >= a.geo.n_lat) return true;
+  int l = 0;
+  while (l + 1 < a.geo.L && q >= a.geo.loff[l + 1]) ++l;
+  const int wl = a.geo.lw[l], local = q - a.geo.loff[l];
+  const int i = local / wl, j = local % wl;
+  const int ti = i / ARM_TH, tj = j / ARM_TW;
+  float G = 0.0f;
+  for (int da = 0; da <= 1; ++da) {
+    const int ta = ti + da;
+    if (ta >= a.tiles.nth[l]) continue;
+    for (int db = -1; db <= 1; ++db) {
+      const int tb = tj + db;
+      if (tb < 0 || tb >= a.tiles.ntw[l]) continue;
+      const int fa = i - (ta * ARM_TH - 3), fb = j - (tb * ARM_TW - 3);
+      if (fa < 0 || fa >= ARM_EH || fb < 0 || fb >= ARM_EW) continue;
+      const int tile = a.tiles.base[l] + ta * a.tiles.ntw[l] + tb;
+      G += a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb];
+    }
   }
-  s_p[rg][cl] = acc;
-  __syncthreads();
+  const float v = a.g_y[q] + G;
+  a.g_y[q] = v;
+  return finitef(v);
+}
+
+// Column sums of [rows][ld] partial matrices, and the ARM fold (see
+// CombineArgs).  A reduction block owns cpb columns of one segment; its
+// 256 / cpb row groups each sum a strided set of rows, then a fixed-order
+// tree combines the row groups.
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
+  __shared__ float s_p[256];
+  const int tid = threadIdx.x;
+  const int n_red = a.block_start[a.nseg];
   bool bad = false;
-  if (rg == 0 && sg >= 0) {
-    float v = 0.0f;
-    for (int k = 0; k < RED_RG; ++k) v += s_p[k][cl];
-    a.seg[sg].dst[gc - a.col_start[sg]] = v;
-    bad = !finitef(v);
+  if ((int)blockIdx.x >= n_red) {
+    bad = !arm_fold_one(a.fold, ((int)blockIdx.x - n_red) * 256 + tid);
+  } else {
+    int sg = 0;
+    while (sg + 1 < a.nseg && (int)blockIdx.x >= a.block_start[sg + 1]) ++sg;
+    const RedSeg& S = a.seg[sg];
+    const int cpb = S.cpb, ngroups = 256 / cpb;
+    const int cl = tid % cpb, rg = tid / cpb;
+    const int col = ((int)blockIdx.x - a.block_start[sg]) * cpb + cl;
+    float acc = 0.0f;
+    if (col < S.cols)
+      for (int r = rg; r < S.rows; r += ngroups) acc += S.src[(size_t)r * S.ld + col];
+    s_p[tid] = acc;
+    __syncthreads();
+    for (int stride = ngroups / 2; stride >= 1; stride >>= 1) {
+      if (rg < stride) s_p[tid] += s_p[tid + stride * cpb];
+      __syncthreads();
+    }
+    if (rg == 0 && col < S.cols) {
+      const float v = s_p[cl];
+      S.dst[col] = v;
+      bad = !finitef(v);
+    }
   }
   const bool any = __syncthreads_or(bad);
   if (tid == 0) a.flags[blockIdx.x] = any ? 1.0f : 0.0f;
@@ -65,7 +102,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) {
   }
 }
 
-// Adam (Kingma & Ba) with bias correction; t = step[0] + 1.
+// Adam (Kingma & Ba) with bias correction; t = step[0] + 1.  Every block reads
+// step[0] before it adds itself to the completion counter step[1]; the block
+// that completes the count advances step[0] and clears the counter, so the
+// next launch sees the new step.
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const int t = a.step[0] + 1;
   const float bc1 = 1.0f - powf(a.beta1, (float)t);
@@ -79,11 +119,13 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
     a.v[i] = v;
     a.theta[i] -= a.lr * (m * k1) / (sqrtf(v * k2) + a.eps);
   }
-}
-
-// Advances the step counter after the update kernel has read it.
-__global__ void adam_advance_kernel(int32_t* step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(&a.step[1], 1);  // after this block's read of step[0] (t is used above)
+    if (prev == (int)gridDim.x - 1) {
+      atomicExch(&a.step[0], t);
+      atomicExch(&a.step[1], 0);
+    }
+  }
 }
 
 }  // namespace cc

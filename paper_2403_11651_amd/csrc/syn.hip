@@ -474,6 +474,7 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
       asm volatile("" : "+s"(wz));
       const f32x4* W1q = reinterpret_cast<const f32x4*>(&sw.W1p[0][0]) + wz;
       const f32x4* W2q = reinterpret_cast<const f32x4*>(&sw.W2t[0][0]) + wz;
+      uint32_t pmask[(HS + 31) / 32] = {};  // signs of the first layer's pre-activations
       // (a) W2, b2 from (g_pre_t, [a, 1]), one staged row per pixel
       {
         float* X2 = P6;
@@ -486,6 +487,7 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
           const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] +
                             w1.y * zz[5] + w1.z * zz[6] + w1.w * zz[7];
           Y2[lane * LY2 + f] = fmaxf(pre, 0.0f);
+          if (pre > 0.0f) pmask[f >> 5] |= 1u << (f & 31);
         }
         Y2[lane * LY2 + HS] = own ? 1.0f : 0.0f;
         wave_lds_sync();
@@ -507,11 +509,9 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
 #pragma unroll 4
         for (int f = 0; f < HS; ++f) {
           const f32x4 w0 = W1q[2 * f], w1 = W1q[2 * f + 1];
-          const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] +
-                            w1.y * zz[5] + w1.z * zz[6] + w1.w * zz[7];
           const f32x4 w2 = W2q[f];
           float g = w2.x * gpt[0] + w2.y * gpt[1] + w2.z * gpt[2];
-          g = pre > 0.0f ? g : 0.0f;
+          g = ((pmask[f >> 5] >> (f & 31)) & 1u) ? g : 0.0f;
           X1[lane * LX1 + f] = g;
           gz[0] += w0.x * g; gz[1] += w0.y * g; gz[2] += w0.z * g; gz[3] += w0.w * g;
           gz[4] += w1.x * g; gz[5] += w1.y * g; gz[6] += w1.z * g;

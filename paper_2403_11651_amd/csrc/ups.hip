@@ -14,49 +14,88 @@
 
 namespace cc {
 
+// All steps s = L-2 .. 1 in one launch.  A work-group owns a UF_T x UF_T tile
+// of level 1 and works from the coarsest level down: the region of
+// stack_{s+1} that U_s needs for the rows / columns [a, b) of level s is
+// [a/2 - 2, (b-1)/2 + 3) clipped to the grid (every clamped tap index falls in
+// it; at most 20 rows / columns for levels >= 2), so each work-group
+// recomputes, in LDS, the small coarse regions its tile depends on.  U_1 is
+// written for the tile; for s >= 2 the work-group writes the part of U_s that
+// lies under its tile, so every output is written exactly once.
+constexpr int UF_T = 32;       // level-1 tile side
+constexpr int UF_R = 20;       // largest region side at levels >= 2
+constexpr int UF_CH = MAXL - 1;  // channels of stack_2 at most (L - 2 < 6)
+
 __global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) {
-  const int s = a.s, L = a.geo.L;
-  const int h = a.geo.lh[s], w = a.geo.lw[s], hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1];
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= h * w) return;
-  const int i = idx / w, j = idx % w;
-  int ro[4], co[4];
-  float vt[4], ht[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ky = 2 * q + 1 - (i & 1), kx = 2 * q + 1 - (j & 1);
-    ro[q] = clampi((i + UPS_P - ky) >> 1, 0, hi - 1);
-    co[q] = clampi((j + UPS_P - kx) >> 1, 0, wi - 1);
-    vt[q] = a.taps[ky];
-    ht[q] = a.taps[UPS_K + kx];
+  __shared__ float s_st[2][UF_CH * UF_R * UF_R];
+  const int L = a.geo.L, tid = threadIdx.x;
+  const int h1 = a.geo.lh[1], w1 = a.geo.lw[1];
+  const int ntx = (w1 + UF_T - 1) / UF_T;
+  const int r0 = (blockIdx.x / ntx) * UF_T, c0 = (blockIdx.x % ntx) * UF_T;
+  // regions [ra, rb) x [ca, cb) per level
+  int ra[MAXL], rb[MAXL], ca[MAXL], cb[MAXL];
+  ra[1] = r0; rb[1] = min(r0 + UF_T, h1); ca[1] = c0; cb[1] = min(c0 + UF_T, w1);
+  for (int l = 1; l + 1 < L; ++l) {
+    ra[l + 1] = max(0, (ra[l] >> 1) - 2); rb[l + 1] = min(a.geo.lh[l + 1], ((rb[l] - 1) >> 1) + 3);
+    ca[l + 1] = max(0, (ca[l] >> 1) - 2); cb[l + 1] = min(a.geo.lw[l + 1], ((cb[l] - 1) >> 1) + 3);
   }
-  const int nch = L - 1 - s;  // channels of stack_{s+1}
-  const int lo = a.geo.loff[s + 1];
-  float acc = 0.0f;
-#pragma unroll
-  for (int q1 = 0; q1 < 4; ++q1) {
-    float ra = 0.0f;
-#pragma unroll
-    for (int q2 = 0; q2 < 4; ++q2) ra += ht[q2] * quantise(a.y, a.u, lo + ro[q1] * wi + co[q2], a.quant);
-    acc += vt[q1] * ra;
-  }
-  a.up_out[idx] = acc;
-  for (int c = 1; c < nch; ++c) {
-    const float* in = a.up_in + (size_t)(c - 1) * hi * wi;
-    float acc2 = 0.0f;
-#pragma unroll
-    for (int q1 = 0; q1 < 4; ++q1) {
-      float ra = 0.0f;
-#pragma unroll
-      for (int q2 = 0; q2 < 4; ++q2) ra += ht[q2] * in[ro[q1] * wi + co[q2]];
-      acc2 += vt[q1] * ra;
+  // stack_{L-1} = y_hat_{L-1} on its region
+  {
+    const int l = L - 1, nr = rb[l] - ra[l], nc = cb[l] - ca[l];
+    float* dst = s_st[l & 1];
+    for (int p = tid; p < nr * nc; p += 256) {
+      const int i = ra[l] + p / nc, j = ca[l] + p % nc;
+      dst[p] = quantise(a.y, a.u, a.geo.loff[l] + i * a.geo.lw[l] + j, a.quant);
     }
-    a.up_out[(size_t)c * h * w + idx] = acc2;
+  }
+  __syncthreads();
+  for (int s = L - 2; s >= 1; --s) {
+    const float* src = s_st[(s + 1) & 1];
+    float* dst = s_st[s & 1];
+    const float* taps = a.ups_w + (size_t)s * 2 * UPS_K;
+    const int nci = L - 1 - s;  // channels of stack_{s+1}
+    const int sr = rb[s + 1] - ra[s + 1], sc = cb[s + 1] - ca[s + 1];
+    const int nr = rb[s] - ra[s], nc = cb[s] - ca[s];
+    const int hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1], ws = a.geo.lw[s];
+    // the part of level s under this tile (written to global for s >= 2)
+    const int oa = r0 >> (s - 1), ob = min((r0 + UF_T) >> (s - 1), a.geo.lh[s]);
+    const int oc = c0 >> (s - 1), od = min((c0 + UF_T) >> (s - 1), ws);
+    float* up = a.up_out[s];
+    const size_t plane = (size_t)a.geo.lh[s] * ws;
+    for (int p = tid; p < nr * nc; p += 256) {
+      const int i = ra[s] + p / nc, j = ca[s] + p % nc;
+      int ro[4], co[4];
+      float vt[4], ht[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ky = 2 * q + 1 - (i & 1), kx = 2 * q + 1 - (j & 1);
+        ro[q] = clampi((i + UPS_P - ky) >> 1, 0, hi - 1) - ra[s + 1];
+        co[q] = clampi((j + UPS_P - kx) >> 1, 0, wi - 1) - ca[s + 1];
+        vt[q] = taps[ky];
+        ht[q] = taps[UPS_K + kx];
+      }
+      const bool owned = s == 1 || (i >= oa && i < ob && j >= oc && j < od);
+      if (s > 1) dst[p] = quantise(a.y, a.u, a.geo.loff[s] + i * ws + j, a.quant);  // channel 0 = y_hat_s
+      for (int c = 0; c < nci; ++c) {
+        const float* in = src + c * sr * sc;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q1 = 0; q1 < 4; ++q1) {
+          float rr = 0.0f;
+#pragma unroll
+          for (int q2 = 0; q2 < 4; ++q2) rr += ht[q2] * in[ro[q1] * sc + co[q2]];
+          acc += vt[q1] * rr;
+        }
+        if (s > 1) dst[(c + 1) * nr * nc + p] = acc;
+        if (owned) up[c * plane + i * ws + j] = acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
 // Adjoint of step s.  One work-group per UT x UT tile of input positions
-// (level s+1), one thread per position, channels in turn.  With padded input
+// (level s+1) and channel, one thread per position.  With padded input
 // indices m' (before clamping), the transpose of the clamped gather is
 //   g_pad[m'_r][m'_c] = sum_{ky, kx} v[ky] h[kx] g_out[2m'_r+ky-3][2m'_c+kx-3]
 // (outputs outside the level-s grid are zero), and an input takes the sum of
@@ -79,9 +118,9 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   const int ho = a.geo.lh[s], wo = a.geo.lw[s], hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1];
   const int ntx = (wi + UT - 1) / UT;
   const int r0 = (blockIdx.x / ntx) * UT, c0 = (blockIdx.x % ntx) * UT;
+  const int ch = blockIdx.y;  // channel of stack_{s+1} handled by this work-group
   const int tr = tid / UT, tc = tid % UT, r = r0 + tr, c = c0 + tc;
   const bool in_tile = r < hi && c < wi;
-  const int nch = L - 1 - s;
   float v[UPS_K], hh[UPS_K], gv[UPS_K], gh[UPS_K];
 #pragma unroll
   for (int k = 0; k < UPS_K; ++k) {
@@ -98,7 +137,8 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   cb[3] = c == wi - 1 ? tc + 3 : -1; cb[4] = c == wi - 1 ? tc + 4 : -1;
   const int jr0 = 2 * r0 - 7, jc0 = 2 * c0 - 7;
   const int lo = a.geo.loff[s + 1];
-  for (int ch = 0; ch < nch; ++ch) {
+  (void)L;
+  {
     const float* gin = a.g_in + (size_t)ch * ho * wo;
     for (int p = tid; p < UR_N * UR_N; p += 256) {
       const int jr = jr0 + p / UR_N, jc = jc0 + p % UR_N;
@@ -164,7 +204,7 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   if (tid < 2 * UPS_K) {
     float acc = 0.0f;
     for (int wv = 0; wv < 4; ++wv) acc += s_red[wv][tid];
-    a.part[blockIdx.x * 2 * UPS_K + tid] = acc;
+    a.part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2 * UPS_K + tid] = acc;
   }
 }
 
