@@ -89,6 +89,75 @@ def make_inputs(arch, H=512, W=768):
     return img, y, w[:na], w[na:na + nu], w[na + nu:]
 
 
+BATCH_ARCH = (7, 8, 2, 8, 16, 1)
+BATCH_DESC = ("32 images, sizes drawn uniformly from 256x256 .. 1024x768 in steps of 64 (seed 999), each with its "
+              "own 7-level Laplace latent pyramid and its own low-complexity decoder (ARM 8-8-8-2, synthesis "
+              "7-16-3 + 1 residual 3x3 conv); blob count 200 per 768x512 of area; lambda 1e-3; Adam lr 1e-2")
+
+
+def batch_inputs(B, n=32):
+    """The batched-overfitting workload: problems, images, initial latents and
+    initial (arm, ups, syn) parameters of each image."""
+    from paper_2403_11651_amd import workloads as WL
+    L, C, NH, K, Hs, R = BATCH_ARCH
+    na = NH * (C * C + C) + 2 * C + 2
+    nu = (L - 1) * 2 * K
+    ns = Hs * L + Hs + 3 * Hs + 3 + R * 84
+    probs, images, y0, params0 = [], [], [], []
+    for k, (H, W) in enumerate(WL.batch_sizes(999, n)):
+        probs.append(B.Problem(H, W, B.Arch(*BATCH_ARCH), B.CC_QUANT_ROUND, 1e-3))
+        images.append(WL.image(1000 + k, H, W, max(1, round(200 * H * W / (768 * 512)))))
+        y0.append(WL.latents(2000 + k, H, W, L))
+        w = WL.weights(3000 + k, na + nu + ns)
+        params0.append((w[:na], w[na:na + nu], w[na + nu:]))
+    return probs, images, y0, params0
+
+
+def run_batched(B, iters, graph_steps=50, log=None):
+    """Overfits the 32-image batch for `iters` iterations (autotuned launch
+    shape, graph replays of graph_steps iterations); returns the record."""
+    import torch
+    from paper_2403_11651_amd import batch as BT
+    if iters % graph_steps:
+        raise ValueError("--batch-iters must be a multiple of the graph length")
+    probs, images, y0, params0 = batch_inputs(B)
+    enc = BT.BatchEncoder(probs, images, y0, params0)
+    t0 = time.perf_counter()
+    tuned = BT.autotune(enc, log=log)
+    tune_s = time.perf_counter() - t0
+    enc.backward()
+    torch.cuda.synchronize()
+    loss0 = enc.loss.cpu().numpy().copy()
+    t0 = time.perf_counter()
+    g = enc.capture(graph_steps)
+    capture_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for r in range(iters // graph_steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1000.0
+    enc.backward()  # the loss of the final parameters
+    torch.cuda.synchronize()
+    l4 = enc.loss.cpu().numpy()
+    if np.any(l4[:, 3] != 0.0) or not np.all(np.isfinite(l4[:, 0])):
+        raise RuntimeError(f"non-finite loss in the batched run: {l4}")
+    px = sum(p.H * p.W for p in probs)
+    return {"workload": BATCH_DESC, "images": len(probs), "pixels": px, "iterations": iters,
+            "seconds": round(secs, 4), "images_per_s": round(len(probs) / secs, 4),
+            "ms_per_iteration": round(1000.0 * secs / iters, 5),
+            "mpix_iters_per_s": round(px * iters / secs / 1e6, 1),
+            "tuning": {"arm_blocks": tuned["tune"][0], "syn_blocks": tuned["tune"][1], "cached": tuned["cached"],
+                       "tune_s": round(tune_s, 2), "candidates_ms": tuned.get("timings")},
+            "graph_steps": graph_steps, "capture_s": round(capture_s, 4),
+            "loss_start_mean": float(loss0[:, 0].mean()), "loss_end_mean": float(l4[:, 0].mean()),
+            "psnr_end_mean_db": float(np.mean(10.0 * np.log10(1.0 / l4[:, 1]))),
+            "rate_end_bpp_mean": float(np.mean(l4[:, 2] / np.array([p.H * p.W for p in probs])))}
+
+
 def cpu_baseline(arch, budget_s=20.0):
     """The FP64 oracle, single-threaded, timed on full 768x512 iterations
     (forward + backward + Adam) until about budget_s seconds have passed."""
@@ -134,6 +203,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--batch-iters", type=int, default=2000,
+                    help="iterations of the 32-image batched overfitting run (0 skips it)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size reference for "
                          "the FETCH_SIZE / WRITE_SIZE hardware counters); not part of any timed step")
@@ -253,6 +324,9 @@ def main():
                  "loss_after_warmup": float(loss_start[0]), "loss_end": float(l4[0]),
                  "wall_s": round(t_wall, 3)},
     }
+    if args.batch_iters > 0:
+        out["batched"] = run_batched(B, args.batch_iters,
+                                     log=lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(arch, args.cpu_budget)
     print(json.dumps(out), flush=True)

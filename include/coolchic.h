@@ -148,6 +148,59 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
 enum { CC_STAGE_NONE = 0, CC_STAGE_ARM = 1, CC_STAGE_SYNTHESIS = 2 };
 int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end);
 
+/* ---- Batched overfitting: many images of uneven sizes in one launch per
+   stage.  Every image has its own latents, parameters and outputs; all share
+   one architecture (and quantiser).  coolchic_batch_create lays out, in the
+   caller's device workspace, one backward workspace per image, the argument
+   blocks of every kernel for every image, and the work-lists that map each
+   work-group of a batched launch to (image, block); it uploads them with a
+   synchronous copy (setup, not the hot path).  coolchic_batch_backward then
+   runs the backward pass of all images (the same results as one
+   coolchic_backward call per image) with one launch per stage, so a whole
+   training iteration of the batch is a dozen launches and can be captured in
+   a HIP graph. */
+typedef struct {
+  const float* img;    /* [3][H][W] */
+  const float* y;      /* [N_lat] */
+  const float* u;      /* [N_lat] for CC_QUANT_NOISE, else NULL */
+  const float* arm_w;
+  const float* ups_w;
+  const float* syn_w;
+  float* loss4;        /* [4] as in coolchic_backward */
+  float* g_y;
+  float* g_arm;
+  float* g_ups;
+  float* g_syn;
+} cc_image_io;
+
+/* Launch shape of the persistent kernels (tuned by the caller): total
+   work-groups of the ARM launch and of the synthesis-backward launch, split
+   over the images in proportion to their tiles.  0 selects, per image, the
+   grid coolchic_backward uses (then the results are bit-identical to it). */
+typedef struct {
+  int32_t arm_blocks;
+  int32_t syn_blocks;
+} cc_batch_tuning;
+
+typedef struct cc_batch cc_batch; /* opaque host-side plan */
+
+/* Device workspace bytes for a batch of n problems (host arrays); 0 if any
+   problem is invalid or the architectures differ.  tune may be NULL. */
+size_t coolchic_batch_workspace_bytes(int32_t n, const cc_problem* probs, const cc_batch_tuning* tune);
+
+/* Builds the plan; probs and io are host arrays of n entries (io holds device
+   pointers, which must stay valid while the plan is used); dloss is the
+   gradient scale of every image's loss.  *out receives a host object to free
+   with coolchic_batch_destroy (NULL on any error).  Synchronises the device
+   (setup call). */
+int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io* io, const cc_batch_tuning* tune,
+                          float dloss, void* ws, size_t ws_bytes, cc_batch** out);
+
+/* Enqueues the backward pass of every image of the batch on stream. */
+int coolchic_batch_backward(const cc_batch* batch, void* stream);
+
+void coolchic_batch_destroy(cc_batch* batch);
+
 /* Static description of an error code. */
 const char* coolchic_strerror(int code);
 

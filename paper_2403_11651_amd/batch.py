@@ -1,0 +1,232 @@
+"""Batched overfitting: many images of uneven sizes trained together.
+
+Every image keeps its own latent pyramid and its own ARM / upsampling /
+synthesis parameters (Section III: each image gets its own overfitted
+decoder); they share only the architecture.  One training iteration of the
+whole batch is the batched backward pass of the HIP library (one launch per
+stage for all images) plus one Adam launch over the parameters of every
+image, so a block of iterations is captured once in a HIP graph and replayed.
+
+The persistent kernels' launch shapes (work-groups of the ARM and of the
+synthesis-backward launch, spread over the images in proportion to their
+tiles) are picked by `autotune`, which times candidates on the device and
+caches the choice per device, architecture and image-size list.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import threading
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class BatchEncoder:
+    """Overfits n images at once (quantiser: rounding with straight-through
+    gradient).  `images[k]` is planar [3][H][W] float32; `y0[k]` the packed
+    initial latent pyramid; `params0[k]` the initial (arm, ups, syn) blocks.
+
+    Parameters of image k live in one flat buffer, segment k = [y | arm | ups |
+    syn], with matching gradient and Adam moment buffers, so a single Adam
+    launch updates every image."""
+
+    def __init__(self, problems, images, y0, params0, lr=1e-2, tune=(0, 0), device="cuda"):
+        n = len(problems)
+        if not (n and len(images) == n and len(y0) == n and len(params0) == n):
+            raise ValueError("problems, images, y0 and params0 must be equally long and non-empty")
+        arch = problems[0].arch
+        for p in problems:
+            if p.arch != arch or p.quant != B.CC_QUANT_ROUND:
+                raise ValueError("every image must share one architecture and use the rounding quantiser")
+        self.device = torch.device(device)
+        self.problems = list(problems)
+        self.lr = float(lr)
+        na, nu, ns = B.param_count(arch)
+        self.seg = []  # (offset, n_lat) per image
+        off = 0
+        for p in problems:
+            n_lat = B.latent_count(p)
+            self.seg.append((off, n_lat))
+            off += n_lat + na + nu + ns
+        self.n_params = off
+        flat = np.empty(off, np.float32)
+        for (o, n_lat), y, (a, u, s) in zip(self.seg, y0, params0):
+            flat[o:o + n_lat] = y
+            flat[o + n_lat:o + n_lat + na] = a
+            flat[o + n_lat + na:o + n_lat + na + nu] = u
+            flat[o + n_lat + na + nu:o + n_lat + na + nu + ns] = s
+        dev = self.device
+        self.theta = torch.from_numpy(flat).to(dev)
+        self.grad = torch.zeros_like(self.theta)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.step_ctr = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros(n, 4, device=dev)
+        self.images = [torch.from_numpy(np.ascontiguousarray(x, np.float32).reshape(-1)).to(dev) for x in images]
+        self._na, self._nu, self._ns = na, nu, ns
+        self.plan = None
+        self.set_tuning(tune)
+
+    # -- views of image k's parameters and gradients
+    def _views(self, buf, k):
+        o, n_lat = self.seg[k]
+        na, nu, ns = self._na, self._nu, self._ns
+        return (buf[o:o + n_lat], buf[o + n_lat:o + n_lat + na], buf[o + n_lat + na:o + n_lat + na + nu],
+                buf[o + n_lat + na + nu:o + n_lat + na + nu + ns])
+
+    def params(self, k):
+        return tuple(t.detach().cpu().numpy() for t in self._views(self.theta, k))
+
+    def grads(self, k):
+        return tuple(t.detach().cpu().numpy() for t in self._views(self.grad, k))
+
+    def set_tuning(self, tune):
+        io = []
+        for k in range(len(self.problems)):
+            y, a, u, s = self._views(self.theta, k)
+            gy, ga, gu, gs = self._views(self.grad, k)
+            io.append(dict(img=self.images[k], y=y, u=None, arm_w=a, ups_w=u, syn_w=s, loss4=self.loss[k],
+                           g_y=gy, g_arm=ga, g_ups=gu, g_syn=gs))
+        if self.plan is not None:
+            self.plan.close()
+        self.plan = B.BatchPlan(self.problems, io, tune=tune, device=self.device)
+        self.tune = self.plan.tune
+
+    def backward(self, stream=None):
+        """Loss and gradients of every image (written to self.loss, self.grad)."""
+        self.plan.backward(stream)
+
+    def step(self, stream=None):
+        """One training iteration of every image."""
+        self.plan.backward(stream)
+        B.coolchic_adam_step(self.theta, self.grad, self.m, self.v, self.step_ctr, lr=self.lr, stream=stream)
+
+    def capture(self, k):
+        """A HIP graph of k training iterations.  Runs one backward pass first
+        (outside the graph; it leaves the parameters unchanged) so that every
+        stream and event the library uses exists before capture."""
+        self.plan.backward()
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(k):
+                self.step()
+        return g
+
+    def run(self, iters, graph_steps=50):
+        """iters training iterations, replaying a captured graph of
+        graph_steps iterations (the remainder eagerly)."""
+        if iters >= graph_steps > 0:
+            g = self.capture(graph_steps)
+            for _ in range(iters // graph_steps):
+                g.replay()
+            rem = iters % graph_steps
+        else:
+            rem = iters
+        for _ in range(rem):
+            self.step()
+
+    def save(self):
+        return [t.clone() for t in (self.theta, self.m, self.v, self.step_ctr, self.loss)]
+
+    def load(self, state):
+        for dst, src in zip((self.theta, self.m, self.v, self.step_ctr, self.loss), state):
+            dst.copy_(src)
+
+
+# ---- autotuner -----------------------------------------------------------
+
+ARM_CANDIDATES = (0, 512, 1024, 2048, 4096)
+SYN_CANDIDATES = (0, 512, 1024, 2048, 4096)
+_cache_lock = threading.Lock()
+
+
+def cache_path():
+    return os.environ.get("COOLCHIC_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "coolchic", "autotune.json"))
+
+
+def tuning_key(enc: BatchEncoder):
+    a = enc.problems[0].arch
+    sizes = ",".join(f"{p.H}x{p.W}" for p in enc.problems)
+    dev = torch.cuda.get_device_name(enc.device)
+    return f"{dev}|{a.n_levels},{a.arm_ctx},{a.arm_layers},{a.ups_taps},{a.syn_hidden},{a.syn_res}|" \
+           f"{hashlib.sha256(sizes.encode()).hexdigest()[:16]}"
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, key, value):
+    with _cache_lock:
+        data = _load_cache(path)
+        data[key] = value
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = f"{path}.{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        except OSError:
+            pass  # a read-only home: the choice is simply not remembered
+
+
+def time_iteration(enc: BatchEncoder, iters=10, reps=3):
+    """Median device time (ms) of one training iteration, from HIP events
+    around `iters` eager iterations, over `reps` repetitions."""
+    stream = torch.cuda.current_stream(enc.device)
+    enc.step()
+    enc.step()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(iters):
+            enc.step()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1) / iters)
+    return float(np.median(out))
+
+
+def autotune(enc: BatchEncoder, use_cache=True, iters=10, reps=3, log=None):
+    """Chooses (arm_blocks, syn_blocks) for enc by coordinate search over the
+    candidate lists (ARM first, with the default synthesis shape, then the
+    synthesis shape), timing whole training iterations.  The encoder's state
+    is restored afterwards; the choice is applied and returned, with the
+    timings, and cached."""
+    path = cache_path()
+    key = tuning_key(enc)
+    if use_cache:
+        hit = _load_cache(path).get(key)
+        if hit:
+            enc.set_tuning(tuple(hit["tune"]))
+            return dict(hit, cached=True)
+    state = enc.save()
+    timings = {}
+
+    def measure(t):
+        if t not in timings:
+            enc.set_tuning(t)
+            timings[t] = time_iteration(enc, iters, reps)
+            if log:
+                log(f"autotune {t}: {timings[t]:.4f} ms/iter")
+        return timings[t]
+
+    best_a = min(ARM_CANDIDATES, key=lambda a: measure((a, 0)))
+    best = min(((best_a, s) for s in SYN_CANDIDATES), key=measure)
+    enc.load(state)
+    enc.set_tuning(best)
+    result = dict(tune=list(best), ms_per_iter=timings[best],
+                  timings={f"{a},{s}": v for (a, s), v in timings.items()})
+    _store_cache(path, key, result)
+    return dict(result, cached=False)

@@ -22,7 +22,8 @@ CC_WS_FORWARD, CC_WS_BACKWARD, CC_WS_DECODE = 0, 1, 2
 # every symbol the header declares
 EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_bytes", "coolchic_forward",
            "coolchic_backward", "coolchic_decode_synth", "coolchic_adam_step", "coolchic_set_stage_events",
-           "coolchic_strerror")
+           "coolchic_strerror", "coolchic_batch_workspace_bytes", "coolchic_batch_create",
+           "coolchic_batch_backward", "coolchic_batch_destroy")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -34,6 +35,15 @@ class CCArch(ctypes.Structure):
 class CCProblem(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("arch", CCArch), ("quant", ctypes.c_int32),
                 ("lam", ctypes.c_float)]
+
+
+class CCImageIO(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("img", "y", "u", "arm_w", "ups_w", "syn_w", "loss4", "g_y", "g_arm", "g_ups", "g_syn")]
+
+
+class CCBatchTuning(ctypes.Structure):
+    _fields_ = [("arm_blocks", ctypes.c_int32), ("syn_blocks", ctypes.c_int32)]
 
 
 class CoolChicError(RuntimeError):
@@ -59,6 +69,11 @@ def _load():
         "coolchic_adam_step": (I, [P, P, P, P, I64, P, F, F, F, F, P]),
         "coolchic_set_stage_events": (I, [I, P, P]),
         "coolchic_strerror": (ctypes.c_char_p, [I]),
+        "coolchic_batch_workspace_bytes": (SZ, [I, pp, ctypes.POINTER(CCBatchTuning)]),
+        "coolchic_batch_create": (I, [I, pp, ctypes.POINTER(CCImageIO), ctypes.POINTER(CCBatchTuning), F, P, SZ,
+                                      ctypes.POINTER(P)]),
+        "coolchic_batch_backward": (I, [P, P]),
+        "coolchic_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -206,6 +221,55 @@ def coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999,
 def coolchic_set_stage_events(stage: int, ev_begin=None, ev_end=None):
     """ev_begin / ev_end: raw hipEvent_t handles (ints) or None."""
     _check(_lib.coolchic_set_stage_events(int(stage), ev_begin, ev_end), "coolchic_set_stage_events")
+
+
+def batch_workspace_bytes(probs, tune=(0, 0)) -> int:
+    arr = (CCProblem * len(probs))(*[p.c() for p in probs])
+    t = CCBatchTuning(*tune)
+    return int(_lib.coolchic_batch_workspace_bytes(len(probs), arr, ctypes.byref(t)))
+
+
+class BatchPlan:
+    """Owner of a coolchic_batch_create plan.  `io` is a list of dicts with the
+    device tensors of each image (keys of CCImageIO; "u" may be None); the plan
+    keeps references to them and to its workspace so the pointers it holds stay
+    valid."""
+
+    def __init__(self, probs, io, tune=(0, 0), dloss=1.0, device="cuda"):
+        n = len(probs)
+        if n == 0 or len(io) != n:
+            raise ValueError("probs and io must be non-empty lists of equal length")
+        self.probs, self.io, self.tune = list(probs), list(io), tuple(int(t) for t in tune)
+        arr = (CCProblem * n)(*[p.c() for p in probs])
+        ios = (CCImageIO * n)()
+        for k, (p, d) in enumerate(zip(probs, io)):
+            n_lat = latent_count(p)
+            na, nu, ns = param_count(p.arch)
+            sizes = {"img": 3 * p.H * p.W, "y": n_lat, "u": n_lat, "arm_w": na, "ups_w": nu, "syn_w": ns,
+                     "loss4": 4, "g_y": n_lat, "g_arm": na, "g_ups": nu, "g_syn": ns}
+            for name, size in sizes.items():
+                setattr(ios[k], name, _ptr(d.get(name), size, f"io[{k}].{name}"))
+        t = CCBatchTuning(*self.tune)
+        nbytes = int(_lib.coolchic_batch_workspace_bytes(n, arr, ctypes.byref(t)))
+        if nbytes == 0:
+            raise CoolChicError(CC_EINVAL, "coolchic_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        rc = _lib.coolchic_batch_create(n, arr, ios, ctypes.byref(t), float(dloss), self.ws.data_ptr(), nbytes,
+                                        ctypes.byref(h))
+        _check(rc, "coolchic_batch_create")
+        self._h = h
+
+    def backward(self, stream=None):
+        _check(_lib.coolchic_batch_backward(self._h, _stream(stream)), "coolchic_batch_backward")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.coolchic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 # raw access for tests of the C ABI itself

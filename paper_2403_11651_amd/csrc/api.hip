@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <vector>
 
 #include "coolchic.h"
 #include "kernels.hpp"
@@ -68,7 +70,7 @@ size_t take(size_t& cur, size_t n) {
   return at;
 }
 
-int make_plan(const cc_problem* p, int which, Plan* P) {
+int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn_grid = 0) {
   int rc = check_problem(p);
   if (rc) return rc;
   std::memset(P, 0, sizeof(*P));
@@ -95,10 +97,10 @@ int make_plan(const cc_problem* p, int which, Plan* P) {
   }
   t.base[L] = nt;
   t.n_tiles = nt;
-  P->arm_grid = std::min(nt, MAX_GRID);
+  P->arm_grid = arm_grid > 0 ? std::min(arm_grid, nt) : std::min(nt, MAX_GRID);
   P->syn_tiles_x = cdiv(p->W, SYN_T);
   P->syn_tiles = P->syn_tiles_x * cdiv(p->H, SYN_T);
-  P->syn_grid = std::min(P->syn_tiles, MAX_GRID);
+  P->syn_grid = syn_grid > 0 ? std::min(syn_grid, P->syn_tiles) : std::min(P->syn_tiles, MAX_GRID);
   for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);  // tiles
   P->fold_grid = cdiv(g.n_lat, 256);
   // column reductions: 16 columns per block for the wide ARM / synthesis
@@ -184,16 +186,23 @@ int join_from(Side* sd, hipStream_t main) {
 }
 
 // U_s for s = L-2 .. 1 in one launch (stack_1 is then complete for the
-// step s = 0 fused into the synthesis kernels).
-int launch_ups_fwd(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
-                   hipStream_t st) {
+// step s = 0 fused into the synthesis kernels); grid 0 when L < 3.
+UpsFwdArgs ups_fwd_args(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
+                        int* grid) {
   const int L = P.geo.L;
-  if (L < 3) return CC_OK;
   UpsFwdArgs a;
   std::memset(&a, 0, sizeof(a));
   a.geo = P.geo; a.y = y; a.u = u; a.quant = quant; a.ups_w = ups_w;
   for (int s = 1; s + 1 < L; ++s) a.up_out[s] = ws + P.up[s];
-  const int grid = cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+  *grid = L < 3 ? 0 : cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+  return a;
+}
+
+int launch_ups_fwd(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
+                   hipStream_t st) {
+  int grid = 0;
+  UpsFwdArgs a = ups_fwd_args(P, ws, y, u, quant, ups_w, &grid);
+  if (!grid) return CC_OK;
   return launch((const void*)ups_fwd_kernel, grid, 256, &a, st);
 }
 
@@ -252,8 +261,8 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   if (!img || !y || !arm_w || !ups_w || !syn_w || !loss4 || !ws) return CC_EINVAL;
   if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
-  ArmKernelFn armk = arm_kernel_for(P.C, P.NH, false);
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), resk = syn_res_fwd_kernel_for(P.Hs, P.nres);
+  const void* armk = arm_kernel_for(P.C, P.NH, false, false);
+  const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *resk = syn_res_fwd_kernel_for(P.Hs, P.nres, false);
   if (!armk || !t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
@@ -266,14 +275,14 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
   aa.rate_map = rate_map; aa.yq_out = yq_out; aa.rpart = W + P.rpart;
   if ((rc = fork_to(sd, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
   if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
   sa.img = img;
   sa.xhat = xhat_out;
   sa.spart = W + P.spart;
-  if ((rc = launch((const void*)t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_SYNTHESIS, (const void*)resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
+  if ((rc = launch(t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_SYNTHESIS, resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
   if ((rc = join_from(sd, st))) return rc;
   FinalArgs fa;
   std::memset(&fa, 0, sizeof(fa));
@@ -284,46 +293,39 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
-int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
-                      const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
-                      float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream) {
-  Plan P;
-  int rc = make_plan(p, CC_WS_BACKWARD, &P);
-  if (rc) return rc;
-  if (!img || !y || !arm_w || !ups_w || !syn_w || !loss4 || !g_y || !g_arm || !g_ups || !g_syn || !ws)
-    return CC_EINVAL;
-  if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
-  if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
-  ArmKernelFn armk = arm_kernel_for(P.C, P.NH, true);
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), bwk = syn_bwd_kernel_for(P.Hs, P.nres);
-  if (!armk || !t0k || !bwk) return CC_EUNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
-  float* W = (float*)ws;
+// Every argument block of one image's backward pass, and the grids.
+struct BwdSet {
+  ArmArgs arm;
+  UpsFwdArgs upf;
+  SynArgs syn;
+  UpsBwdArgs upb[MAXL];
+  CombineArgs comb;
+  FinalArgs fin;
+  int upf_grid, t0_grid, comb_grid;
+};
+
+void build_backward(const cc_problem* p, const Plan& P, float* W, const float* img, const float* y, const float* u,
+                    const float* arm_w, const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y,
+                    float* g_arm, float* g_ups, float* g_syn, BwdSet* b) {
+  std::memset(b, 0, sizeof(*b));
   const int L = P.geo.L;
   const float HW = (float)p->H * p->W;
-  std::lock_guard<std::mutex> lock(g_side_mu);
-  Side* sd = nullptr;
-  if ((rc = side_for_current_device(&sd))) return rc;
-  (void)hipGetLastError();
-  ArmArgs aa;
-  std::memset(&aa, 0, sizeof(aa));
+  ArmArgs& aa = b->arm;
   aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
   aa.scale = dloss * p->lambda / HW;
   aa.gext = W + P.gext; aa.wpart = W + P.wpart_arm; aa.rpart = W + P.rpart;
-  if ((rc = fork_to(sd, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_ARM, (const void*)armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
-  if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
-  SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
+  b->upf = ups_fwd_args(P, W, y, u, p->quant, ups_w, &b->upf_grid);
+  SynArgs& sa = b->syn;
+  sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
   sa.img = img;
   sa.dscale = dloss * 2.0f / (3.0f * HW);
   sa.g_y = g_y;
   sa.gz = W + P.gz;
   sa.wpart = W + P.wpart_syn;
   sa.spart = W + P.spart;
-  if ((rc = launch((const void*)t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_SYNTHESIS, (const void*)bwk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
+  b->t0_grid = cdiv(p->H * p->W, 256);
   for (int s = 0; s + 1 < L; ++s) {
-    UpsBwdArgs ua;
+    UpsBwdArgs& ua = b->upb[s];
     ua.geo = P.geo; ua.s = s; ua.y = y; ua.u = u; ua.quant = p->quant;
     ua.taps = ups_w + (size_t)s * 2 * UPS_K;
     ua.up_in = (s + 1 <= L - 2) ? W + P.up[s + 1] : nullptr;
@@ -331,16 +333,8 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
     ua.g_y = g_y + P.geo.loff[s + 1];
     ua.g_out = (s + 1 <= L - 2) ? W + P.gb[s + 1] : nullptr;
     ua.part = W + P.upart[s];
-    {
-      void* argv[] = {&ua};
-      if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], L - 1 - s), dim3(256), argv, 0, st) !=
-          hipSuccess)
-        return CC_EHIP;
-    }
   }
-  if ((rc = join_from(sd, st))) return rc;
-  CombineArgs ca;
-  std::memset(&ca, 0, sizeof(ca));
+  CombineArgs& ca = b->comb;
   int ns = 0, blk = 0;
   auto add = [&](const float* src, int rows, int cols, int cpb, float* dst) {
     ca.seg[ns] = RedSeg{src, rows, cols, cols, cpb, dst};
@@ -356,16 +350,283 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   ca.block_start[ns] = blk;
   ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
   ca.flags = W + P.flags;
-  if ((rc = launch((const void*)combine_kernel, blk + P.fold_grid, 256, &ca, st))) return rc;
-  FinalArgs fa;
-  std::memset(&fa, 0, sizeof(fa));
+  b->comb_grid = blk + P.fold_grid;
+  FinalArgs& fa = b->fin;
   fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
-  fa.flags = W + P.flags; fa.nflags = P.red_grid + P.fold_grid;
+  fa.flags = W + P.flags; fa.nflags = b->comb_grid;
   fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
   fa.have_rate = 1; fa.have_sse = 1; fa.loss4 = loss4;
-  if ((rc = launch((const void*)finalize_kernel, 1, 256, &fa, st))) return rc;
+}
+
+int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
+                      const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
+                      float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream) {
+  Plan P;
+  int rc = make_plan(p, CC_WS_BACKWARD, &P);
+  if (rc) return rc;
+  if (!img || !y || !arm_w || !ups_w || !syn_w || !loss4 || !g_y || !g_arm || !g_ups || !g_syn || !ws)
+    return CC_EINVAL;
+  if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
+  if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
+  const void* armk = arm_kernel_for(P.C, P.NH, true, false);
+  const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *bwk = syn_bwd_kernel_for(P.Hs, P.nres, false);
+  if (!armk || !t0k || !bwk) return CC_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const int L = P.geo.L;
+  static thread_local BwdSet b;
+  build_backward(p, P, (float*)ws, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, g_y, g_arm, g_ups, g_syn, &b);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side* sd = nullptr;
+  if ((rc = side_for_current_device(&sd))) return rc;
+  (void)hipGetLastError();
+  if ((rc = fork_to(sd, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
+  if (b.upf_grid && (rc = launch((const void*)ups_fwd_kernel, b.upf_grid, 256, &b.upf, st))) return rc;
+  if ((rc = launch(t0k, b.t0_grid, 256, &b.syn, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_SYNTHESIS, bwk, P.syn_grid, SYN_THREADS, &b.syn, st))) return rc;
+  for (int s = 0; s + 1 < L; ++s) {
+    void* argv[] = {&b.upb[s]};
+    if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], L - 1 - s), dim3(256), argv, 0, st) !=
+        hipSuccess)
+      return CC_EHIP;
+  }
+  if ((rc = join_from(sd, st))) return rc;
+  if ((rc = launch((const void*)combine_kernel, b.comb_grid, 256, &b.comb, st))) return rc;
+  if ((rc = launch((const void*)finalize_kernel, 1, 256, &b.fin, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
+
+}  // extern "C"
+
+namespace cc {
+namespace {
+
+// Host-side plan of a batch.
+struct BatchPlan {
+  int n = 0, L = 0, device = 0;
+  const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr;
+  // device arrays inside the workspace
+  ArmArgs* d_arm = nullptr;
+  UpsFwdArgs* d_upf = nullptr;
+  SynArgs* d_syn = nullptr;
+  UpsBwdArgs* d_upb[MAXL] = {};
+  CombineArgs* d_comb = nullptr;
+  FinalArgs* d_fin = nullptr;
+  WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_upb[MAXL] = {},
+           *w_comb = nullptr;
+  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_upb[MAXL] = {}, n_comb = 0;
+};
+
+int share(int total, long long part, long long whole, int cap) {
+  if (total <= 0) return 0;  // default grid
+  long long g = (long long)total * part / whole;
+  return (int)std::max(1LL, std::min<long long>(g, cap));
+}
+
+// Per-image plans for a batch and the layout of the batch workspace (bytes).
+int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, std::vector<Plan>& plans,
+                 std::vector<size_t>& img_off, size_t* desc_off, size_t* total_bytes) {
+  if (n <= 0 || !probs) return CC_EINVAL;
+  long long tiles_arm = 0, tiles_syn = 0;
+  plans.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int rc = make_plan(&probs[k], CC_WS_BACKWARD, &plans[k]);
+    if (rc) return rc;
+    const cc_arch &a = probs[k].arch, &a0 = probs[0].arch;
+    if (std::memcmp(&a, &a0, sizeof(cc_arch)) || probs[k].quant != probs[0].quant) return CC_EINVAL;
+    tiles_arm += plans[k].tiles.n_tiles;
+    tiles_syn += plans[k].syn_tiles;
+  }
+  const int ta = tune ? tune->arm_blocks : 0, ts = tune ? tune->syn_blocks : 0;
+  img_off.resize(n);
+  size_t cur = 0;
+  for (int k = 0; k < n; ++k) {
+    const int ga = share(ta, plans[k].tiles.n_tiles, tiles_arm, 4096);
+    const int gs = share(ts, plans[k].syn_tiles, tiles_syn, 4096);
+    make_plan(&probs[k], CC_WS_BACKWARD, &plans[k], ga, gs);
+    img_off[k] = cur;
+    cur += (plans[k].total * sizeof(float) + 255) / 256 * 256;
+  }
+  *desc_off = cur;
+  // descriptors and work-lists
+  const int L = probs[0].arch.n_levels;
+  size_t d = 0;
+  auto blk = [&](size_t bytes) { d += (bytes + 255) / 256 * 256; };
+  blk(sizeof(ArmArgs) * n);
+  blk(sizeof(UpsFwdArgs) * n);
+  blk(sizeof(SynArgs) * n);
+  for (int s = 0; s + 1 < L; ++s) blk(sizeof(UpsBwdArgs) * n);
+  blk(sizeof(CombineArgs) * n);
+  blk(sizeof(FinalArgs) * n);
+  long long items = 0;
+  for (int k = 0; k < n; ++k) {
+    const Plan& P = plans[k];
+    items += P.arm_grid + P.syn_grid + cdiv(P.geo.H * P.geo.W, 256) + P.red_grid + P.fold_grid;
+    items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+    for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * (L - 1 - s);
+  }
+  blk(sizeof(WorkItem) * items + 256 * (L + 8));
+  *total_bytes = cur + d;
+  return CC_OK;
+}
+
+}  // namespace
+}  // namespace cc
+
+struct cc_batch {
+  cc::BatchPlan p;
+};
+
+extern "C" {
+
+size_t coolchic_batch_workspace_bytes(int32_t n, const cc_problem* probs, const cc_batch_tuning* tune) {
+  std::vector<Plan> plans;
+  std::vector<size_t> off;
+  size_t d = 0, total = 0;
+  if (batch_layout(n, probs, tune, plans, off, &d, &total)) return 0;
+  return total;
+}
+
+int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io* io, const cc_batch_tuning* tune,
+                          float dloss, void* ws, size_t ws_bytes, cc_batch** out) {
+  if (!out) return CC_EINVAL;
+  *out = nullptr;
+  if (!io || !ws) return CC_EINVAL;
+  std::vector<Plan> plans;
+  std::vector<size_t> img_off;
+  size_t desc_off = 0, total = 0;
+  int rc = batch_layout(n, probs, tune, plans, img_off, &desc_off, &total);
+  if (rc) return rc;
+  if (ws_bytes < total) return CC_EWORKSPACE;
+  for (int k = 0; k < n; ++k) {
+    const cc_image_io& q = io[k];
+    if (!q.img || !q.y || !q.arm_w || !q.ups_w || !q.syn_w || !q.loss4 || !q.g_y || !q.g_arm || !q.g_ups ||
+        !q.g_syn)
+      return CC_EINVAL;
+    if (probs[k].quant == CC_QUANT_NOISE && !q.u) return CC_EINVAL;
+  }
+  const Plan& P0 = plans[0];
+  const int L = P0.geo.L;
+  BatchPlan B;
+  B.n = n;
+  B.L = L;
+  B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
+  B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
+  B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
+  if (!B.armk || !B.t0k || !B.bwk) return CC_EUNSUPPORTED;
+  if (hipGetDevice(&B.device) != hipSuccess) return CC_EHIP;
+  // host copies of every argument block and work-list
+  std::vector<ArmArgs> h_arm(n);
+  std::vector<UpsFwdArgs> h_upf(n);
+  std::vector<SynArgs> h_syn(n);
+  std::vector<std::vector<UpsBwdArgs>> h_upb(L, std::vector<UpsBwdArgs>(n));
+  std::vector<CombineArgs> h_comb(n);
+  std::vector<FinalArgs> h_fin(n);
+  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_comb;
+  std::vector<std::vector<WorkItem>> w_upb(L);
+  BwdSet* b = new (std::nothrow) BwdSet;
+  if (!b) return CC_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    const cc_image_io& q = io[k];
+    const Plan& P = plans[k];
+    float* W = (float*)((char*)ws + img_off[k]);
+    build_backward(&probs[k], P, W, q.img, q.y, q.u, q.arm_w, q.ups_w, q.syn_w, dloss, q.loss4, q.g_y, q.g_arm,
+                   q.g_ups, q.g_syn, b);
+    h_arm[k] = b->arm; h_upf[k] = b->upf; h_syn[k] = b->syn; h_comb[k] = b->comb; h_fin[k] = b->fin;
+    for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
+    for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
+    for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
+    for (int i = 0; i < b->t0_grid; ++i) w_t0.push_back(WorkItem{k, i, b->t0_grid, 0});
+    for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
+    for (int s = 0; s + 1 < L; ++s)
+      for (int ch = 0; ch < L - 1 - s; ++ch)
+        for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], ch});
+    for (int i = 0; i < b->comb_grid; ++i) w_comb.push_back(WorkItem{k, i, b->comb_grid, 0});
+  }
+  delete b;
+  // upload: argument blocks, then work-lists
+  char* base = (char*)ws + desc_off;
+  size_t d = 0;
+  int err = 0;
+  auto put = [&](const void* src, size_t bytes) -> void* {
+    void* dst = base + d;
+    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) err = 1;
+    d += (bytes + 255) / 256 * 256;
+    return dst;
+  };
+  B.d_arm = (ArmArgs*)put(h_arm.data(), sizeof(ArmArgs) * n);
+  B.d_upf = (UpsFwdArgs*)put(h_upf.data(), sizeof(UpsFwdArgs) * n);
+  B.d_syn = (SynArgs*)put(h_syn.data(), sizeof(SynArgs) * n);
+  for (int s = 0; s + 1 < L; ++s) B.d_upb[s] = (UpsBwdArgs*)put(h_upb[s].data(), sizeof(UpsBwdArgs) * n);
+  B.d_comb = (CombineArgs*)put(h_comb.data(), sizeof(CombineArgs) * n);
+  B.d_fin = (FinalArgs*)put(h_fin.data(), sizeof(FinalArgs) * n);
+  auto putw = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) {
+    *cnt = (int)v.size();
+    *dst = (WorkItem*)put(v.data(), sizeof(WorkItem) * v.size());
+  };
+  putw(w_arm, &B.w_arm, &B.n_arm);
+  putw(w_upf, &B.w_upf, &B.n_upf);
+  putw(w_t0, &B.w_t0, &B.n_t0);
+  putw(w_syn, &B.w_syn, &B.n_syn);
+  for (int s = 0; s + 1 < L; ++s) putw(w_upb[s], &B.w_upb[s], &B.n_upb[s]);
+  putw(w_comb, &B.w_comb, &B.n_comb);
+  if (err || desc_off + d > ws_bytes) return err ? CC_EHIP : CC_EWORKSPACE;
+  cc_batch* h = new (std::nothrow) cc_batch;
+  if (!h) return CC_EINVAL;
+  h->p = B;
+  *out = h;
+  return CC_OK;
+}
+
+int coolchic_batch_backward(const cc_batch* batch, void* stream) {
+  if (!batch) return CC_EINVAL;
+  const BatchPlan& B = batch->p;
+  hipStream_t st = (hipStream_t)stream;
+  int rc, dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return CC_EHIP;
+  if (dev != B.device) return CC_EINVAL;  // the plan's buffers live on another device
+  auto go = [&](int stage, const void* fn, int grid, int block, void* descs, void* work) -> int {
+    if (grid <= 0) return CC_OK;
+    void* argv[] = {&descs, &work};
+    const bool timed = stage != CC_STAGE_NONE && stage == g_stage && g_ev_begin && g_ev_end;
+    if (timed && hipEventRecord(g_ev_begin, st) != hipSuccess) return CC_EHIP;
+    if (hipLaunchKernel(fn, dim3(grid), dim3(block), argv, 0, st) != hipSuccess) return CC_EHIP;
+    if (timed && hipEventRecord(g_ev_end, st) != hipSuccess) return CC_EHIP;
+    return CC_OK;
+  };
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side* sd = nullptr;
+  if ((rc = side_for_current_device(&sd))) return rc;
+  (void)hipGetLastError();
+  if ((rc = fork_to(sd, st))) return rc;
+  {
+    // the ARM launch goes to the side stream
+    void* descs = B.d_arm;
+    void* work = B.w_arm;
+    void* argv[] = {&descs, &work};
+    const bool timed = g_stage == CC_STAGE_ARM && g_ev_begin && g_ev_end;
+    if (timed && hipEventRecord(g_ev_begin, sd->stream) != hipSuccess) return CC_EHIP;
+    if (hipLaunchKernel(B.armk, dim3(B.n_arm), dim3(ARM_THREADS), argv, 0, sd->stream) != hipSuccess) return CC_EHIP;
+    if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
+  }
+  if ((rc = go(CC_STAGE_NONE, (const void*)ups_fwd_kernel_batch, B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
+  if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
+  if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
+  for (int s = 0; s + 1 < B.L; ++s)
+    if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
+      return rc;
+  if ((rc = join_from(sd, st))) return rc;
+  if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb, 256, B.d_comb, B.w_comb))) return rc;
+  {
+    void* descs = B.d_fin;
+    void* argv[] = {&descs};
+    if (hipLaunchKernel((const void*)finalize_kernel_batch, dim3(B.n), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+void coolchic_batch_destroy(cc_batch* batch) { delete batch; }
 
 int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups_w, const float* syn_w, float* xhat,
                           void* ws, size_t ws_bytes, void* stream) {
@@ -377,7 +638,7 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   if (rc) return rc;
   if (!yq || !ups_w || !syn_w || !xhat || !ws) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
-  SynKernelFn t0k = syn_t0_kernel_for(P.Hs, P.nres), resk = syn_res_fwd_kernel_for(P.Hs, P.nres);
+  const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *resk = syn_res_fwd_kernel_for(P.Hs, P.nres, false);
   if (!t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
@@ -385,8 +646,8 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   if ((rc = launch_ups_fwd(P, W, yq, nullptr, 2, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, yq, nullptr, 2, ups_w, syn_w);
   sa.xhat = xhat;
-  if ((rc = launch((const void*)t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
-  if ((rc = launch((const void*)resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
+  if ((rc = launch(t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
+  if ((rc = launch(resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ int ctx_dx(int k) {
 constexpr int STG = 36;  // row stride of the per-wave staging matrices
 
 template <int C, int NH, bool BWD>
-__global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
+__device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const int nblk) {
   constexpr int NR = C / 2;            // accumulator rows holding features < C
   constexpr int CS = C + 1;            // row stride of the context-gradient buffer
   constexpr int NW = NH * (C * C + C) + 2 * C + 2;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) { accWo0[r] = 0.0f; accWo1[r] = 0.0f; }
 
-  for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
+  for (int tile = bid; tile < a.tiles.n_tiles; tile += nblk) {
     int l = 0;
     while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
     const int local = tile - a.tiles.base[l];
@@ -260,22 +260,35 @@ __global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
   if (tid == 0) {
     float s = 0.0f;
     for (int k = 0; k < ARM_WAVES; ++k) s += s_rate[k];
-    a.rpart[blockIdx.x] = s;
+    a.rpart[bid] = s;
   }
   if (BWD) {
     for (int p = tid; p < NW; p += ARM_THREADS) {
       float s = 0.0f;
       for (int k = 0; k < ARM_WAVES; ++k) s += red[k * NW + p];
-      a.wpart[(size_t)blockIdx.x * NW + p] = s;
+      a.wpart[(size_t)bid * NW + p] = s;
     }
   }
 }
 
+template <int C, int NH, bool BWD>
+__global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel(ArmArgs a) {
+  arm_body<C, NH, BWD>(a, blockIdx.x, gridDim.x);
+}
+
+template <int C, int NH, bool BWD>
+__global__ __launch_bounds__(ARM_THREADS, 2) void arm_kernel_batch(const ArmArgs* __restrict__ descs,
+                                                                 const WorkItem* __restrict__ work) {
+  const WorkItem w = work[blockIdx.x];
+  arm_body<C, NH, BWD>(descs[w.img], w.bid, w.nblk);
+}
+
 // ---- instantiation table
-template <bool BWD>
-static ArmKernelFn pick(int C, int NH) {
-#define CC_ARM_CASE(CC, HH) \
-  if (C == CC && NH == HH) return arm_kernel<CC, HH, BWD>;
+template <bool BWD, bool BATCH>
+static const void* pick(int C, int NH) {
+#define CC_ARM_CASE(CC, HH)                                                                          \
+  if (C == CC && NH == HH)                                                                          \
+    return BATCH ? (const void*)arm_kernel_batch<CC, HH, BWD> : (const void*)arm_kernel<CC, HH, BWD>;
   CC_ARM_CASE(8, 1) CC_ARM_CASE(8, 2) CC_ARM_CASE(8, 3)
   CC_ARM_CASE(16, 1) CC_ARM_CASE(16, 2) CC_ARM_CASE(16, 3)
   CC_ARM_CASE(24, 1) CC_ARM_CASE(24, 2) CC_ARM_CASE(24, 3)
@@ -283,6 +296,9 @@ static ArmKernelFn pick(int C, int NH) {
   return nullptr;
 }
 
-ArmKernelFn arm_kernel_for(int C, int NH, bool bwd) { return bwd ? pick<true>(C, NH) : pick<false>(C, NH); }
+const void* arm_kernel_for(int C, int NH, bool bwd, bool batch) {
+  if (batch) return bwd ? pick<true, true>(C, NH) : pick<false, true>(C, NH);
+  return bwd ? pick<true, false>(C, NH) : pick<false, false>(C, NH);
+}
 
 }  // namespace cc

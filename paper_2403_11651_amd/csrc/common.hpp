@@ -66,4 +66,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
 
+// One work-group of a batched launch: the image whose argument block it
+// uses, its block index and the block count of that image's share, and a
+// kernel-specific extra index.
+struct WorkItem {
+  int img, bid, nblk, aux;
+};
+
 }  // namespace cc

@@ -33,8 +33,9 @@ struct ArmArgs {
   float* wpart;        // backward: [gridDim][n_arm] weight-gradient partials
   float* rpart;        // [gridDim] rate partial sums (bits)
 };
-typedef void (*ArmKernelFn)(ArmArgs);
-ArmKernelFn arm_kernel_for(int C, int NH, bool bwd);
+// kernel handle (host stub address) for hipLaunchKernel; batch: the variant
+// taking (const ArmArgs* descs, const WorkItem* work)
+const void* arm_kernel_for(int C, int NH, bool bwd, bool batch);
 
 struct FoldArgs {
   Geo geo;
@@ -54,6 +55,7 @@ struct UpsFwdArgs {
   float* up_out[MAXL];         // U_s output [(L-1-s)][h_s][w_s] for s = 1..L-2
 };
 __global__ void ups_fwd_kernel(UpsFwdArgs a);
+__global__ void ups_fwd_kernel_batch(const UpsFwdArgs* d, const WorkItem* w);
 
 struct UpsBwdArgs {
   Geo geo;
@@ -69,6 +71,7 @@ struct UpsBwdArgs {
   float* part;         // [gridDim][2K] tap-gradient partials
 };
 __global__ void ups_bwd_kernel(UpsBwdArgs a);
+__global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
 
 // ---------------------------------------------------------------- synthesis
 constexpr int SYN_T = 16;                  // output tile side (pixels)
@@ -96,10 +99,9 @@ struct SynArgs {
   float* spart;        // [gridDim] squared-error partial sums
   int n_tiles_x, n_tiles;
 };
-typedef void (*SynKernelFn)(SynArgs);
-SynKernelFn syn_t0_kernel_for(int Hs, int nres);
-SynKernelFn syn_res_fwd_kernel_for(int Hs, int nres);
-SynKernelFn syn_bwd_kernel_for(int Hs, int nres);
+const void* syn_t0_kernel_for(int Hs, int nres, bool batch);
+const void* syn_res_fwd_kernel_for(int Hs, int nres, bool batch);
+const void* syn_bwd_kernel_for(int Hs, int nres, bool batch);
 
 // ---------------------------------------------------------------- reductions, optimiser
 constexpr int RED_MAXSEG = 12;
@@ -120,6 +122,7 @@ struct CombineArgs {
   float* flags;        // [gridDim] 1 if any result of the block is not finite
 };
 __global__ void combine_kernel(CombineArgs a);
+__global__ void combine_kernel_batch(const CombineArgs* d, const WorkItem* w);
 
 struct FinalArgs {
   const float* rpart; int nr;    // rate partials (bits)
@@ -130,6 +133,7 @@ struct FinalArgs {
   float* loss4;
 };
 __global__ void finalize_kernel(FinalArgs a);
+__global__ void finalize_kernel_batch(const FinalArgs* d);
 
 struct AdamArgs {
   float* theta;

@@ -38,20 +38,20 @@ __device__ bool arm_fold_one(const FoldArgs& a, int q) {
 // CombineArgs).  A reduction block owns cpb columns of one segment; its
 // 256 / cpb row groups each sum a strided set of rows, then a fixed-order
 // tree combines the row groups.
-__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
+__device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid) {
   __shared__ float s_p[256];
   const int tid = threadIdx.x;
   const int n_red = a.block_start[a.nseg];
   bool bad = false;
-  if ((int)blockIdx.x >= n_red) {
-    bad = !arm_fold_one(a.fold, ((int)blockIdx.x - n_red) * 256 + tid);
+  if (bid >= n_red) {
+    bad = !arm_fold_one(a.fold, (bid - n_red) * 256 + tid);
   } else {
     int sg = 0;
-    while (sg + 1 < a.nseg && (int)blockIdx.x >= a.block_start[sg + 1]) ++sg;
+    while (sg + 1 < a.nseg && bid >= a.block_start[sg + 1]) ++sg;
     const RedSeg& S = a.seg[sg];
     const int cpb = S.cpb, ngroups = 256 / cpb;
     const int cl = tid % cpb, rg = tid / cpb;
-    const int col = ((int)blockIdx.x - a.block_start[sg]) * cpb + cl;
+    const int col = (bid - a.block_start[sg]) * cpb + cl;
     float acc = 0.0f;
     if (col < S.cols)
       for (int r = rg; r < S.rows; r += ngroups) acc += S.src[(size_t)r * S.ld + col];
@@ -68,7 +68,13 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     }
   }
   const bool any = __syncthreads_or(bad);
-  if (tid == 0) a.flags[blockIdx.x] = any ? 1.0f : 0.0f;
+  if (tid == 0) a.flags[bid] = any ? 1.0f : 0.0f;
+}
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) { combine_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void combine_kernel_batch(const CombineArgs* __restrict__ d,
+                                                            const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  combine_body(d[it.img], it.bid);
 }
 
 __device__ float block_sum_fixed(const float* src, int n, float* s_tmp) {
@@ -87,19 +93,27 @@ __device__ float block_sum_fixed(const float* src, int n, float* s_tmp) {
 }
 
 // loss4 = {D + lambda R / (HW), D, R, non-finite flag} (Eq. (1); D = SSE / 3HW).
-__global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) {
+__device__ __forceinline__ void finalize_body(const FinalArgs& a) {
   __shared__ float s_tmp[256];
   const float R = a.have_rate ? block_sum_fixed(a.rpart, a.nr, s_tmp) : 0.0f;
   const float sse = a.have_sse ? block_sum_fixed(a.spart, a.ns, s_tmp) : 0.0f;
   const float fl = a.nflags ? block_sum_fixed(a.flags, a.nflags, s_tmp) : 0.0f;
   if (threadIdx.x == 0) {
+    // explicit rounding steps, so that every kernel built from this body
+    // (single image or batched) computes the loss the same way
     const float D = sse * a.inv_3hw;
-    const float L = D + a.lambda * R * a.inv_hw;
+    const float L = __builtin_fmaf(a.lambda * R, a.inv_hw, D);
     a.loss4[0] = L;
     a.loss4[1] = D;
     a.loss4[2] = R;
     a.loss4[3] = (fl > 0.0f || !finitef(L) || !finitef(D) || !finitef(R)) ? 1.0f : 0.0f;
   }
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) { finalize_body(a); }
+// one work-group per image
+__global__ __launch_bounds__(256) void finalize_kernel_batch(const FinalArgs* __restrict__ d) {
+  finalize_body(d[blockIdx.x]);
 }
 
 // Adam (Kingma & Ba) with bias correction; t = step[0] + 1.  Every block reads

@@ -107,12 +107,12 @@ __device__ __forceinline__ void layers_1x1(const SynW<HS, NRES>& sw, const float
 }
 
 template <int HS, int NRES>
-__global__ __launch_bounds__(256) void syn_t0_kernel(SynArgs a) {
+__device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   __shared__ SynW<HS, NRES> sw;
   const int H = a.geo.H, W = a.geo.W, L = a.geo.L;
   stage_weights(sw, a.w, L, threadIdx.x);
   __syncthreads();
-  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int idx = bid * 256 + threadIdx.x;
   if (idx >= H * W) return;
   const int i = idx / W, j = idx % W;
   float z[MAXL], zz[8], t[3];
@@ -162,14 +162,14 @@ __device__ __forceinline__ void res_layer(const float* wr, const float* src, flo
 }
 
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
+__device__ __forceinline__ void syn_res_fwd_body(const SynArgs& a, const int bid, const int nblk) {
   constexpr int FA = SYN_FMAX * SYN_FMAX, E = NRES, FS = SYN_T + 2 * E;
   __shared__ SynW<HS, NRES> sw;
   __shared__ float s_t[2][3 * FA];
   const int H = a.geo.H, W = a.geo.W, tid = threadIdx.x;
   stage_weights(sw, a.w, a.geo.L, tid);
   float sse = 0.0f;
-  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+  for (int tile = bid; tile < a.n_tiles; tile += nblk) {
     const int i0 = (tile / a.n_tiles_x) * SYN_T, j0 = (tile % a.n_tiles_x) * SYN_T;
     const int fi0 = i0 - E, fj0 = j0 - E;
     const bool inside = fi0 >= 0 && fj0 >= 0 && fi0 + FS <= H && fj0 + FS <= W;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
   if (tid == 0 && a.spart) {
     float acc = 0.0f;
     for (int k = 0; k < SYN_THREADS / 64; ++k) acc += s_red[k];
-    a.spart[blockIdx.x] = acc;
+    a.spart[bid] = acc;
   }
 }
 
@@ -348,7 +348,7 @@ __device__ __forceinline__ void relu_mask(const float* t, float* g, int tid) {
 }
 
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
+__device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, const int nblk) {
   constexpr int FA = SYN_FMAX * SYN_FMAX, E = 2 * NRES, FS = SYN_T + 2 * E;
   constexpr int BMA = (HS + 15) / 16;   // blocks of the hidden width
   constexpr int BNA = (HS + 1 + 15) / 16;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
   for (int r = 0; r < NRES; ++r) zero_acc(accR[r]);
   float sse = 0.0f;
 
-  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+  for (int tile = bid; tile < a.n_tiles; tile += nblk) {
     const int i0 = (tile / a.n_tiles_x) * SYN_T, j0 = (tile % a.n_tiles_x) * SYN_T;
     const int fi0 = i0 - E, fj0 = j0 - E;
     const bool inside = fi0 >= 0 && fj0 >= 0 && fi0 + FS <= H && fj0 + FS <= W;
@@ -579,37 +579,76 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
   for (int p = tid0; p < n_syn; p += SYN_THREADS) {
     float acc = 0.0f;
     for (int k = 0; k < SYN_THREADS / 64; ++k) acc += red[k * n_syn + p];
-    a.wpart[(size_t)blockIdx.x * n_syn + p] = acc;
+    a.wpart[(size_t)bid * n_syn + p] = acc;
   }
   if (tid0 == 0) {
     float acc = 0.0f;
     for (int k = 0; k < SYN_THREADS / 64; ++k) acc += s_red[k];
-    a.spart[blockIdx.x] = acc;
+    a.spart[bid] = acc;
   }
+}
+
+template <int HS, int NRES>
+__global__ __launch_bounds__(256) void syn_t0_kernel(SynArgs a) {
+  syn_t0_body<HS, NRES>(a, blockIdx.x);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(256) void syn_t0_kernel_batch(const SynArgs* __restrict__ d, const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  syn_t0_body<HS, NRES>(d[it.img], it.bid);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel(SynArgs a) {
+  syn_res_fwd_body<HS, NRES>(a, blockIdx.x, gridDim.x);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel_batch(const SynArgs* __restrict__ d,
+                                                                        const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  syn_res_fwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
+  syn_bwd_body<HS, NRES>(a, blockIdx.x, gridDim.x);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel_batch(const SynArgs* __restrict__ d,
+                                                                       const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  syn_bwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
 }
 
 #define CC_SYN_TABLE(KERNEL)                                         \
   if (nres == 1) switch (Hs) {                                       \
-      case 8: return KERNEL<8, 1>;                                   \
-      case 16: return KERNEL<16, 1>;                                 \
-      case 24: return KERNEL<24, 1>;                                 \
-      case 32: return KERNEL<32, 1>;                                 \
-      case 40: return KERNEL<40, 1>;                                 \
-      case 48: return KERNEL<48, 1>;                                 \
+      case 8: return (const void*)KERNEL<8, 1>;                                   \
+      case 16: return (const void*)KERNEL<16, 1>;                                 \
+      case 24: return (const void*)KERNEL<24, 1>;                                 \
+      case 32: return (const void*)KERNEL<32, 1>;                                 \
+      case 40: return (const void*)KERNEL<40, 1>;                                 \
+      case 48: return (const void*)KERNEL<48, 1>;                                 \
     }                                                                \
   if (nres == 2) switch (Hs) {                                       \
-      case 8: return KERNEL<8, 2>;                                   \
-      case 16: return KERNEL<16, 2>;                                 \
-      case 24: return KERNEL<24, 2>;                                 \
-      case 32: return KERNEL<32, 2>;                                 \
-      case 40: return KERNEL<40, 2>;                                 \
-      case 48: return KERNEL<48, 2>;                                 \
+      case 8: return (const void*)KERNEL<8, 2>;                                   \
+      case 16: return (const void*)KERNEL<16, 2>;                                 \
+      case 24: return (const void*)KERNEL<24, 2>;                                 \
+      case 32: return (const void*)KERNEL<32, 2>;                                 \
+      case 40: return (const void*)KERNEL<40, 2>;                                 \
+      case 48: return (const void*)KERNEL<48, 2>;                                 \
     }                                                                \
   return nullptr;
 
-SynKernelFn syn_t0_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_t0_kernel) }
-SynKernelFn syn_res_fwd_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_res_fwd_kernel) }
-SynKernelFn syn_bwd_kernel_for(int Hs, int nres) { CC_SYN_TABLE(syn_bwd_kernel) }
+const void* syn_t0_kernel_for(int Hs, int nres, bool batch) {
+  if (batch) { CC_SYN_TABLE(syn_t0_kernel_batch) }
+  CC_SYN_TABLE(syn_t0_kernel)
+}
+const void* syn_res_fwd_kernel_for(int Hs, int nres, bool batch) {
+  if (batch) { CC_SYN_TABLE(syn_res_fwd_kernel_batch) }
+  CC_SYN_TABLE(syn_res_fwd_kernel)
+}
+const void* syn_bwd_kernel_for(int Hs, int nres, bool batch) {
+  if (batch) { CC_SYN_TABLE(syn_bwd_kernel_batch) }
+  CC_SYN_TABLE(syn_bwd_kernel)
+}
 #undef CC_SYN_TABLE
 
 }  // namespace cc

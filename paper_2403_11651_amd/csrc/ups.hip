@@ -26,12 +26,12 @@ constexpr int UF_T = 32;       // level-1 tile side
 constexpr int UF_R = 20;       // largest region side at levels >= 2
 constexpr int UF_CH = MAXL - 1;  // channels of stack_2 at most (L - 2 < 6)
 
-__global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) {
+__device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid) {
   __shared__ float s_st[2][UF_CH * UF_R * UF_R];
   const int L = a.geo.L, tid = threadIdx.x;
   const int h1 = a.geo.lh[1], w1 = a.geo.lw[1];
   const int ntx = (w1 + UF_T - 1) / UF_T;
-  const int r0 = (blockIdx.x / ntx) * UF_T, c0 = (blockIdx.x % ntx) * UF_T;
+  const int r0 = (bid / ntx) * UF_T, c0 = (bid % ntx) * UF_T;
   // regions [ra, rb) x [ca, cb) per level
   int ra[MAXL], rb[MAXL], ca[MAXL], cb[MAXL];
   ra[1] = r0; rb[1] = min(r0 + UF_T, h1); ca[1] = c0; cb[1] = min(c0 + UF_T, w1);
@@ -109,7 +109,7 @@ constexpr int UT = 16;                 // input positions per tile side
 constexpr int UP_N = UT + 4;           // padded indices per tile side: [m0-2, m0+UT+2)
 constexpr int UR_N = 2 * UT + 14;      // output rows / columns read: [2m0-7, 2m0+2UT+7)
 
-__global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
+__device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid, const int ntiles, const int ch) {
   __shared__ float s_g[UR_N * UR_N];
   __shared__ float s_T[UR_N * UP_N];   // [output row][padded column]
   __shared__ float s_T2[UP_N * UR_N];  // [padded row][output column]
@@ -117,8 +117,7 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   const int s = a.s, L = a.geo.L, tid = threadIdx.x;
   const int ho = a.geo.lh[s], wo = a.geo.lw[s], hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1];
   const int ntx = (wi + UT - 1) / UT;
-  const int r0 = (blockIdx.x / ntx) * UT, c0 = (blockIdx.x % ntx) * UT;
-  const int ch = blockIdx.y;  // channel of stack_{s+1} handled by this work-group
+  const int r0 = (bid / ntx) * UT, c0 = (bid % ntx) * UT;  // ch: channel of stack_{s+1} handled here
   const int tr = tid / UT, tc = tid % UT, r = r0 + tr, c = c0 + tc;
   const bool in_tile = r < hi && c < wi;
   float v[UPS_K], hh[UPS_K], gv[UPS_K], gh[UPS_K];
@@ -204,8 +203,23 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   if (tid < 2 * UPS_K) {
     float acc = 0.0f;
     for (int wv = 0; wv < 4; ++wv) acc += s_red[wv][tid];
-    a.part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2 * UPS_K + tid] = acc;
+    a.part[((size_t)ch * ntiles + bid) * 2 * UPS_K + tid] = acc;
   }
+}
+
+__global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) { ups_fwd_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void ups_fwd_kernel_batch(const UpsFwdArgs* __restrict__ d,
+                                                            const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  ups_fwd_body(d[it.img], it.bid);
+}
+__global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
+  ups_bwd_body(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+__global__ __launch_bounds__(256) void ups_bwd_kernel_batch(const UpsBwdArgs* __restrict__ d,
+                                                            const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  ups_bwd_body(d[it.img], it.bid, it.nblk, it.aux);
 }
 
 }  // namespace cc

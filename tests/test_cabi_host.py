@@ -80,3 +80,49 @@ def test_null_pointers_and_small_workspace(B):
     assert B.lib.coolchic_adam_step(d, d, d, d, 0, d, 0.01, 0.9, 0.999, 1e-8, None) == -1
     assert B.lib.coolchic_adam_step(d, d, d, d, 10, d, 0.01, 1.0, 0.999, 1e-8, None) == -1
     assert B.strerror(-3).startswith("workspace")
+
+
+def _batch(B, probs):
+    arr = (B.CCProblem * len(probs))(*[p.c() for p in probs])
+    return arr, B.CCBatchTuning(0, 0)
+
+
+def test_batch_workspace_bytes(B):
+    a = B.Problem(256, 320, B.LOW)
+    b = B.Problem(512, 768, B.LOW)
+    one = B.batch_workspace_bytes([a])
+    two = B.batch_workspace_bytes([a, b])
+    # every image brings its own backward workspace, plus argument blocks
+    assert one >= B.workspace_bytes(a, 1)
+    assert two >= one + B.workspace_bytes(b, 1)
+    # a larger persistent grid needs more partial-sum rows
+    assert B.batch_workspace_bytes([a, b], (4096, 4096)) > B.batch_workspace_bytes([a, b], (64, 64))
+    assert B.batch_workspace_bytes([a, B.Problem(512, 768, B.FULL)]) == 0  # architectures differ
+    assert B.batch_workspace_bytes([a, B.Problem(100, 768, B.LOW)]) == 0  # invalid size
+    arr, t = _batch(B, [a])
+    assert B.lib.coolchic_batch_workspace_bytes(0, arr, ctypes.byref(t)) == 0
+    assert B.lib.coolchic_batch_workspace_bytes(1, None, ctypes.byref(t)) == 0
+    assert B.lib.coolchic_batch_workspace_bytes(1, arr, None) == one  # NULL tuning = default shapes
+
+
+def test_batch_create_argument_checks(B):
+    probs = [B.Problem(64, 128, B.LOW), B.Problem(128, 64, B.LOW)]
+    arr, t = _batch(B, probs)
+    need = B.batch_workspace_bytes(probs)
+    io = (B.CCImageIO * 2)()
+    for k in range(2):
+        for name, _ in B.CCImageIO._fields_:
+            if name != "u":
+                setattr(io[k], name, 0x1000)
+    out = ctypes.c_void_p(0x1)
+    ws = ctypes.c_void_p(0x1000)
+    rc = B.lib.coolchic_batch_create(2, arr, io, ctypes.byref(t), 1.0, None, need, ctypes.byref(out))
+    assert rc == B.CC_EINVAL and not out.value
+    rc = B.lib.coolchic_batch_create(2, arr, io, ctypes.byref(t), 1.0, ws, need - 1, ctypes.byref(out))
+    assert rc == B.CC_EWORKSPACE
+    io[1].g_syn = None
+    rc = B.lib.coolchic_batch_create(2, arr, io, ctypes.byref(t), 1.0, ws, need, ctypes.byref(out))
+    assert rc == B.CC_EINVAL
+    assert B.lib.coolchic_batch_create(2, arr, None, ctypes.byref(t), 1.0, ws, need, ctypes.byref(out)) == B.CC_EINVAL
+    assert B.lib.coolchic_batch_backward(None, None) == B.CC_EINVAL
+    B.lib.coolchic_batch_destroy(None)  # no-op
