@@ -17,6 +17,8 @@ Workloads (all FP32, NumPy PCG64 ``default_rng``):
 * weights: every parameter (ARM, upsampling and synthesis, biases included)
   drawn iid from N(0, 0.1^2).
 * noise: the additive quantisation noise u ~ U[-0.5, 0.5).
+* normal_blocks: initial parameters of a network, block by block N(0, std^2)
+  (the caller gives each block's size and std).
 """
 from __future__ import annotations
 
@@ -68,6 +70,16 @@ def weights(seed: int, n: int, std: float = 0.1) -> np.ndarray:
     """n iid N(0, std^2) parameters, float32."""
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, std, size=n).astype(np.float32)
+
+
+def normal_blocks(seed: int, blocks) -> np.ndarray:
+    """Concatenated iid normal draws, block by block: blocks is a list of
+    (count, std); a block with std 0 is zeros (and draws nothing)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n, std in blocks:
+        parts.append(rng.normal(0.0, std, size=n) if std > 0 else np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def noise(seed: int, n: int) -> np.ndarray:
