@@ -201,6 +201,57 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream);
 
 void coolchic_batch_destroy(cc_batch* batch);
 
+/* ---- Learned warm start.  Section IV-B replaces overfitting by an analysis
+   transform mapping the image to the latent grids, with the decoder
+   parameters learned beside it; Section V proposes to fine-tune such an
+   output per image.  This network predicts, for a batch of images, the
+   initial latent pyramid and decoder parameters that the overfitting then
+   refines:
+     trunk   f_k = bf16(ReLU(conv3x3 stride 2 (f_{k-1}) + b_k)), k = 1..4, 32
+             channels, f_0 = bf16(x), zero padding, matrix-core products in
+             bfloat16 with FP32 accumulation;
+     latents y_l = V_l . f_l + beta_l (l = 1..4), from f_4 average-pooled by 2
+             and 4 (l = 5, 6), and y_0 = conv3x3(bf16(x)) + beta_0 + V_0 . f_1
+             repeated over 2x2 blocks;
+     decoder theta = P mean(f_4) + pi.
+   Weight matrices (conv kernels, V_l, the 3x3 level-0 kernel, P) are used
+   rounded to bfloat16; biases, beta_l and pi are used as given.
+   Master parameters (FP32, packed): for k = 1..4 W_k [32][3][3][C_in] (out,
+   ky, kx, in; C_in = 3 for k = 1, else 32) then b_k [32]; level 0: V_0 [32],
+   beta_0, K_0 [3][3][3] (ky, kx, colour); levels 1..6: V_l [32], beta_l; then
+   P [n_theta][32] and pi [n_theta], n_theta = coolchic_param_count(arch).
+   Images must be multiples of 64 on both sides and arch must have 7 levels. */
+typedef struct {
+  int32_t H, W;        /* image size (multiples of 64) */
+  int32_t batch;       /* images per call */
+  cc_arch arch;        /* decoder whose parameters are predicted */
+} cc_warm_problem;
+
+/* Packed master parameters of the network; -1 for an unsupported arch. */
+int64_t coolchic_warm_param_count(const cc_arch* arch);
+
+/* which = CC_WS_FORWARD or CC_WS_BACKWARD; 0 if the problem is invalid. */
+size_t coolchic_warm_workspace_bytes(const cc_warm_problem* p, int which);
+
+/* x [batch][3][H][W]; net: master parameters; y_out [batch][N_lat] (packed
+   pyramid of each image, the layout coolchic_forward takes); theta_out
+   [batch][n_theta] (arm, ups, syn blocks, the layout of coolchic_forward's
+   weights). */
+int coolchic_warm_forward(const cc_warm_problem* p, const float* x, const float* net, float* y_out,
+                          float* theta_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Training loss of the batch against plain-overfit targets and its gradient
+   g_net (same layout as net; overwritten).  Loss of one image: mean over its
+   latents of (y - y_target)^2 plus mean over the decoder parameters of
+   (theta - theta_target)^2; the batch loss is the mean over images.  The
+   gradient reaching each feature map is rounded to bfloat16 before the
+   convolution adjoints; a rounded weight passes its gradient to the master
+   value unchanged.  loss4 (device) = {loss, latent part, parameter part,
+   1 if anything was not finite}.  Recomputes the forward pass. */
+int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
+                           const float* theta_target, float* loss4, float* g_net, void* ws, size_t ws_bytes,
+                           void* stream);
+
 /* Static description of an error code. */
 const char* coolchic_strerror(int code);
 

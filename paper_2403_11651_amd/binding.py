@@ -23,7 +23,8 @@ CC_WS_FORWARD, CC_WS_BACKWARD, CC_WS_DECODE = 0, 1, 2
 EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_bytes", "coolchic_forward",
            "coolchic_backward", "coolchic_decode_synth", "coolchic_adam_step", "coolchic_set_stage_events",
            "coolchic_strerror", "coolchic_batch_workspace_bytes", "coolchic_batch_create",
-           "coolchic_batch_backward", "coolchic_batch_destroy")
+           "coolchic_batch_backward", "coolchic_batch_destroy", "coolchic_warm_param_count",
+           "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -35,6 +36,10 @@ class CCArch(ctypes.Structure):
 class CCProblem(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("arch", CCArch), ("quant", ctypes.c_int32),
                 ("lam", ctypes.c_float)]
+
+
+class CCWarmProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("batch", ctypes.c_int32), ("arch", CCArch)]
 
 
 class CCImageIO(ctypes.Structure):
@@ -74,6 +79,10 @@ def _load():
                                       ctypes.POINTER(P)]),
         "coolchic_batch_backward": (I, [P, P]),
         "coolchic_batch_destroy": (None, [P]),
+        "coolchic_warm_param_count": (I64, [pa]),
+        "coolchic_warm_workspace_bytes": (SZ, [ctypes.POINTER(CCWarmProblem), I]),
+        "coolchic_warm_forward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, SZ, P]),
+        "coolchic_warm_backward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -270,6 +279,58 @@ class BatchPlan:
 
     def __del__(self):
         self.close()
+
+
+@dataclass(frozen=True)
+class WarmProblem:
+    H: int
+    W: int
+    batch: int
+    arch: Arch = LOW
+
+    def c(self) -> CCWarmProblem:
+        return CCWarmProblem(self.H, self.W, self.batch, self.arch.c())
+
+
+def warm_param_count(arch: Arch) -> int:
+    n = _lib.coolchic_warm_param_count(ctypes.byref(arch.c()))
+    if n < 0:
+        raise CoolChicError(CC_EUNSUPPORTED, "coolchic_warm_param_count")
+    return int(n)
+
+
+def warm_workspace(wp: WarmProblem, which: int, device="cuda") -> torch.Tensor:
+    n = int(_lib.coolchic_warm_workspace_bytes(ctypes.byref(wp.c()), int(which)))
+    if n == 0:
+        raise CoolChicError(CC_EINVAL, "coolchic_warm_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def coolchic_warm_forward(wp: WarmProblem, x, net, y_out, theta_out, ws=None, stream=None):
+    n_lat = latent_count(Problem(wp.H, wp.W, wp.arch))
+    n_theta = sum(param_count(wp.arch))
+    if ws is None:
+        ws = warm_workspace(wp, CC_WS_FORWARD, device=x.device)
+    rc = _lib.coolchic_warm_forward(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
+                                    _ptr(net, warm_param_count(wp.arch), "net"),
+                                    _ptr(y_out, wp.batch * n_lat, "y_out"),
+                                    _ptr(theta_out, wp.batch * n_theta, "theta_out"), _ptr(ws, None, "ws"),
+                                    ws.numel(), _stream(stream))
+    _check(rc, "coolchic_warm_forward")
+
+
+def coolchic_warm_backward(wp: WarmProblem, x, net, y_target, theta_target, loss4, g_net, ws=None, stream=None):
+    n_lat = latent_count(Problem(wp.H, wp.W, wp.arch))
+    n_theta = sum(param_count(wp.arch))
+    nn = warm_param_count(wp.arch)
+    if ws is None:
+        ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
+    rc = _lib.coolchic_warm_backward(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
+                                     _ptr(net, nn, "net"), _ptr(y_target, wp.batch * n_lat, "y_target"),
+                                     _ptr(theta_target, wp.batch * n_theta, "theta_target"),
+                                     _ptr(loss4, 4, "loss4"), _ptr(g_net, nn, "g_net"), _ptr(ws, None, "ws"),
+                                     ws.numel(), _stream(stream))
+    _check(rc, "coolchic_warm_backward")
 
 
 # raw access for tests of the C ABI itself

@@ -658,7 +658,7 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
     return CC_EINVAL;
   AdamArgs a{theta, grad, m, v, n, step, lr, beta1, beta2, eps};
   const int64_t blocks = (n + 255) / 256;
-  const int grid = (int)std::min<int64_t>(blocks, 256);
+  const int grid = (int)std::min<int64_t>(blocks, 2048);
   (void)hipGetLastError();
   int rc = launch((const void*)adam_kernel, grid, 256, &a, (hipStream_t)stream);
   if (rc) return rc;
@@ -688,6 +688,229 @@ const char* coolchic_strerror(int code) {
     case CC_EHIP: return "HIP kernel launch failed";
   }
   return "unknown error code";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- warm start
+
+namespace cc {
+namespace {
+
+struct WarmPlan {
+  WarmArgs a;
+  int g_prep, g_conv[5], g_heads, g_df4, g_bd[5], g_h0, g_bw[5], g_comb;
+  size_t total;  // floats
+  CombineArgs comb;
+  FinalArgs fin;
+};
+
+int warm_check(const cc_warm_problem* p) {
+  if (!p) return CC_EINVAL;
+  if (p->H <= 0 || p->W <= 0 || p->H % 64 || p->W % 64 || p->H > 8192 || p->W > 8192) return CC_EINVAL;
+  if (p->batch < 1 || p->batch > 4096) return CC_EINVAL;
+  if (!arch_ok(&p->arch)) return CC_EUNSUPPORTED;
+  if (p->arch.n_levels != 7) return CC_EUNSUPPORTED;
+  // every index of the batch's latents and feature maps fits in 32 bits
+  if ((int64_t)p->batch * p->H * p->W * 8 >= ((int64_t)1 << 31)) return CC_EINVAL;
+  return CC_OK;
+}
+
+int64_t warm_param_count(int64_t n_theta) {
+  int64_t n = 0;
+  for (int k = 1; k <= 4; ++k) n += WS_CH * 9 * (k == 1 ? 3 : WS_CH) + WS_CH;
+  return n + 60 + 6 * 33 + 33 * n_theta;
+}
+
+// Offsets (and, with a workspace base, pointers) of every buffer.
+int warm_plan(const cc_warm_problem* p, int which, WarmPlan* P, float* base) {
+  int rc = warm_check(p);
+  if (rc) return rc;
+  if (which != CC_WS_FORWARD && which != CC_WS_BACKWARD) return CC_EINVAL;
+  std::memset(P, 0, sizeof(*P));
+  WarmArgs& a = P->a;
+  int64_t na, nu, ns;
+  counts(&p->arch, &na, &nu, &ns);
+  a.B = p->batch; a.H = p->H; a.W = p->W;
+  a.n_theta = (int)(na + nu + ns);
+  if (a.n_theta > WS_MAX_THETA) return CC_EUNSUPPORTED;
+  for (int k = 0; k <= 4; ++k) { a.h[k] = p->H >> k; a.w[k] = p->W >> k; }
+  int off = 0;
+  for (int l = 0; l < 7; ++l) {
+    a.lh[l] = p->H >> l; a.lw[l] = p->W >> l; a.loff[l] = off;
+    off += a.lh[l] * a.lw[l];
+  }
+  a.loff[7] = off;
+  a.n_lat = off;
+  int o = 0;
+  for (int k = 1; k <= 4; ++k) {
+    a.conv_off[k] = o;
+    o += WS_CH * 9 * (k == 1 ? 3 : WS_CH) + WS_CH;
+  }
+  a.head_off[0] = o;
+  for (int l = 1; l < 7; ++l) a.head_off[l] = o + 60 + 33 * (l - 1);
+  a.ptheta = a.head_off[6] + 33;
+  a.n_net = a.ptheta + 33 * a.n_theta;
+  const int B = a.B;
+  a.sy = 2.0f / ((float)a.n_lat * B);
+  a.sth = 2.0f / ((float)a.n_theta * B);
+  // grids
+  P->g_prep = std::min(cdiv(a.n_net + 5 * WS_CH, 256), 1024);
+  for (int k = 1; k <= 4; ++k) {
+    const int64_t tiles = (int64_t)B * a.h[k] * cdiv(a.w[k], 32);
+    P->g_conv[k] = (int)std::min<int64_t>((tiles + 3) / 4, 2048);
+    const int64_t chunks = ((int64_t)B * a.h[k] * a.w[k] + 15) / 16;
+    P->g_bw[k] = (int)std::max<int64_t>(1, std::min<int64_t>(256, (chunks + 15) / 16));
+  }
+  P->g_heads = (int)std::min<int64_t>(((int64_t)B * a.n_lat + 255) / 256, 2048);
+  P->g_df4 = cdiv(B * a.h[4] * a.w[4], WS_DF4_POS);
+  for (int k = 2; k <= 4; ++k) {
+    const int64_t tiles = (int64_t)B * a.h[k - 1] * 2 * cdiv(a.w[k - 1] / 2, 32);
+    P->g_bd[k] = (int)std::min<int64_t>((tiles + 3) / 4, 2048);
+  }
+  P->g_h0 = (int)std::min<int64_t>(((int64_t)B * p->H * p->W + 255) / 256, 1024);
+  // buffers (sizes in floats; bfloat16 arrays take half a float per value)
+  size_t cur = 0;
+  auto put = [&](size_t nfl) -> float* {
+    const size_t at = take(cur, nfl);
+    return base ? base + at : nullptr;
+  };
+  auto put16 = [&](size_t n16) -> uint16_t* { return (uint16_t*)put((n16 + 1) / 2); };
+  a.net_r = put(a.n_net);
+  a.wf[1] = put16(WS_CH * 32);
+  for (int k = 2; k <= 4; ++k) a.wf[k] = put16(WS_CH * 9 * WS_CH);
+  for (int k = 1; k <= 4; ++k) a.f[k] = put16((size_t)B * a.h[k] * a.w[k] * WS_CH);
+  a.gap = put((size_t)B * WS_CH);
+  if (which == CC_WS_BACKWARD) {
+    for (int k = 2; k <= 4; ++k) a.wt[k] = put16(9 * WS_CH * WS_CH);
+    for (int k = 1; k <= 4; ++k) a.dp[k] = put16((size_t)B * a.h[k] * a.w[k] * WS_CH);
+    a.y = put((size_t)B * a.n_lat);
+    a.theta = put((size_t)B * a.n_theta);
+    a.dgap = put((size_t)B * WS_CH);
+    a.lpart_y = put(P->g_heads);
+    a.lpart_th = put(B);
+    for (int k = 1; k <= 4; ++k)
+      a.part_conv[k] = put((size_t)P->g_bw[k] * (WS_CH * 9 * (k == 1 ? 3 : WS_CH) + WS_CH));
+    a.part_h456 = put((size_t)P->g_df4 * 99);
+    for (int l = 1; l <= 3; ++l) a.part_h[l] = put((size_t)P->g_bd[l + 1] * 33);
+    a.part_v0 = put((size_t)P->g_bd[2] * 32);
+    a.part_h0 = put((size_t)P->g_h0 * 28);
+    a.part_th = put((size_t)B * 33 * a.n_theta);
+    // column sums of every partial block into the gradient, in layout order
+    CombineArgs& ca = P->comb;
+    int nsg = 0, blk = 0;
+    auto seg = [&](const float* src, int rows, int cols, int dst_off) {
+      ca.seg[nsg] = RedSeg{src, rows, cols, cols, 16, (float*)(intptr_t)dst_off};
+      ca.block_start[nsg] = blk;
+      blk += cdiv(cols, 16);
+      ++nsg;
+    };
+    for (int k = 1; k <= 4; ++k)
+      seg(a.part_conv[k], P->g_bw[k], WS_CH * 9 * (k == 1 ? 3 : WS_CH) + WS_CH, a.conv_off[k]);
+    seg(a.part_v0, P->g_bd[2], 32, a.head_off[0]);
+    seg(a.part_h0, P->g_h0, 28, a.head_off[0] + 32);
+    for (int l = 1; l <= 3; ++l) seg(a.part_h[l], P->g_bd[l + 1], 33, a.head_off[l]);
+    seg(a.part_h456, P->g_df4, 99, a.head_off[4]);
+    seg(a.part_th, B, 33 * a.n_theta, a.ptheta);
+    ca.nseg = nsg;
+    ca.block_start[nsg] = blk;
+    P->g_comb = blk;
+    ca.flags = put(blk);
+    FinalArgs& fa = P->fin;
+    fa.spart = a.lpart_y; fa.ns = P->g_heads;
+    fa.rpart = a.lpart_th; fa.nr = B;
+    fa.flags = ca.flags; fa.nflags = blk;
+    fa.lambda = 1.0f; fa.inv_hw = 1.0f; fa.inv_3hw = 1.0f;
+    fa.have_rate = 1; fa.have_sse = 1;
+  }
+  P->total = cur;
+  return CC_OK;
+}
+
+int warm_forward_launches(WarmPlan& P, hipStream_t st, int bwd) {
+  int rc;
+  WarmArgs& a = P.a;
+  if ((rc = launch((const void*)warm_prep_kernel, P.g_prep, 256, &a, st))) return rc;
+  for (int k = 1; k <= 4; ++k) {
+    void* argv[] = {&a, &k};
+    if (hipLaunchKernel(warm_conv_fwd_kernel_for(k), dim3(P.g_conv[k]), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  {
+    void* argv[] = {&a, &bwd};
+    if (hipLaunchKernel((const void*)warm_heads_fwd_kernel, dim3(P.g_heads), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+    if (hipLaunchKernel((const void*)warm_theta_kernel, dim3(a.B), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  return CC_OK;
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+int64_t coolchic_warm_param_count(const cc_arch* arch) {
+  if (!arch_ok(arch)) return -1;
+  int64_t na, nu, ns;
+  counts(arch, &na, &nu, &ns);
+  if (na + nu + ns > WS_MAX_THETA) return -1;
+  return warm_param_count(na + nu + ns);
+}
+
+size_t coolchic_warm_workspace_bytes(const cc_warm_problem* p, int which) {
+  WarmPlan P;
+  if (warm_plan(p, which, &P, nullptr)) return 0;
+  return P.total * sizeof(float);
+}
+
+int coolchic_warm_forward(const cc_warm_problem* p, const float* x, const float* net, float* y_out, float* theta_out,
+                          void* ws, size_t ws_bytes, void* stream) {
+  static thread_local WarmPlan P;
+  int rc = warm_plan(p, CC_WS_FORWARD, &P, nullptr);
+  if (rc) return rc;
+  if (!x || !net || !y_out || !theta_out || !ws) return CC_EINVAL;
+  if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
+  warm_plan(p, CC_WS_FORWARD, &P, (float*)ws);
+  P.a.x = x; P.a.net = net; P.a.y = y_out; P.a.theta = theta_out;
+  P.a.f[0] = nullptr;
+  (void)hipGetLastError();
+  if ((rc = warm_forward_launches(P, (hipStream_t)stream, 0))) return rc;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
+                           const float* theta_target, float* loss4, float* g_net, void* ws, size_t ws_bytes,
+                           void* stream) {
+  static thread_local WarmPlan P;
+  int rc = warm_plan(p, CC_WS_BACKWARD, &P, nullptr);
+  if (rc) return rc;
+  if (!x || !net || !y_target || !theta_target || !loss4 || !g_net || !ws) return CC_EINVAL;
+  if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
+  warm_plan(p, CC_WS_BACKWARD, &P, (float*)ws);
+  WarmArgs& a = P.a;
+  a.x = x; a.net = net; a.y_t = y_target; a.th_t = theta_target;
+  for (int s = 0; s < P.comb.nseg; ++s) P.comb.seg[s].dst = g_net + (intptr_t)P.comb.seg[s].dst;
+  P.fin.loss4 = loss4;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if ((rc = warm_forward_launches(P, st, 1))) return rc;
+  if ((rc = launch((const void*)warm_df4_kernel, P.g_df4, 256, &a, st))) return rc;
+  for (int k = 4; k >= 2; --k) {
+    void* argv[] = {&a, &k};
+    if (hipLaunchKernel((const void*)warm_bwd_data_kernel, dim3(P.g_bd[k]), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  if ((rc = launch((const void*)warm_head0_grad_kernel, P.g_h0, 256, &a, st))) return rc;
+  for (int k = 1; k <= 4; ++k) {
+    void* argv[] = {&a, &k};
+    if (hipLaunchKernel(warm_bwd_weight_kernel_for(k), dim3(P.g_bw[k]), dim3(256), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  if ((rc = launch((const void*)combine_kernel, P.g_comb, 256, &P.comb, st))) return rc;
+  if ((rc = launch((const void*)finalize_kernel, 1, 256, &P.fin, st))) return rc;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
 }  // extern "C"

@@ -146,4 +146,52 @@ struct AdamArgs {
 };
 __global__ void adam_kernel(AdamArgs a);
 
+// ---------------------------------------------------------------- warm start
+constexpr int WS_CH = 32;          // trunk width
+constexpr int WS_MAX_THETA = 4096; // decoder parameters the head can predict
+
+// Level k = 0..4 of the trunk: k = 0 is the image (3 planar FP32 channels),
+// k >= 1 the bfloat16 feature maps f_k [B][h_k][w_k][32] (channels last).
+// The latent pyramid of each image is packed level by level (7 levels).
+struct WarmArgs {
+  int B, H, W;
+  int h[5], w[5];
+  int n_lat, n_theta, n_net;
+  int loff[8], lh[8], lw[8];
+  int conv_off[5];     // offset of W_k in the master vector (k = 1..4); b_k follows W_k
+  int head_off[7];     // level l head block: V_l[32], beta_l (level 0: then K_0[27])
+  int ptheta;          // P [n_theta][32], then pi [n_theta]
+  const float* x;      // [B][3][H][W]
+  const float* net;    // master parameters
+  float* net_r;        // the same with every weight matrix rounded to bfloat16
+  uint16_t* wf[5];     // forward operands [32][K] (K = 32 for k = 1, 288 otherwise)
+  uint16_t* wt[5];     // data-adjoint operands [9][32 in][32 out] (k >= 2)
+  uint16_t* f[5];      // feature maps (k >= 1)
+  uint16_t* dp[5];     // gradient at the pre-activation, rounded (k >= 1)
+  float* y;            // [B][n_lat] predicted latents
+  float* theta;        // [B][n_theta] predicted decoder parameters
+  const float* y_t;    // backward: targets
+  const float* th_t;
+  float sy, sth;       // 2 / (n_lat B), 2 / (n_theta B)
+  float* gap;          // [B][32]
+  float* dgap;         // [B][32]
+  float* lpart_y;      // [heads grid] latent-loss partials
+  float* lpart_th;     // [B] parameter-loss partials
+  float* part_conv[5]; // [grid][32 * 9 * C_in + 32] conv weight / bias gradient partials
+  float* part_h456;    // [grid][99] heads 4, 5, 6
+  float* part_h[4];    // levels 1..3: [grid][33]
+  float* part_v0;      // [grid][32] V_0 (level-0 path through f_1)
+  float* part_h0;      // [grid][28] beta_0, K_0
+  float* part_th;      // [B][33 n_theta] P, pi
+};
+__global__ void warm_prep_kernel(WarmArgs a);
+__global__ void warm_heads_fwd_kernel(WarmArgs a, int with_loss);
+__global__ void warm_theta_kernel(WarmArgs a, int bwd);
+__global__ void warm_df4_kernel(WarmArgs a);
+__global__ void warm_head0_grad_kernel(WarmArgs a);
+__global__ void warm_bwd_data_kernel(WarmArgs a, int k);
+const void* warm_conv_fwd_kernel_for(int k);
+const void* warm_bwd_weight_kernel_for(int k);
+constexpr int WS_DF4_POS = 64;     // f_4 positions per block of warm_df4_kernel
+
 }  // namespace cc

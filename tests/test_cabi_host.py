@@ -126,3 +126,29 @@ def test_batch_create_argument_checks(B):
     assert B.lib.coolchic_batch_create(2, arr, None, ctypes.byref(t), 1.0, ws, need, ctypes.byref(out)) == B.CC_EINVAL
     assert B.lib.coolchic_batch_backward(None, None) == B.CC_EINVAL
     B.lib.coolchic_batch_destroy(None)  # no-op
+
+
+def test_warm_param_count_matches_oracle(B):
+    from oracle import warmstart as WS
+    for arch in (B.LOW, B.FULL, B.Arch(7, 16, 1, 8, 24, 1)):
+        n_theta = sum(B.param_count(arch))
+        assert B.warm_param_count(arch) == WS.WarmLayout(n_theta).size
+    assert B.lib.coolchic_warm_param_count(ctypes.byref(B.Arch(7, 12, 2, 8, 16, 1).c())) == -1
+
+
+def test_warm_workspace_and_invalid_problems(B):
+    ws = lambda wp, w: B.lib.coolchic_warm_workspace_bytes(ctypes.byref(wp.c()), w)
+    ok = B.WarmProblem(512, 768, 4)
+    f, b = ws(ok, 0), ws(ok, 1)
+    assert 0 < f < b
+    assert ws(B.WarmProblem(512, 768, 8), 1) > b
+    for bad in (B.WarmProblem(500, 768, 1), B.WarmProblem(512, 760, 1), B.WarmProblem(512, 768, 0),
+                B.WarmProblem(512, 768, 1, B.Arch(6, 8, 2, 8, 16, 1)), B.WarmProblem(8192, 8192, 64)):
+        assert ws(bad, 1) == 0
+    assert ws(ok, 2) == 0
+    d = ctypes.c_void_p(0x1000)
+    pc = ok.c()
+    assert B.lib.coolchic_warm_forward(ctypes.byref(pc), d, d, d, None, d, f, None) == B.CC_EINVAL
+    assert B.lib.coolchic_warm_forward(ctypes.byref(pc), d, d, d, d, d, f - 1, None) == B.CC_EWORKSPACE
+    assert B.lib.coolchic_warm_backward(ctypes.byref(pc), d, d, d, d, d, None, d, b, None) == B.CC_EINVAL
+    assert B.lib.coolchic_warm_backward(ctypes.byref(pc), d, d, d, d, d, d, d, b - 1, None) == B.CC_EWORKSPACE

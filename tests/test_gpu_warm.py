@@ -1,0 +1,142 @@
+"""GPU parity of the warm-start network (bfloat16 matrix-core kernels) against
+the FP64 oracle with the same rounding points.
+
+Bars: predicted latents and decoder parameters within 1e-4 relative in the
+2-norm and 1e-3 * max|ref| element by element; loss within 1e-5 relative;
+every gradient block within 1e-3 relative in the 2-norm.  The FP32
+accumulation differs from the FP64 oracle only by rounding, except where a
+feature value or feature gradient lies within that rounding of a bfloat16
+rounding boundary: such an element rounds the other way (one bfloat16 step,
+2^-8 relative) -- rare, and far inside these bars."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import warmstart as WS
+from paper_2403_11651_amd import workloads as WL
+from tests.test_oracle_warm import _net
+
+pytestmark = pytest.mark.gpu
+N_THETA = 521
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_11651_amd import binding
+    return binding
+
+
+def make(H, W, n, seed):
+    xs = [WL.image(seed + i, H, W, max(4, H * W // 2000)) for i in range(n)]
+    ys = [WL.latents(seed + 100 + i, H, W, 7) for i in range(n)]
+    ths = [WL.weights(seed + 200 + i, N_THETA) for i in range(n)]
+    return xs, ys, ths
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def gpu_forward(B, H, W, xs, net):
+    wp = B.WarmProblem(H, W, len(xs), B.LOW)
+    n_lat = B.latent_count(B.Problem(H, W, B.LOW))
+    y = torch.full((len(xs), n_lat), float("nan"), device="cuda")
+    th = torch.full((len(xs), N_THETA), float("nan"), device="cuda")
+    B.coolchic_warm_forward(wp, dev(np.stack(xs)), dev(net), y, th)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), th.cpu().numpy()
+
+
+def gpu_backward(B, H, W, xs, net, ys, ths):
+    wp = B.WarmProblem(H, W, len(xs), B.LOW)
+    loss4 = torch.zeros(4, device="cuda")
+    g = torch.full((net.size,), float("nan"), device="cuda")
+    B.coolchic_warm_backward(wp, dev(np.stack(xs)), dev(net), dev(np.stack(ys)), dev(np.stack(ths)), loss4, g)
+    torch.cuda.synchronize()
+    return loss4.cpu().numpy(), g.cpu().numpy()
+
+
+def close(name, got, ref, rel=1e-4, elem=1e-3):
+    got = np.asarray(got, np.float64)
+    assert np.all(np.isfinite(got)), name
+    nrm = np.linalg.norm(ref)
+    assert np.linalg.norm(got - ref) <= rel * nrm, (name, np.linalg.norm(got - ref) / nrm)
+    assert np.max(np.abs(got - ref)) <= elem * np.max(np.abs(ref)), (name, np.max(np.abs(got - ref)))
+
+
+def blocks():
+    lay = WS.WarmLayout(N_THETA)
+    out = []
+    for k in range(1, 5):
+        off, shape = lay.conv(k)
+        n = int(np.prod(shape))
+        out += [(f"W{k}", off, off + n), (f"b{k}", off + n, off + n + 32)]
+    out += [("heads", lay.heads, lay.ptheta), ("P", lay.ptheta, lay.ptheta + 32 * N_THETA),
+            ("pi", lay.ptheta + 32 * N_THETA, lay.size)]
+    return out
+
+
+CASES = [(64, 64, 2, 10), (64, 192, 3, 20), (128, 128, 1, 30), (192, 64, 2, 40)]
+
+
+@pytest.mark.parametrize("H,W,n,seed", CASES)
+def test_warm_forward_matches_oracle(B, H, W, n, seed):
+    xs, _, _ = make(H, W, n, seed)
+    net = _net(seed)
+    y, th = gpu_forward(B, H, W, xs, net)
+    for i, x in enumerate(xs):
+        ref = WS.forward(x.astype(np.float64), net.astype(np.float32).astype(np.float64), N_THETA)
+        close(f"y[{i}]", y[i], WS.pack_levels(ref["y"]))
+        close(f"theta[{i}]", th[i], ref["theta"])
+
+
+@pytest.mark.parametrize("H,W,n,seed", CASES)
+def test_warm_backward_matches_oracle(B, H, W, n, seed):
+    xs, ys, ths = make(H, W, n, seed)
+    net = _net(seed + 1).astype(np.float32)
+    l4, g = gpu_backward(B, H, W, xs, net, ys, ths)
+    L, gref = WS.batch_backward([x.astype(np.float64) for x in xs], net.astype(np.float64), N_THETA,
+                                [y.astype(np.float64) for y in ys], [t.astype(np.float64) for t in ths])
+    assert l4[3] == 0.0
+    assert abs(l4[0] - L) <= 1e-5 * abs(L), (l4, L)
+    assert abs(l4[1] + l4[2] - l4[0]) <= 1e-6 * abs(l4[0])
+    for name, lo, hi in blocks():
+        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-2)
+
+
+def test_warm_full_size_matches_oracle(B):
+    """768x512, the size the network is trained and evaluated at."""
+    H, W = 512, 768
+    xs, ys, ths = make(H, W, 1, 50)
+    xs = [WL.image(50, H, W, 200)]
+    net = _net(51).astype(np.float32)
+    y, th = gpu_forward(B, H, W, xs, net)
+    ref = WS.forward(xs[0].astype(np.float64), net.astype(np.float64), N_THETA)
+    close("y", y[0], WS.pack_levels(ref["y"]))
+    close("theta", th[0], ref["theta"])
+    l4, g = gpu_backward(B, H, W, xs, net, ys, ths)
+    L, gref = WS.backward(xs[0].astype(np.float64), net.astype(np.float64), N_THETA, ys[0].astype(np.float64),
+                          ths[0].astype(np.float64))
+    assert abs(l4[0] - L) <= 1e-5 * abs(L)
+    for name, lo, hi in blocks():
+        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-2)
+
+
+def test_warm_backward_deterministic(B):
+    H, W = 128, 192
+    xs, ys, ths = make(H, W, 2, 60)
+    net = _net(61).astype(np.float32)
+    a = gpu_backward(B, H, W, xs, net, ys, ths)
+    b = gpu_backward(B, H, W, xs, net, ys, ths)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_warm_nonfinite_flag(B):
+    H, W = 64, 64
+    xs, ys, ths = make(H, W, 1, 70)
+    ys[0] = ys[0].copy()
+    ys[0][5] = np.inf
+    l4, _ = gpu_backward(B, H, W, xs, _net(71).astype(np.float32), ys, ths)
+    assert l4[3] == 1.0
