@@ -148,6 +148,17 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
 enum { CC_STAGE_NONE = 0, CC_STAGE_ARM = 1, CC_STAGE_SYNTHESIS = 2 };
 int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end);
 
+/* Uniform noise u in [-1/2, 1/2) for the training proxy y_hat = y + u
+   (Section II "Encoding": the latents are optimised through a
+   differentiable proxy of the quantisation).  u[4g + e] = (w_e >> 8) 2^-24
+   - 1/2, where (w_0..w_3) = Philox4x32-10 (Salmon et al., SC 2011) of the
+   counter (g mod 2^32, g >> 32, it, stream_id) under the key (seed mod 2^32,
+   seed >> 32), and it = *step (a device int32, e.g. the step counter that
+   coolchic_adam_step advances, so that a captured graph draws fresh noise on
+   every replay) or 0 when step is NULL.  Enqueued on stream. */
+int coolchic_uniform_noise(float* u, int64_t n, uint64_t seed, const int32_t* step, uint32_t stream_id,
+                           void* stream);
+
 /* ---- Batched overfitting: many images of uneven sizes in one launch per
    stage.  Every image has its own latents, parameters and outputs; all share
    one architecture (and quantiser).  coolchic_batch_create lays out, in the
@@ -251,6 +262,16 @@ int coolchic_warm_forward(const cc_warm_problem* p, const float* x, const float*
 int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
                            const float* theta_target, float* loss4, float* g_net, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* Gradient g_net of an outer loss given its gradients g_y [batch][N_lat] and
+   g_theta [batch][n_theta] with respect to the network's outputs (for
+   instance the rate-distortion loss of Eq. (1) of the predicted latents and
+   decoder, as coolchic_backward gives it), with the rounding points of
+   coolchic_warm_backward.  loss4 = {0, 0, 0, non-finite flag}.  Recomputes
+   the forward pass. */
+int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const float* net, const float* g_y,
+                                const float* g_theta, float* loss4, float* g_net, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* Static description of an error code. */
 const char* coolchic_strerror(int code);

@@ -228,14 +228,26 @@ def loss(out, y_target, theta_target):
 def backward(x, net, n_theta, y_target, theta_target, round_bf16=True, weight=1.0):
     """Loss of one image (times weight) and its gradient with respect to the
     packed master parameters (hand-written adjoint of forward)."""
-    R = _r(round_bf16)
     out = forward(x, net, n_theta, round_bf16)
-    f, q, y = out["f"], out["q"], out["y"]
-    yv = pack_levels(y)
-    n_lat = yv.size
+    yv = pack_levels(out["y"])
     L = weight * loss(out, y_target, theta_target)
-    dyv = weight * 2.0 * (yv - y_target) / n_lat
+    dyv = weight * 2.0 * (yv - y_target) / yv.size
     dth = weight * 2.0 * (out["theta"] - theta_target) / n_theta
+    return L, adjoint(out, n_theta, dyv, dth, round_bf16)
+
+
+def backward_from_grads(x, net, n_theta, dy_packed, dtheta, round_bf16=True):
+    """Gradient with respect to the packed master parameters of an outer loss
+    whose gradients with respect to the outputs (packed latents, decoder
+    parameters) are given."""
+    out = forward(x, net, n_theta, round_bf16)
+    return adjoint(out, n_theta, np.asarray(dy_packed, np.float64), np.asarray(dtheta, np.float64), round_bf16)
+
+
+def adjoint(out, n_theta, dyv, dth, round_bf16=True):
+    """Reverse pass of forward() for output gradients (dyv packed, dth)."""
+    R = _r(round_bf16)
+    f, q, y = out["f"], out["q"], out["y"]
     dy, o = [], 0
     for a in y:
         dy.append(dyv[o:o + a.size].reshape(a.shape))
@@ -277,7 +289,7 @@ def backward(x, net, n_theta, y_target, theta_target, round_bf16=True, weight=1.
         dfin, g[f"W{k}"], g[f"b{k}"] = conv3x3_s2_adjoint(f[k - 1], q[f"W{k}"], dpre)
         if k > 1:
             df[k - 1] = dfin
-    return L, pack(g, n_theta)
+    return pack(g, n_theta)
 
 
 def batch_backward(xs, net, n_theta, ys, thetas, round_bf16=True):

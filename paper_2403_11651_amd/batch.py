@@ -14,6 +14,7 @@ caches the choice per device, architecture and image-size list.
 """
 from __future__ import annotations
 
+import dataclasses
 import hashlib
 import json
 import os
@@ -26,35 +27,40 @@ from . import binding as B
 
 
 class BatchEncoder:
-    """Overfits n images at once (quantiser: rounding with straight-through
-    gradient).  `images[k]` is planar [3][H][W] float32; `y0[k]` the packed
-    initial latent pyramid; `params0[k]` the initial (arm, ups, syn) blocks.
+    """Overfits n images at once.  `images[k]` is planar [3][H][W] float32;
+    `y0[k]` the packed initial latent pyramid; `params0[k]` the initial
+    (arm, ups, syn) blocks.
 
     Parameters of image k live in one flat buffer, segment k = [y | arm | ups |
     syn], with matching gradient and Adam moment buffers, so a single Adam
-    launch updates every image."""
+    launch updates every image.  The quantisation proxy is a mode: rounding
+    with a straight-through gradient (CC_QUANT_ROUND, the default) or additive
+    uniform noise (CC_QUANT_NOISE), drawn on the device every iteration from
+    the Philox generator keyed by `noise_seed` and the step counter."""
 
-    def __init__(self, problems, images, y0, params0, lr=1e-2, tune=(0, 0), device="cuda"):
+    def __init__(self, problems, images, y0, params0, lr=1e-2, tune=(0, 0), noise_seed=0, device="cuda"):
         n = len(problems)
         if not (n and len(images) == n and len(y0) == n and len(params0) == n):
             raise ValueError("problems, images, y0 and params0 must be equally long and non-empty")
         arch = problems[0].arch
         for p in problems:
-            if p.arch != arch or p.quant != B.CC_QUANT_ROUND:
-                raise ValueError("every image must share one architecture and use the rounding quantiser")
+            if p.arch != arch:
+                raise ValueError("every image must share one architecture")
         self.device = torch.device(device)
-        self.problems = list(problems)
+        self.problems = [dataclasses.replace(p, quant=B.CC_QUANT_ROUND) for p in problems]
         self.lr = float(lr)
+        self.noise_seed = int(noise_seed)
         na, nu, ns = B.param_count(arch)
-        self.seg = []  # (offset, n_lat) per image
-        off = 0
+        self.seg = []  # (offset, n_lat, offset in the noise buffer) per image
+        off = uoff = 0
         for p in problems:
             n_lat = B.latent_count(p)
-            self.seg.append((off, n_lat))
+            self.seg.append((off, n_lat, uoff))
             off += n_lat + na + nu + ns
+            uoff += n_lat
         self.n_params = off
         flat = np.empty(off, np.float32)
-        for (o, n_lat), y, (a, u, s) in zip(self.seg, y0, params0):
+        for (o, n_lat, _), y, (a, u, s) in zip(self.seg, y0, params0):
             flat[o:o + n_lat] = y
             flat[o + n_lat:o + n_lat + na] = a
             flat[o + n_lat + na:o + n_lat + na + nu] = u
@@ -64,16 +70,19 @@ class BatchEncoder:
         self.grad = torch.zeros_like(self.theta)
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
+        self.u = torch.zeros(uoff, device=dev)
         self.step_ctr = torch.zeros(2, dtype=torch.int32, device=dev)
         self.loss = torch.zeros(n, 4, device=dev)
         self.images = [torch.from_numpy(np.ascontiguousarray(x, np.float32).reshape(-1)).to(dev) for x in images]
         self._na, self._nu, self._ns = na, nu, ns
-        self.plan = None
-        self.set_tuning(tune)
+        self.plans = {}
+        self.mode = B.CC_QUANT_ROUND
+        self.tune = tuple(int(t) for t in tune)
+        self.plan = self._plan(self.mode)
 
     # -- views of image k's parameters and gradients
     def _views(self, buf, k):
-        o, n_lat = self.seg[k]
+        o, n_lat, _ = self.seg[k]
         na, nu, ns = self._na, self._nu, self._ns
         return (buf[o:o + n_lat], buf[o + n_lat:o + n_lat + na], buf[o + n_lat + na:o + n_lat + na + nu],
                 buf[o + n_lat + na + nu:o + n_lat + na + nu + ns])
@@ -84,42 +93,77 @@ class BatchEncoder:
     def grads(self, k):
         return tuple(t.detach().cpu().numpy() for t in self._views(self.grad, k))
 
+    def _plan(self, mode):
+        if mode not in self.plans:
+            io = []
+            for k in range(len(self.problems)):
+                y, a, u, s = self._views(self.theta, k)
+                gy, ga, gu, gs = self._views(self.grad, k)
+                _, n_lat, uo = self.seg[k]
+                io.append(dict(img=self.images[k], y=y, u=self.u[uo:uo + n_lat] if mode == B.CC_QUANT_NOISE else None,
+                               arm_w=a, ups_w=u, syn_w=s, loss4=self.loss[k], g_y=gy, g_arm=ga, g_ups=gu, g_syn=gs))
+            probs = [dataclasses.replace(p, quant=mode) for p in self.problems]
+            self.plans[mode] = B.BatchPlan(probs, io, tune=self.tune, device=self.device)
+        return self.plans[mode]
+
     def set_tuning(self, tune):
-        io = []
-        for k in range(len(self.problems)):
-            y, a, u, s = self._views(self.theta, k)
-            gy, ga, gu, gs = self._views(self.grad, k)
-            io.append(dict(img=self.images[k], y=y, u=None, arm_w=a, ups_w=u, syn_w=s, loss4=self.loss[k],
-                           g_y=gy, g_arm=ga, g_ups=gu, g_syn=gs))
-        if self.plan is not None:
-            self.plan.close()
-        self.plan = B.BatchPlan(self.problems, io, tune=tune, device=self.device)
-        self.tune = self.plan.tune
+        tune = tuple(int(t) for t in tune)
+        if tune != self.tune:
+            for p in self.plans.values():
+                p.close()
+            self.plans = {}
+            self.tune = tune
+        self.plan = self._plan(self.mode)
+
+    def set_mode(self, mode):
+        """CC_QUANT_ROUND or CC_QUANT_NOISE for the following iterations."""
+        if mode not in (B.CC_QUANT_ROUND, B.CC_QUANT_NOISE):
+            raise ValueError("unknown quantisation mode")
+        self.mode = mode
+        self.plan = self._plan(mode)
+
+    def _draw(self, stream=None):
+        B.coolchic_uniform_noise(self.u, self.noise_seed, step=self.step_ctr, stream=stream)
 
     def backward(self, stream=None):
-        """Loss and gradients of every image (written to self.loss, self.grad)."""
+        """Loss and gradients of every image (written to self.loss, self.grad)
+        at the current parameters, in the current mode."""
+        if self.mode == B.CC_QUANT_NOISE:
+            self._draw(stream)
         self.plan.backward(stream)
 
     def step(self, stream=None):
         """One training iteration of every image."""
-        self.plan.backward(stream)
+        self.backward(stream)
         B.coolchic_adam_step(self.theta, self.grad, self.m, self.v, self.step_ctr, lr=self.lr, stream=stream)
 
-    def capture(self, k):
-        """A HIP graph of k training iterations.  Runs one backward pass first
-        (outside the graph; it leaves the parameters unchanged) so that every
-        stream and event the library uses exists before capture."""
-        self.plan.backward()
+    def probe(self, stream=None):
+        """Loss (and gradients) of the current parameters with the rounding
+        quantiser, whatever the training mode: the rate-distortion cost the
+        decoder will actually see."""
+        self._plan(B.CC_QUANT_ROUND).backward(stream)
+
+    def capture(self, k, probe=False):
+        """A HIP graph of k training iterations in the current mode (then, with
+        probe, the rounding-mode loss of the result).  Runs one backward pass
+        first (outside the graph; it leaves the parameters unchanged) so that
+        every stream and event the library uses exists before capture."""
+        self.backward()
         torch.cuda.synchronize(self.device)
         g = torch.cuda.CUDAGraph()
+        if probe:
+            self.probe()
+        torch.cuda.synchronize(self.device)
         with torch.cuda.graph(g):
             for _ in range(k):
                 self.step()
+            if probe:
+                self.probe()
         return g
 
     def run(self, iters, graph_steps=50):
-        """iters training iterations, replaying a captured graph of
-        graph_steps iterations (the remainder eagerly)."""
+        """iters training iterations in the current mode, replaying a captured
+        graph of graph_steps iterations (the remainder eagerly)."""
         if iters >= graph_steps > 0:
             g = self.capture(graph_steps)
             for _ in range(iters // graph_steps):
@@ -129,6 +173,15 @@ class BatchEncoder:
             rem = iters
         for _ in range(rem):
             self.step()
+
+    def fit(self, iters, noise_frac=0.8, graph_steps=50):
+        """The two-phase schedule: noise proxy for the first noise_frac of the
+        iterations, then rounding with the straight-through gradient."""
+        n_noise = int(round(iters * noise_frac))
+        self.set_mode(B.CC_QUANT_NOISE)
+        self.run(n_noise, graph_steps)
+        self.set_mode(B.CC_QUANT_ROUND)
+        self.run(iters - n_noise, graph_steps)
 
     def save(self):
         return [t.clone() for t in (self.theta, self.m, self.v, self.step_ctr, self.loss)]

@@ -24,7 +24,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_backward", "coolchic_decode_synth", "coolchic_adam_step", "coolchic_set_stage_events",
            "coolchic_strerror", "coolchic_batch_workspace_bytes", "coolchic_batch_create",
            "coolchic_batch_backward", "coolchic_batch_destroy", "coolchic_warm_param_count",
-           "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward")
+           "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward",
+           "coolchic_uniform_noise", "coolchic_warm_backward_grad")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -79,10 +80,12 @@ def _load():
                                       ctypes.POINTER(P)]),
         "coolchic_batch_backward": (I, [P, P]),
         "coolchic_batch_destroy": (None, [P]),
+        "coolchic_uniform_noise": (I, [P, I64, ctypes.c_uint64, P, ctypes.c_uint32, P]),
         "coolchic_warm_param_count": (I64, [pa]),
         "coolchic_warm_workspace_bytes": (SZ, [ctypes.POINTER(CCWarmProblem), I]),
         "coolchic_warm_forward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, SZ, P]),
         "coolchic_warm_backward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, P, P, SZ, P]),
+        "coolchic_warm_backward_grad": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -227,6 +230,17 @@ def coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, beta1=0.9, beta2=0.999,
     _check(rc, "coolchic_adam_step")
 
 
+def coolchic_uniform_noise(u, seed: int, step=None, stream_id: int = 0, stream=None):
+    """Fill u (device float32) with Philox uniform noise in [-1/2, 1/2);
+    step: device int32 tensor whose first element is the iteration, or None."""
+    if step is not None and (step.dtype != torch.int32 or not step.is_cuda):
+        raise TypeError("step must be a device int32 tensor")
+    rc = _lib.coolchic_uniform_noise(_ptr(u, None, "u"), u.numel(), int(seed) & ((1 << 64) - 1),
+                                     None if step is None else step.data_ptr(), int(stream_id) & 0xffffffff,
+                                     _stream(stream))
+    _check(rc, "coolchic_uniform_noise")
+
+
 def coolchic_set_stage_events(stage: int, ev_begin=None, ev_end=None):
     """ev_begin / ev_end: raw hipEvent_t handles (ints) or None."""
     _check(_lib.coolchic_set_stage_events(int(stage), ev_begin, ev_end), "coolchic_set_stage_events")
@@ -331,6 +345,20 @@ def coolchic_warm_backward(wp: WarmProblem, x, net, y_target, theta_target, loss
                                      _ptr(loss4, 4, "loss4"), _ptr(g_net, nn, "g_net"), _ptr(ws, None, "ws"),
                                      ws.numel(), _stream(stream))
     _check(rc, "coolchic_warm_backward")
+
+
+def coolchic_warm_backward_grad(wp: WarmProblem, x, net, g_y, g_theta, loss4, g_net, ws=None, stream=None):
+    n_lat = latent_count(Problem(wp.H, wp.W, wp.arch))
+    n_theta = sum(param_count(wp.arch))
+    nn = warm_param_count(wp.arch)
+    if ws is None:
+        ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
+    rc = _lib.coolchic_warm_backward_grad(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
+                                          _ptr(net, nn, "net"), _ptr(g_y, wp.batch * n_lat, "g_y"),
+                                          _ptr(g_theta, wp.batch * n_theta, "g_theta"), _ptr(loss4, 4, "loss4"),
+                                          _ptr(g_net, nn, "g_net"), _ptr(ws, None, "ws"), ws.numel(),
+                                          _stream(stream))
+    _check(rc, "coolchic_warm_backward_grad")
 
 
 # raw access for tests of the C ABI itself

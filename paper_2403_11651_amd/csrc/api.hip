@@ -666,6 +666,19 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
+int coolchic_uniform_noise(float* u, int64_t n, uint64_t seed, const int32_t* step, uint32_t stream_id,
+                           void* stream) {
+  if (!u || n <= 0) return CC_EINVAL;
+  const int64_t groups = (n + 3) / 4;
+  const int grid = (int)std::min<int64_t>((groups + 255) / 256, 2048);
+  (void)hipGetLastError();
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  void* argv[] = {&u, &n, (void*)&k0, (void*)&k1, &step, &stream_id};
+  if (hipLaunchKernel((const void*)noise_kernel, dim3(grid), dim3(256), argv, 0, (hipStream_t)stream) != hipSuccess)
+    return CC_EHIP;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
 int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end) {
   if (stage == CC_STAGE_NONE) {
     g_stage = CC_STAGE_NONE;
@@ -880,17 +893,23 @@ int coolchic_warm_forward(const cc_warm_problem* p, const float* x, const float*
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
-int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
-                           const float* theta_target, float* loss4, float* g_net, void* ws, size_t ws_bytes,
-                           void* stream) {
+}  // extern "C"
+
+namespace cc {
+namespace {
+
+int warm_backward_impl(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
+                       const float* theta_target, const float* g_y, const float* g_theta, float* loss4, float* g_net,
+                       void* ws, size_t ws_bytes, void* stream) {
   static thread_local WarmPlan P;
   int rc = warm_plan(p, CC_WS_BACKWARD, &P, nullptr);
   if (rc) return rc;
-  if (!x || !net || !y_target || !theta_target || !loss4 || !g_net || !ws) return CC_EINVAL;
+  const bool regress = y_target && theta_target, given = g_y && g_theta;
+  if (!x || !net || regress == given || !loss4 || !g_net || !ws) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   warm_plan(p, CC_WS_BACKWARD, &P, (float*)ws);
   WarmArgs& a = P.a;
-  a.x = x; a.net = net; a.y_t = y_target; a.th_t = theta_target;
+  a.x = x; a.net = net; a.y_t = y_target; a.th_t = theta_target; a.gy_in = g_y; a.gth_in = g_theta;
   for (int s = 0; s < P.comb.nseg; ++s) P.comb.seg[s].dst = g_net + (intptr_t)P.comb.seg[s].dst;
   P.fin.loss4 = loss4;
   hipStream_t st = (hipStream_t)stream;
@@ -911,6 +930,26 @@ int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float
   if ((rc = launch((const void*)combine_kernel, P.g_comb, 256, &P.comb, st))) return rc;
   if ((rc = launch((const void*)finalize_kernel, 1, 256, &P.fin, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+int coolchic_warm_backward(const cc_warm_problem* p, const float* x, const float* net, const float* y_target,
+                           const float* theta_target, float* loss4, float* g_net, void* ws, size_t ws_bytes,
+                           void* stream) {
+  if (!y_target || !theta_target) return CC_EINVAL;
+  return warm_backward_impl(p, x, net, y_target, theta_target, nullptr, nullptr, loss4, g_net, ws, ws_bytes,
+                            stream);
+}
+
+int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const float* net, const float* g_y,
+                                const float* g_theta, float* loss4, float* g_net, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!g_y || !g_theta) return CC_EINVAL;
+  return warm_backward_impl(p, x, net, nullptr, nullptr, g_y, g_theta, loss4, g_net, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

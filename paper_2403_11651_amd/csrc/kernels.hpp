@@ -145,6 +145,7 @@ struct AdamArgs {
   float lr, beta1, beta2, eps;
 };
 __global__ void adam_kernel(AdamArgs a);
+__global__ void noise_kernel(float* u, int64_t n, uint32_t k0, uint32_t k1, const int32_t* step, uint32_t stream_id);
 
 // ---------------------------------------------------------------- warm start
 constexpr int WS_CH = 32;          // trunk width
@@ -170,8 +171,10 @@ struct WarmArgs {
   uint16_t* dp[5];     // gradient at the pre-activation, rounded (k >= 1)
   float* y;            // [B][n_lat] predicted latents
   float* theta;        // [B][n_theta] predicted decoder parameters
-  const float* y_t;    // backward: targets
+  const float* y_t;    // backward: targets (regression loss), or
   const float* th_t;
+  const float* gy_in;  // backward: given gradients of an outer loss w.r.t. y and theta
+  const float* gth_in;
   float sy, sth;       // 2 / (n_lat B), 2 / (n_theta B)
   float* gap;          // [B][32]
   float* dgap;         // [B][32]

@@ -55,10 +55,11 @@ __device__ __forceinline__ void load_feat(const uint16_t* p, float (&v)[WS_CH]) 
   }
 }
 
-// dy of latent q (packed index) of image b; sy = 2 / (n_lat B)
+// Gradient of the loss w.r.t. latent q (packed index) of image b: given by
+// the caller, or that of the regression loss (sy = 2 / (n_lat B)).
 __device__ __forceinline__ float dlat(const WarmArgs& a, int b, int q) {
   const size_t i = (size_t)b * a.n_lat + q;
-  return (a.y[i] - a.y_t[i]) * a.sy;
+  return a.gy_in ? a.gy_in[i] : (a.y[i] - a.y_t[i]) * a.sy;
 }
 
 // ------------------------------------------------------------ parameters
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(256) void warm_heads_fwd_kernel(WarmArgs a, int wit
       yv += acc;
     }
     a.y[t] = yv;
-    if (with_loss) {
+    if (with_loss && a.y_t) {
       const float d = yv - a.y_t[t];
       lp += d * d;
     }
@@ -257,9 +258,14 @@ __global__ __launch_bounds__(256) void warm_theta_kernel(WarmArgs a, int bwd) {
     const float th = acc + pi[t];
     a.theta[(size_t)b * a.n_theta + t] = th;
     if (bwd) {
-      const float d = th - a.th_t[(size_t)b * a.n_theta + t];
-      lp += d * d;
-      const float dth = d * a.sth;
+      float dth;
+      if (a.gth_in) {
+        dth = a.gth_in[(size_t)b * a.n_theta + t];
+      } else {
+        const float d = th - a.th_t[(size_t)b * a.n_theta + t];
+        lp += d * d;
+        dth = d * a.sth;
+      }
       s_dth[t] = dth;
       float* row = a.part_th + (size_t)b * a.n_theta * (WS_CH + 1);
 #pragma unroll

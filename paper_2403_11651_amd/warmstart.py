@@ -113,6 +113,55 @@ class WarmStart:
         return hist
 
 
+    def train_rd(self, x, epochs, batch=16, lr=3e-4, lam=1e-3, quant=B.CC_QUANT_ROUND, noise_seed=11, log=None):
+        """Fine-tunes the network through the codec: the loss of a mini-batch is
+        the mean over its images of Eq. (1) evaluated at the predicted latents
+        and decoder (rounding with the straight-through gradient, or the noise
+        proxy with fresh noise every step), its output gradients come from the
+        batched coolchic backward pass, and coolchic_warm_backward_grad carries
+        them into the network (the non-overfitted training of Section IV-B,
+        started from the pair regression).  Returns the mean loss of every
+        epoch."""
+        n = (x.shape[0] // batch) * batch
+        if n == 0:
+            raise ValueError("fewer images than one mini-batch")
+        H, W, dev = self.H, self.W, self.device
+        na, nu, ns = B.param_count(self.arch)
+        xb = torch.empty(batch, 3, H, W, device=dev)
+        yp = torch.empty(batch, self.n_lat, device=dev)
+        thp = torch.empty(batch, self.n_theta, device=dev)
+        gy = torch.empty(batch, self.n_lat, device=dev)
+        gth = torch.empty(batch, self.n_theta, device=dev)
+        u = torch.empty(batch * self.n_lat, device=dev)
+        loss = torch.zeros(batch, 4, device=dev)
+        noise = quant == B.CC_QUANT_NOISE
+        probs = [B.Problem(H, W, self.arch, quant, lam)] * batch
+        io = [dict(img=xb[k].reshape(-1), y=yp[k], u=u[k * self.n_lat:(k + 1) * self.n_lat] if noise else None,
+                   arm_w=thp[k, :na],
+                   ups_w=thp[k, na:na + nu], syn_w=thp[k, na + nu:], loss4=loss[k], g_y=gy[k], g_arm=gth[k, :na],
+                   g_ups=gth[k, na:na + nu], g_syn=gth[k, na + nu:]) for k in range(batch)]
+        plan = B.BatchPlan(probs, io, dloss=1.0 / batch, device=dev)
+        wp = B.WarmProblem(H, W, batch, self.arch)
+        hist = []
+        for ep in range(epochs):
+            acc = torch.zeros((), device=dev)
+            for s in range(0, n, batch):
+                xb.copy_(x[s:s + batch])
+                B.coolchic_warm_forward(wp, xb, self.net, yp, thp, ws=self._wsp(batch, B.CC_WS_FORWARD))
+                if noise:
+                    B.coolchic_uniform_noise(u, noise_seed, step=self.step_ctr)
+                plan.backward()
+                B.coolchic_warm_backward_grad(wp, xb, self.net, gy, gth, self.loss4, self.g,
+                                              ws=self._wsp(batch, B.CC_WS_BACKWARD))
+                B.coolchic_adam_step(self.net, self.g, self.m, self.v, self.step_ctr, lr=lr)
+                acc += loss[:, 0].sum() / batch
+            hist.append(float(acc) / (n // batch))
+            if log:
+                log(f"warm-start rate-distortion epoch {ep}: loss {hist[-1]:.5f}")
+        plan.close()
+        return hist
+
+
 # ---- encoding with and without the warm start -----------------------------
 
 def encoder(arch, images, y0, params0, lam=1e-3, lr=1e-2):
@@ -122,10 +171,12 @@ def encoder(arch, images, y0, params0, lam=1e-3, lr=1e-2):
     return BatchEncoder(probs, images, y0, params0, lr=lr)
 
 
-def plain_overfit(arch, images, iters, dec_seed=7, graph_steps=50, lam=1e-3):
+def plain_overfit(arch, images, iters, dec_seed=7, graph_steps=50, lam=1e-3, noise_frac=0.8):
     """From-scratch overfitting: latents 0, decoder parameters from the shared
-    seeded initialisation.  Returns (y [n][n_lat], theta [n][n_theta], loss4
-    [n][4] of the final parameters, seconds)."""
+    seeded initialisation, the noise proxy for the first noise_frac of the
+    iterations and rounding for the rest.  Returns (y [n][n_lat], theta
+    [n][n_theta], loss4 [n][4] of the final parameters with rounding,
+    seconds)."""
     H, W = images[0].shape[-2:]
     n_lat = B.latent_count(B.Problem(H, W, arch))
     na, nu, ns = B.param_count(arch)
@@ -134,7 +185,7 @@ def plain_overfit(arch, images, iters, dec_seed=7, graph_steps=50, lam=1e-3):
     enc = encoder(arch, images, [np.zeros(n_lat, np.float32)] * len(images), params0, lam)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    enc.run(iters, graph_steps=graph_steps)
+    enc.fit(iters, noise_frac=noise_frac, graph_steps=graph_steps)
     enc.backward()
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
@@ -143,24 +194,46 @@ def plain_overfit(arch, images, iters, dec_seed=7, graph_steps=50, lam=1e-3):
     return ys, ths, enc.loss.cpu().numpy(), secs
 
 
-def iterations_to_target(enc, target, max_iters, check_every=10):
-    """Runs enc until each image's loss is at or below target[k] (checked
-    every check_every iterations, on the loss of the parameters the last
-    iteration of the block started from).  Returns (iterations per image,
-    -1 where never reached; the loss4 rows at the crossing; seconds)."""
-    n = len(target)
-    hit = np.full(n, -1)
+def psnr(mse):
+    return -10.0 * np.log10(np.maximum(mse, 1e-30))
+
+
+def iterations_to_target(enc, target_loss, target_psnr, target_bpp, px, max_iters, check_every=10, noise_iters=0):
+    """Runs enc (the noise proxy for the first noise_iters iterations, then
+    rounding), checking every check_every iterations the rounding-mode loss4
+    of each image (the first check is the starting point itself), until
+    every image meets the criterion: PSNR within 0.1 dB of target_psnr[k]
+    and rate at most 1 % above target_bpp[k] (px pixels per image).
+    Returns dict(loss=iterations at which the loss first is at or below
+    target_loss[k], criterion=iterations at which the criterion first holds
+    (-1: never), at=loss4 rows there, seconds)."""
+    n = len(target_loss)
+    hit_l = np.full(n, -1)
+    hit_c = np.full(n, -1)
     at = np.zeros((n, 4), np.float32)
-    g = enc.capture(check_every)
+    graphs = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    while done < max_iters and (hit < 0).any():
-        g.replay()
-        done += check_every
+
+    def check():
         L = enc.loss.cpu().numpy()
-        new = (hit < 0) & (L[:, 0] <= target)
-        hit[new] = done
+        hit_l[(hit_l < 0) & (L[:, 0] <= target_loss)] = done
+        ok = (psnr(L[:, 1]) >= target_psnr - 0.1) & (L[:, 2] / px <= 1.01 * target_bpp)
+        new = (hit_c < 0) & ok
+        hit_c[new] = done
         at[new] = L[new]
+
+    enc.probe()  # the prediction itself (iteration 0)
+    check()
+    while done < max_iters and (hit_c < 0).any():
+        mode = B.CC_QUANT_NOISE if done < noise_iters else B.CC_QUANT_ROUND
+        if mode not in graphs:
+            enc.set_mode(mode)
+            graphs[mode] = enc.capture(check_every, probe=True)
+        enc.set_mode(mode)
+        graphs[mode].replay()
+        done += check_every
+        check()
     torch.cuda.synchronize()
-    return hit, at, time.perf_counter() - t0
+    return dict(loss=hit_l, criterion=hit_c, at=at, seconds=time.perf_counter() - t0)

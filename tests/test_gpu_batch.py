@@ -118,13 +118,51 @@ def test_batch_adam_step_matches_oracle(B, BT):
         assert np.max(np.abs(got - th1)) <= 1e-6 + 2e-7 * np.max(np.abs(th)), k
 
 
-def test_graph_replays_match_eager(B, BT):
+def test_noise_kernel_matches_oracle_philox(B):
+    from oracle import noise as NZ
+    u = torch.full((1001,), float("nan"), device="cuda")
+    step = torch.tensor([7, 0], dtype=torch.int32, device="cuda")
+    B.coolchic_uniform_noise(u, (5 << 32) | 123, step=step, stream_id=3)
+    ref = NZ.uniform_noise(1001, (5 << 32) | 123, it=7, stream_id=3)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    B.coolchic_uniform_noise(u, 9)
+    assert np.array_equal(u.cpu().numpy(), NZ.uniform_noise(1001, 9))
+
+
+def test_batch_noise_mode_vs_oracle(B, BT):
+    """Noise proxy: the batched pass draws u on the device; the oracle takes
+    the same u from its own Philox generator."""
+    from oracle import noise as NZ
+    cs = batch_cases(CS.LOW, SMALL_SIZES[:3], seed0=800)
+    enc = make_encoder(B, BT, cs)
+    enc.noise_seed = 77
+    enc.set_mode(B.CC_QUANT_NOISE)
+    enc.backward()
+    torch.cuda.synchronize()
+    u_all = NZ.uniform_noise(sum(c.y.size for c in cs), 77, it=0)
+    L = enc.loss.cpu().numpy()
+    o = 0
+    for k, c in enumerate(cs):
+        u = u_all[o:o + c.y.size]
+        o += c.y.size
+        ref = O.backward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=u)
+        assert abs(L[k, 0] - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+        for name, g in zip(("g_y", "g_arm", "g_ups", "g_syn"), enc.grads(k)):
+            assert_grad_close(f"{k}.{name}", g, ref[name])
+
+
+@pytest.mark.parametrize("mode", ["round", "noise"])
+def test_graph_replays_match_eager(B, BT, mode):
     """Every replay of a captured block of iterations equals the same number of
     eager iterations, with unrelated eager work and synchronisations between
-    the replays."""
+    the replays (noise mode: fresh noise every iteration from the device step
+    counter)."""
     cs = batch_cases(CS.LOW, SMALL_SIZES[:3], seed0=500)
     eager = make_encoder(B, BT, cs)
     graphed = make_encoder(B, BT, cs)
+    if mode == "noise":
+        eager.set_mode(B.CC_QUANT_NOISE)
+        graphed.set_mode(B.CC_QUANT_NOISE)
     g = graphed.capture(3)
     scratch = torch.randn(1 << 16, device="cuda")
     for r in range(4):
@@ -145,7 +183,8 @@ def test_training_lowers_every_loss(B, BT):
     enc.backward()
     torch.cuda.synchronize()
     l0 = enc.loss[:, 0].cpu().numpy().copy()
-    enc.run(60, graph_steps=20)
+    enc.fit(100, noise_frac=0.6, graph_steps=20)
+    assert enc.mode == B.CC_QUANT_ROUND and int(enc.step_ctr[0]) == 100
     enc.backward()
     torch.cuda.synchronize()
     l1 = enc.loss.cpu().numpy()

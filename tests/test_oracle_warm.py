@@ -189,6 +189,26 @@ def test_forward_backward_match_torch_autograd(H, W, seed):
         assert np.linalg.norm(g[lo:hi] - gt[lo:hi]) <= 1e-10 * np.linalg.norm(gt[lo:hi]), name
 
 
+def test_backward_from_grads_matches_torch_autograd():
+    """An outer loss linear in the outputs, sum(a y) + sum(b theta): its
+    gradient through the network from the given output gradients (a, b)."""
+    H, W = 64, 128
+    x = WL.image(40, H, W, 8).astype(np.float64)
+    net = _net(41)
+    n_lat = sum((H >> l) * (W >> l) for l in range(7))
+    rng = np.random.default_rng(42)
+    a, b = rng.normal(size=n_lat), rng.normal(size=N_THETA)
+    g = WS.backward_from_grads(x, net, N_THETA, a, b)
+    # (y - t)^2 / n with t = y - n a / 2 has gradient a w.r.t. y: reuse the
+    # torch formulation of the regression loss with those targets
+    out = WS.forward(x, net, N_THETA)
+    yv = WS.pack_levels(out["y"])
+    t_y = yv - n_lat * a / 2.0
+    t_th = out["theta"] - N_THETA * b / 2.0
+    _, gt, _, _ = torch_warm_loss(x, net, N_THETA, t_y, t_th, H, W)
+    assert np.linalg.norm(g - gt) <= 1e-9 * np.linalg.norm(gt)
+
+
 def test_gradient_finite_differences_unrounded():
     """Central differences of the unrounded network (float64) on sampled
     parameters of every block."""
