@@ -158,6 +158,42 @@ def run_batched(B, iters, graph_steps=50, log=None):
             "rate_end_bpp_mean": float(np.mean(l4[:, 2] / np.array([p.H * p.W for p in probs])))}
 
 
+WARM_TRAIN, WARM_HELD, WARM_ITERS = 256, 32, 500
+
+
+def warm_start_images():
+    """Images of the bounded warm-start run, generated in worker processes
+    (before this process touches the GPU)."""
+    from paper_2403_11651_amd import warmstart_eval as WE
+    return (WE.make_images([10000 + i for i in range(WARM_TRAIN)], 512, 768),
+            WE.make_images([20000 + i for i in range(WARM_HELD)], 512, 768))
+
+
+def run_warm_start(images, iters=WARM_ITERS, log=None):
+    """A bounded run of the warm-start experiment at 768x512 (pairs from the
+    plain encoder, regression then rate-distortion training of the network,
+    held-out evaluation); returns the seconds per image to the plain
+    encoder's result with and without the warm start."""
+    from paper_2403_11651_amd import warmstart_eval as WE
+    tr, ho = images
+    n_train, n_held = len(tr), len(ho)
+    res = WE.run(tr, ho, iters, epochs=40, rd_epochs=20, schedules=((30, 2e-3),), log=log)
+    r = res["heldout_results"]
+    warm = r["rd_round_noise30_lr0.002"]
+    return {"workload": f"{n_train} training pairs and {n_held} held-out 768x512 images (seeds 10000 + i, "
+                        f"20000 + i), low-complexity decoder, plain encoder {iters} iterations (80 % noise proxy, "
+                        f"then rounding)",
+            "s_per_image_plain": round(r["plain"]["s_per_image"], 5),
+            "s_per_image_warm": round(warm["s_per_image"], 5),
+            "speedup": round(r["plain"]["s_per_image"] / warm["s_per_image"], 3),
+            "criterion_met": warm["criterion_met"], "met_at_start": warm["met_at_start"],
+            "fallbacks": warm["fallbacks"], "iters_median": warm["iters_median_criterion"],
+            "plain_psnr_db": round(r["plain"]["psnr_mean"], 3), "plain_bpp": round(r["plain"]["bpp_mean"], 4),
+            "untrained_criterion_met": r["untrained_noise30_lr0.002"]["criterion_met"],
+            "pair_generation_s": res["pair_generation_s"], "train_s": res["train_s"],
+            "rd_train_s": res["rd_round_train_s"]}
+
+
 def cpu_baseline(arch, budget_s=20.0):
     """The FP64 oracle, single-threaded, timed on full 768x512 iterations
     (forward + backward + Adam) until about budget_s seconds have passed."""
@@ -205,6 +241,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--batch-iters", type=int, default=2000,
                     help="iterations of the 32-image batched overfitting run (0 skips it)")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the bounded warm-start experiment")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size reference for "
                          "the FETCH_SIZE / WRITE_SIZE hardware counters); not part of any timed step")
@@ -214,6 +251,7 @@ def main():
               f"communication, so --gpus {args.gpus} is not run here", file=sys.stderr)
         sys.exit(2)
 
+    warm_images = None if args.no_warm_start else warm_start_images()
     import torch
     from paper_2403_11651_amd import binding as B
     if not torch.cuda.is_available():
@@ -327,6 +365,8 @@ def main():
     if args.batch_iters > 0:
         out["batched"] = run_batched(B, args.batch_iters,
                                      log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    if not args.no_warm_start:
+        out["warm_start"] = run_warm_start(warm_images, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(arch, args.cpu_budget)
     print(json.dumps(out), flush=True)
