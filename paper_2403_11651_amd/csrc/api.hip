@@ -18,6 +18,7 @@ constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
 constexpr int MAX_GRID = 512;
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline int t0_tiles(int H, int W) { return cdiv(H, SYN_T0_H) * cdiv(W, SYN_T0_W); }
 
 struct Plan {
   Geo geo;
@@ -281,7 +282,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   sa.img = img;
   sa.xhat = xhat_out;
   sa.spart = W + P.spart;
-  if ((rc = launch(t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
+  if ((rc = launch(t0k, t0_tiles(p->H, p->W), 256, &sa, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
   if ((rc = join_from(sd, st))) return rc;
   FinalArgs fa;
@@ -323,7 +324,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   sa.gz = W + P.gz;
   sa.wpart = W + P.wpart_syn;
   sa.spart = W + P.spart;
-  b->t0_grid = cdiv(p->H * p->W, 256);
+  b->t0_grid = t0_tiles(p->H, p->W);
   for (int s = 0; s + 1 < L; ++s) {
     UpsBwdArgs& ua = b->upb[s];
     ua.geo = P.geo; ua.s = s; ua.y = y; ua.u = u; ua.quant = p->quant;
@@ -461,7 +462,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   long long items = 0;
   for (int k = 0; k < n; ++k) {
     const Plan& P = plans[k];
-    items += P.arm_grid + P.syn_grid + cdiv(P.geo.H * P.geo.W, 256) + P.red_grid + P.fold_grid;
+    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.red_grid + P.fold_grid;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * (L - 1 - s);
   }
@@ -646,7 +647,7 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   if ((rc = launch_ups_fwd(P, W, yq, nullptr, 2, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, yq, nullptr, 2, ups_w, syn_w);
   sa.xhat = xhat;
-  if ((rc = launch(t0k, cdiv(p->H * p->W, 256), 256, &sa, st))) return rc;
+  if ((rc = launch(t0k, t0_tiles(p->H, p->W), 256, &sa, st))) return rc;
   if ((rc = launch(resk, P.syn_grid, SYN_THREADS, &sa, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
@@ -657,10 +658,12 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
   if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
     return CC_EINVAL;
   AdamArgs a{theta, grad, m, v, n, step, lr, beta1, beta2, eps};
-  const int64_t blocks = (n + 255) / 256;
-  const int grid = (int)std::min<int64_t>(blocks, 2048);
+  const bool vec = ((uintptr_t)theta | (uintptr_t)grad | (uintptr_t)m | (uintptr_t)v) % 16 == 0;
+  // at most 512 blocks: the completion counter takes one atomic per block
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 512));
   (void)hipGetLastError();
-  int rc = launch((const void*)adam_kernel, grid, 256, &a, (hipStream_t)stream);
+  int rc = launch(vec ? (const void*)adam_kernel<true> : (const void*)adam_kernel<false>, grid, 256, &a,
+                  (hipStream_t)stream);
   if (rc) return rc;
 
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;

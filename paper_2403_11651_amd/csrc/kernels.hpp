@@ -75,6 +75,7 @@ __global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
 
 // ---------------------------------------------------------------- synthesis
 constexpr int SYN_T = 16;                  // output tile side (pixels)
+constexpr int SYN_T0_H = 16, SYN_T0_W = 32;  // pixel tile of syn_t0_kernel
 constexpr int SYN_THREADS = 256;
 constexpr int SYN_MAXRES = 2;              // residual 3x3 convs supported
 constexpr int SYN_FMAX = SYN_T + 4 * SYN_MAXRES;  // largest LDS frame side
@@ -144,6 +145,7 @@ struct AdamArgs {
   int32_t* step;
   float lr, beta1, beta2, eps;
 };
+template <bool VEC>
 __global__ void adam_kernel(AdamArgs a);
 __global__ void noise_kernel(float* u, int64_t n, uint32_t k0, uint32_t k1, const int32_t* step, uint32_t stream_id);
 

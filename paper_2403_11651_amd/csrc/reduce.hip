@@ -119,19 +119,45 @@ __global__ __launch_bounds__(256) void finalize_kernel_batch(const FinalArgs* __
 // Adam (Kingma & Ba) with bias correction; t = step[0] + 1.  Every block reads
 // step[0] before it adds itself to the completion counter step[1]; the block
 // that completes the count advances step[0] and clears the counter, so the
-// next launch sees the new step.
+// next launch sees the new step.  VEC: all four arrays are 16-byte aligned
+// and are read and written four values at a time.
+__device__ __forceinline__ void adam_one(const AdamArgs& a, float k1, float k2, float& th, float g, float& m,
+                                         float& v) {
+  m = a.beta1 * m + (1.0f - a.beta1) * g;
+  v = a.beta2 * v + (1.0f - a.beta2) * g * g;
+  th -= a.lr * (m * k1) / (sqrtf(v * k2) + a.eps);
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const int t = a.step[0] + 1;
-  const float bc1 = 1.0f - powf(a.beta1, (float)t);
-  const float bc2 = 1.0f - powf(a.beta2, (float)t);
-  const float k1 = 1.0f / bc1, k2 = 1.0f / bc2;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
-    const float g = a.g[i];
-    const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
-    const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
+  const float k1 = 1.0f / (1.0f - powf(a.beta1, (float)t));
+  const float k2 = 1.0f / (1.0f - powf(a.beta2, (float)t));
+  const int64_t stride = (int64_t)gridDim.x * 256, first = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t done = 0;
+  if (VEC) {
+    const int64_t n4 = a.n / 4;
+    for (int64_t i = first; i < n4; i += stride) {
+      float4 th = reinterpret_cast<float4*>(a.theta)[i];
+      const float4 g = reinterpret_cast<const float4*>(a.g)[i];
+      float4 m = reinterpret_cast<float4*>(a.m)[i];
+      float4 v = reinterpret_cast<float4*>(a.v)[i];
+      adam_one(a, k1, k2, th.x, g.x, m.x, v.x);
+      adam_one(a, k1, k2, th.y, g.y, m.y, v.y);
+      adam_one(a, k1, k2, th.z, g.z, m.z, v.z);
+      adam_one(a, k1, k2, th.w, g.w, m.w, v.w);
+      reinterpret_cast<float4*>(a.m)[i] = m;
+      reinterpret_cast<float4*>(a.v)[i] = v;
+      reinterpret_cast<float4*>(a.theta)[i] = th;
+    }
+    done = n4 * 4;
+  }
+  for (int64_t i = done + first; i < a.n; i += stride) {
+    float th = a.theta[i], m = a.m[i], v = a.v[i];
+    adam_one(a, k1, k2, th, a.g[i], m, v);
     a.m[i] = m;
     a.v[i] = v;
-    a.theta[i] -= a.lr * (m * k1) / (sqrtf(v * k2) + a.eps);
+    a.theta[i] = th;
   }
   if (threadIdx.x == 0) {
     const int prev = atomicAdd(&a.step[1], 1);  // after this block's read of step[0] (t is used above)
@@ -141,5 +167,7 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
     }
   }
 }
+template __global__ void adam_kernel<true>(AdamArgs);
+template __global__ void adam_kernel<false>(AdamArgs);
 
 }  // namespace cc

@@ -21,19 +21,38 @@
 namespace cc {
 
 // The L channels of z at pixel (i, j): y_hat_0 and U_0 of every channel of
-// stack_1 = [y_hat_1, U_1 output].
+// stack_1 = [y_hat_1, U_1 output].  U_0 runs vertically first (four taps per
+// column, explicit FMAs), then horizontally, in the same order as the tiled
+// computation of syn_t0_body, so both give bit-identical z.
+// The four taps of one direction that reach an output of parity `odd`
+// (tap 2q + 1 - odd for the q-th input), selected from the eight taps held
+// in registers (uniform loads, no per-lane indexing).
+__device__ __forceinline__ void parity_taps(const float (&k8)[UPS_K], int odd, float (&t)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = odd ? k8[2 * q] : k8[2 * q + 1];
+}
+
+__device__ __forceinline__ void load_taps(const float* __restrict__ taps, float (&kv)[UPS_K], float (&kh)[UPS_K]) {
+#pragma unroll
+  for (int k = 0; k < UPS_K; ++k) {
+    kv[k] = taps[k];
+    kh[k] = taps[UPS_K + k];
+  }
+}
+
 __device__ __forceinline__ void compute_z(const SynArgs& a, int i, int j, float z[MAXL]) {
   const int L = a.geo.L, W = a.geo.W, h1 = a.geo.lh[1], w1 = a.geo.lw[1];
   z[0] = quantise(a.y, a.u, i * W + j, a.quant);
   int ro[4], co[4];
-  float vt[4], ht[4];
+  float vt[4], ht[4], kv[UPS_K], kh[UPS_K];
+  load_taps(a.ups0, kv, kh);
+  parity_taps(kv, i & 1, vt);
+  parity_taps(kh, j & 1, ht);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int ky = 2 * q + 1 - (i & 1), kx = 2 * q + 1 - (j & 1);
     ro[q] = clampi((i + UPS_P - ky) >> 1, 0, h1 - 1);
     co[q] = clampi((j + UPS_P - kx) >> 1, 0, w1 - 1);
-    vt[q] = a.ups0[ky];
-    ht[q] = a.ups0[UPS_K + kx];
   }
   const int lo1 = a.geo.loff[1];
 #pragma unroll
@@ -42,15 +61,15 @@ __device__ __forceinline__ void compute_z(const SynArgs& a, int i, int j, float 
     if (c < L) {
       float acc = 0.0f;
 #pragma unroll
-      for (int q1 = 0; q1 < 4; ++q1) {
-        float ra = 0.0f;
+      for (int q2 = 0; q2 < 4; ++q2) {
+        float v = 0.0f;
 #pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) {
+        for (int q1 = 0; q1 < 4; ++q1) {
           const int p = ro[q1] * w1 + co[q2];
           const float val = c == 1 ? quantise(a.y, a.u, lo1 + p, a.quant) : a.up1[(size_t)(c - 2) * h1 * w1 + p];
-          ra += ht[q2] * val;
+          v = __builtin_fmaf(vt[q1], val, v);
         }
-        acc += vt[q1] * ra;
+        acc = __builtin_fmaf(ht[q2], v, acc);
       }
       z[c] = acc;
     }
@@ -86,43 +105,108 @@ __device__ __forceinline__ void stage_weights(SynW<HS, NRES>& sw, const float* _
   }
 }
 
-// The two 1x1 layers at one pixel: a = ReLU(W1 z + b1) (z[7] = 1 carries the
-// bias), t0 = ReLU(W2 a + b2).  Keeps a and the pre-activation sign if asked.
-template <int HS, int NRES, bool KEEP>
-__device__ __forceinline__ void layers_1x1(const SynW<HS, NRES>& sw, const float (&zz)[8], float (&t)[3],
-                                           float* av, bool* pos) {
-  t[0] = sw.b2[0]; t[1] = sw.b2[1]; t[2] = sw.b2[2];
+// The two 1x1 layers, a = ReLU(W1 z + b1) (z[7] = 1 carries the bias) and
+// t0 = ReLU(W2 a + b2), for NP pixels at once: every weight read from LDS
+// serves all NP pixels (the hidden units run in a partly unrolled loop, so
+// the weights are read where they are used).
+template <int HS, int NRES, int NP>
+__device__ __forceinline__ void layers_1x1_np(const SynW<HS, NRES>& sw, const float (&zz)[NP][8], float (&t)[NP][3]) {
 #pragma unroll
+  for (int n = 0; n < NP; ++n) {
+    t[n][0] = sw.b2[0]; t[n][1] = sw.b2[1]; t[n][2] = sw.b2[2];
+  }
+#pragma unroll 4
   for (int f = 0; f < HS; ++f) {
     const f32x4 w0 = *reinterpret_cast<const f32x4*>(&sw.W1p[f][0]);
     const f32x4 w1 = *reinterpret_cast<const f32x4*>(&sw.W1p[f][4]);
-    const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] + w1.y * zz[5] +
-                      w1.z * zz[6] + w1.w * zz[7];
-    const float a = fmaxf(pre, 0.0f);
     const f32x4 w2 = *reinterpret_cast<const f32x4*>(&sw.W2t[f][0]);
-    t[0] += w2.x * a; t[1] += w2.y * a; t[2] += w2.z * a;
-    if (KEEP) { av[f] = a; pos[f] = pre > 0.0f; }
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      const float pre = w0.x * zz[n][0] + w0.y * zz[n][1] + w0.z * zz[n][2] + w0.w * zz[n][3] + w1.x * zz[n][4] +
+                        w1.y * zz[n][5] + w1.z * zz[n][6] + w1.w * zz[n][7];
+      const float av = fmaxf(pre, 0.0f);
+      t[n][0] += w2.x * av; t[n][1] += w2.y * av; t[n][2] += w2.z * av;
+    }
   }
-  t[0] = fmaxf(t[0], 0.0f); t[1] = fmaxf(t[1], 0.0f); t[2] = fmaxf(t[2], 0.0f);
+#pragma unroll
+  for (int n = 0; n < NP; ++n) {
+    t[n][0] = fmaxf(t[n][0], 0.0f); t[n][1] = fmaxf(t[n][1], 0.0f); t[n][2] = fmaxf(t[n][2], 0.0f);
+  }
 }
 
 template <int HS, int NRES>
 __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
+  constexpr int RH = SYN_T0_H / 2 + 4, RW = SYN_T0_W / 2 + 4;
   __shared__ SynW<HS, NRES> sw;
-  const int H = a.geo.H, W = a.geo.W, L = a.geo.L;
-  stage_weights(sw, a.w, L, threadIdx.x);
+  __shared__ float s_s[MAXL - 1][RH][RW + 1];
+  __shared__ float s_v[MAXL - 1][SYN_T0_H][RW + 1];
+  const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid = threadIdx.x;
+  const int h1 = a.geo.lh[1], w1 = a.geo.lw[1], lo1 = a.geo.loff[1];
+  const int ntx = (W + SYN_T0_W - 1) / SYN_T0_W;
+  const int i0 = (bid / ntx) * SYN_T0_H, j0 = (bid % ntx) * SYN_T0_W;
+  const int r0 = i0 / 2 - 2, c0 = j0 / 2 - 2;
+  const int nch = L - 1;
+  float kv[UPS_K], kh[UPS_K];
+  load_taps(a.ups0, kv, kh);
+  stage_weights(sw, a.w, L, tid);
+  for (int p = tid; p < nch * RH * RW; p += 256) {
+    const int c = p / (RH * RW), rem = p % (RH * RW), rr = rem / RW, cc = rem % RW;
+    const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
+    s_s[c][rr][cc] = c == 0 ? quantise(a.y, a.u, lo1 + q, a.quant) : a.up1[(size_t)(c - 1) * h1 * w1 + q];
+  }
   __syncthreads();
-  const int idx = bid * 256 + threadIdx.x;
-  if (idx >= H * W) return;
-  const int i = idx / W, j = idx % W;
-  float z[MAXL], zz[8], t[3];
-  compute_z(a, i, j, z);
+  for (int p = tid; p < nch * SYN_T0_H * RW; p += 256) {
+    const int c = p / (SYN_T0_H * RW), rem = p % (SYN_T0_H * RW), ti = rem / RW, cc = rem % RW;
+    const int i = i0 + ti;
+    float vt[4];
+    parity_taps(kv, i & 1, vt);
+    float v = 0.0f;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) zz[c] = c < L ? z[c] : 0.0f;
-  zz[7] = 1.0f;
-  layers_1x1<HS, NRES, false>(sw, zz, t, nullptr, nullptr);
+    for (int q = 0; q < 4; ++q) {
+      const int ky = 2 * q + 1 - (i & 1);
+      v = __builtin_fmaf(vt[q], s_s[c][((i + UPS_P - ky) >> 1) - r0][cc], v);
+    }
+    s_v[c][ti][cc] = v;
+  }
+  __syncthreads();
+  // two pixels per thread, rows ti and ti + SYN_T0_H / 2 of one column
+  constexpr int NP = SYN_T0_H * SYN_T0_W / 256;
+  static_assert(NP == 2, "two pixels per thread");
+  float zz[NP][8], t[NP][3];
+  int pi[NP], pj[NP];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) a.t0[(size_t)c * H * W + idx] = t[c];
+  for (int n = 0; n < NP; ++n) {
+    const int ti = tid / SYN_T0_W + n * (SYN_T0_H / NP), tj = tid % SYN_T0_W;
+    pi[n] = i0 + ti;
+    pj[n] = j0 + tj;
+    const int i = min(pi[n], H - 1), j = min(pj[n], W - 1);  // ragged tiles: computed, not stored
+    zz[n][0] = quantise(a.y, a.u, i * W + j, a.quant);
+    int col[4];
+    float ht[4];
+    parity_taps(kh, pj[n] & 1, ht);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kx = 2 * q + 1 - (pj[n] & 1);
+      col[q] = ((pj[n] + UPS_P - kx) >> 1) - c0;
+    }
+#pragma unroll
+    for (int c = 1; c < 7; ++c) {
+      float acc = 0.0f;
+      if (c < L) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+      }
+      zz[n][c] = acc;
+    }
+    zz[n][7] = 1.0f;
+  }
+  layers_1x1_np<HS, NRES, NP>(sw, zz, t);
+#pragma unroll
+  for (int n = 0; n < NP; ++n) {
+    if (pi[n] >= H || pj[n] >= W) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.t0[(size_t)c * H * W + pi[n] * W + pj[n]] = t[n][c];
+  }
 }
 
 // One residual layer t_r = phi(t_{r-1} + conv(t_{r-1}) + b) on the frame region

@@ -143,24 +143,27 @@ def test_warm_nonfinite_flag(B):
 
 
 def test_trained_warm_start_gains(B):
-    """The network trained on plain-overfit pairs (by the library's own
-    forward / backward kernels and Adam) against the same network untrained
-    and against overfitting from scratch, on held-out images: it starts
-    closer, and meets the from-scratch encoder's result (within 0.1 dB at
-    no more than 1 % more rate) on more images, in a fraction of the
-    from-scratch iterations."""
+    """The network trained on plain-overfit pairs and then through the codec's
+    loss (by the library's own forward / backward kernels and Adam) against
+    the same network untrained and against overfitting from scratch, on
+    held-out images: it starts far closer and meets the from-scratch
+    encoder's result (within 0.1 dB at no more than 1 % more rate) on more
+    images, in at most a quarter of the from-scratch iterations.  (The
+    seconds-per-image comparison, fallbacks included, is made at 768x512
+    with 2000 pairs by the evaluation driver and the benchmark; with 128
+    small training pairs here about half the held-out images fall back.)"""
     from paper_2403_11651_amd import warmstart_eval as WE
     H, W, iters = 256, 384, 300
     tr = WE.make_images([10000 + i for i in range(128)], H, W, workers=1)
     ho = WE.make_images([20000 + i for i in range(16)], H, W, workers=1)
-    res = WE.run(tr, ho, iters, epochs=40, rd_epochs=0, schedules=((0, 1e-2),))
+    res = WE.run(tr, ho, iters, epochs=40, rd_epochs=20, schedules=((30, 2e-3),))
     r = res["heldout_results"]
     tl = res["train_loss"]
     assert tl[-1] < 0.6 * tl[0], tl
-    t, u = r["pairs_only_noise0_lr0.01"], r["untrained_noise0_lr0.01"]
-    assert t["start_loss_mean"] < 0.7 * u["start_loss_mean"], r
-    assert t["loss_reached"] >= u["loss_reached"] + 3, r
-    assert t["iters_median_loss"] <= 0.5 * iters, r
+    t, u, p = r["rd_round_noise30_lr0.002"], r["untrained_noise30_lr0.002"], r["plain"]
+    assert t["start_loss_mean"] < 0.5 * u["start_loss_mean"], r
+    assert t["criterion_met"] >= u["criterion_met"] + 4, r
+    assert t["iters_median_criterion"] <= 0.25 * p["iters"], r
     assert t["s_per_image"] < u["s_per_image"], r
 
 
