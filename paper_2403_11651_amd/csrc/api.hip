@@ -31,7 +31,9 @@ struct Plan {
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
-  size_t t0, gz, gext, wpart_arm, wpart_syn, rpart, spart, upart[MAXL], flags, total;
+  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], flags, total;
+  int head_grid;  // tiles of the 1x1-layer backward
+  int n_head;     // 1x1-layer parameters (W1, b1, W2, b2)
 };
 
 bool arch_ok(const cc_arch* a) {
@@ -108,7 +110,9 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   // partials (at most MAX_GRID rows), one column per block for the tall
   // upsampling partials (tiles x channels rows)
   P->red_blocks_arm = cdiv((int)P->n_arm, 16);
-  P->red_blocks_syn = cdiv((int)P->n_syn, 16);
+  P->n_head = P->Hs * L + 4 * P->Hs + 3;
+  P->head_grid = cdiv(p->H, SYN_HD) * cdiv(p->W, SYN_HD);
+  P->red_blocks_syn = cdiv(P->nres * 84, 16) + cdiv(P->n_head, 16);
   P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
   for (int s = 0; s + 1 < L; ++s) {
     P->red_blocks_ups[s] = 2 * UPS_K;
@@ -125,7 +129,9 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     for (int s = 1; s + 1 < L; ++s) P->gb[s] = take(cur, (size_t)(L - 1 - s) * g.lh[s] * g.lw[s]);
     P->gext = take(cur, (size_t)nt * ARM_EXT);
     P->wpart_arm = take(cur, (size_t)P->arm_grid * P->n_arm);
-    P->wpart_syn = take(cur, (size_t)P->syn_grid * P->n_syn);
+    P->gpt = take(cur, (size_t)3 * p->H * p->W);
+    P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
+    P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
     for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * (L - 1 - s) * 2 * UPS_K);
     P->flags = take(cur, (size_t)P->red_grid + P->fold_grid);
   }
@@ -322,6 +328,8 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   sa.dscale = dloss * 2.0f / (3.0f * HW);
   sa.g_y = g_y;
   sa.gz = W + P.gz;
+  sa.gpt = W + P.gpt;
+  sa.hpart = W + P.hpart;
   sa.wpart = W + P.wpart_syn;
   sa.spart = W + P.spart;
   b->t0_grid = t0_tiles(p->H, p->W);
@@ -346,7 +354,8 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 16, g_arm);
   for (int s = 0; s + 1 < L; ++s)
     add(W + P.upart[s], P.ups_grid[s] * (L - 1 - s), 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
-  add(W + P.wpart_syn, P.syn_grid, (int)P.n_syn, 16, g_syn);
+  add(W + P.hpart, P.head_grid, P.n_head, 16, g_syn);                                // W1, b1, W2, b2
+  add(W + P.wpart_syn, P.syn_grid, P.nres * 84, 16, g_syn + (P.n_syn - P.nres * 84));  // residual convs
   ca.nseg = ns;
   ca.block_start[ns] = blk;
   ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
@@ -371,7 +380,8 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   const void* armk = arm_kernel_for(P.C, P.NH, true, false);
   const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *bwk = syn_bwd_kernel_for(P.Hs, P.nres, false);
-  if (!armk || !t0k || !bwk) return CC_EUNSUPPORTED;
+  const void* hdk = syn_head_bwd_kernel_for(P.Hs, P.nres, false);
+  if (!armk || !t0k || !bwk || !hdk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   const int L = P.geo.L;
   static thread_local BwdSet b;
@@ -385,6 +395,7 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if (b.upf_grid && (rc = launch((const void*)ups_fwd_kernel, b.upf_grid, 256, &b.upf, st))) return rc;
   if ((rc = launch(t0k, b.t0_grid, 256, &b.syn, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, bwk, P.syn_grid, SYN_THREADS, &b.syn, st))) return rc;
+  if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
     if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], L - 1 - s), dim3(256), argv, 0, st) !=
@@ -405,7 +416,7 @@ namespace {
 // Host-side plan of a batch.
 struct BatchPlan {
   int n = 0, L = 0, device = 0;
-  const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr;
+  const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr, *hdk = nullptr;
   // device arrays inside the workspace
   ArmArgs* d_arm = nullptr;
   UpsFwdArgs* d_upf = nullptr;
@@ -413,9 +424,9 @@ struct BatchPlan {
   UpsBwdArgs* d_upb[MAXL] = {};
   CombineArgs* d_comb = nullptr;
   FinalArgs* d_fin = nullptr;
-  WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_upb[MAXL] = {},
-           *w_comb = nullptr;
-  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_upb[MAXL] = {}, n_comb = 0;
+  WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_head = nullptr,
+           *w_upb[MAXL] = {}, *w_comb = nullptr;
+  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb = 0;
 };
 
 int share(int total, long long part, long long whole, int cap) {
@@ -462,7 +473,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   long long items = 0;
   for (int k = 0; k < n; ++k) {
     const Plan& P = plans[k];
-    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.red_grid + P.fold_grid;
+    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * (L - 1 - s);
   }
@@ -514,7 +525,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
   B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
   B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
-  if (!B.armk || !B.t0k || !B.bwk) return CC_EUNSUPPORTED;
+  B.hdk = syn_head_bwd_kernel_for(P0.Hs, P0.nres, true);
+  if (!B.armk || !B.t0k || !B.bwk || !B.hdk) return CC_EUNSUPPORTED;
   if (hipGetDevice(&B.device) != hipSuccess) return CC_EHIP;
   // host copies of every argument block and work-list
   std::vector<ArmArgs> h_arm(n);
@@ -523,7 +535,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   std::vector<std::vector<UpsBwdArgs>> h_upb(L, std::vector<UpsBwdArgs>(n));
   std::vector<CombineArgs> h_comb(n);
   std::vector<FinalArgs> h_fin(n);
-  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_comb;
+  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_comb;
   std::vector<std::vector<WorkItem>> w_upb(L);
   BwdSet* b = new (std::nothrow) BwdSet;
   if (!b) return CC_EINVAL;
@@ -539,6 +551,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
     for (int i = 0; i < b->t0_grid; ++i) w_t0.push_back(WorkItem{k, i, b->t0_grid, 0});
     for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
+    for (int i = 0; i < P.head_grid; ++i) w_head.push_back(WorkItem{k, i, P.head_grid, 0});
     for (int s = 0; s + 1 < L; ++s)
       for (int ch = 0; ch < L - 1 - s; ++ch)
         for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], ch});
@@ -569,6 +582,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   putw(w_upf, &B.w_upf, &B.n_upf);
   putw(w_t0, &B.w_t0, &B.n_t0);
   putw(w_syn, &B.w_syn, &B.n_syn);
+  putw(w_head, &B.w_head, &B.n_head);
   for (int s = 0; s + 1 < L; ++s) putw(w_upb[s], &B.w_upb[s], &B.n_upb[s]);
   putw(w_comb, &B.w_comb, &B.n_comb);
   if (err || desc_off + d > ws_bytes) return err ? CC_EHIP : CC_EWORKSPACE;
@@ -613,6 +627,7 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   if ((rc = go(CC_STAGE_NONE, (const void*)ups_fwd_kernel_batch, B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
   if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
   if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
+  if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
   for (int s = 0; s + 1 < B.L; ++s)
     if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
       return rc;

@@ -76,6 +76,7 @@ __global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
 // ---------------------------------------------------------------- synthesis
 constexpr int SYN_T = 16;                  // output tile side (pixels)
 constexpr int SYN_T0_H = 16, SYN_T0_W = 32;  // pixel tile of syn_t0_kernel
+constexpr int SYN_HD = 16;                 // pixel tile side of syn_head_bwd_kernel (one pixel per thread)
 constexpr int SYN_THREADS = 256;
 constexpr int SYN_MAXRES = 2;              // residual 3x3 convs supported
 constexpr int SYN_FMAX = SYN_T + 4 * SYN_MAXRES;  // largest LDS frame side
@@ -96,13 +97,16 @@ struct SynArgs {
   float dscale;        // backward: dloss * 2 / (3 H W)
   float* g_y;          // backward: level 0 of the packed latent gradient
   float* gz;           // backward: [(L-1)][H][W] gradient of U_0's output
-  float* wpart;        // backward: [gridDim][n_syn]
+  float* gpt;          // backward: [3][H][W] gradient at the pre-activation of t0
+  float* wpart;        // backward: [gridDim][n_res * 84] residual-conv weight-gradient partials
+  float* hpart;        // backward: [head tiles][Hs L + 4 Hs + 3] 1x1-layer weight-gradient partials
   float* spart;        // [gridDim] squared-error partial sums
   int n_tiles_x, n_tiles;
 };
 const void* syn_t0_kernel_for(int Hs, int nres, bool batch);
 const void* syn_res_fwd_kernel_for(int Hs, int nres, bool batch);
 const void* syn_bwd_kernel_for(int Hs, int nres, bool batch);
+const void* syn_head_bwd_kernel_for(int Hs, int nres, bool batch);
 
 // ---------------------------------------------------------------- reductions, optimiser
 constexpr int RED_MAXSEG = 12;

@@ -431,19 +431,19 @@ __device__ __forceinline__ void relu_mask(const float* t, float* g, int tid) {
   }
 }
 
+// Backward of the residual convs on 16x16 tiles (frames with a halo of
+// 2 n_res pixels of t0 in LDS): recompute the convs, score the distortion,
+// run their adjoint back to t0 and write the gradient at the pre-activation
+// of t0 (masked by its ReLU) for the head kernel; conv weight gradients on
+// the matrix cores.
 template <int HS, int NRES>
 __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, const int nblk) {
   constexpr int FA = SYN_FMAX * SYN_FMAX, E = 2 * NRES, FS = SYN_T + 2 * E;
-  constexpr int BMA = (HS + 15) / 16;   // blocks of the hidden width
-  constexpr int BNA = (HS + 1 + 15) / 16;
   // LDS pool: residual-conv frames (t_0..t_NRES, two gradient buffers) and the
-  // per-wave staging of the conv weight gradients live during phases 1-5; the
-  // per-pixel phase 6 reuses the whole pool as 64-row staging per wave.
+  // per-wave staging of the conv weight gradients.
   constexpr int FRAMES = (NRES + 1 + 2) * 3 * FA;
   constexpr int STG_R = 32 * (3 + (28 | 1));                 // conv staging per wave (32 items)
-  constexpr int LX1 = HS | 1, LY1 = 9, LX2 = 3, LY2 = (HS + 1) | 1;
-  constexpr int P6W = 64 * ((LX1 + LY1) > (LX2 + LY2) ? (LX1 + LY1) : (LX2 + LY2));  // phase-6 staging per wave
-  constexpr int POOL = (FRAMES + 4 * STG_R) > 4 * P6W ? (FRAMES + 4 * STG_R) : 4 * P6W;
+  constexpr int POOL = FRAMES + 4 * STG_R;
   __shared__ SynW<HS, NRES> sw;
   __shared__ float pool[POOL];
   float (*s_t)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool);
@@ -453,9 +453,7 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
   stage_weights(sw, a.w, L, tid0);
   float* stg = pool + FRAMES + wave * STG_R;
 
-  f32x4 accW1[BMA][1], accW2[1][BNA], accR[NRES][1][2];
-  zero_acc(accW1);
-  zero_acc(accW2);
+  f32x4 accR[NRES][1][2];
 #pragma unroll
   for (int r = 0; r < NRES; ++r) zero_acc(accR[r]);
   float sse = 0.0f;
@@ -534,97 +532,210 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
       cur ^= 1;
       __syncthreads();
     }
-    // 5./6. per pixel: 1x1 layers recomputed, then their adjoint down to z
+    // 5. per pixel: the gradient at the pre-activation of t0, and the distortion
     {
       const int i = i0 + ty, j = j0 + tx;
-      float gpt[3];
+      if (own) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float t0v = s_t[0][c * FA + fpo];
-        gpt[c] = (own && t0v > 0.0f) ? s_g[cur][c * FA + fpo] : 0.0f;
-        if (own) {
-          const float e = s_t[NRES][c * FA + fpo] - a.img[(size_t)c * H * W + i * W + j];
+        for (int c = 0; c < 3; ++c) {
+          const size_t gi = (size_t)c * H * W + i * W + j;
+          const float t0v = s_t[0][c * FA + fpo];
+          a.gpt[gi] = t0v > 0.0f ? s_g[cur][c * FA + fpo] : 0.0f;
+          const float e = s_t[NRES][c * FA + fpo] - a.img[gi];
           sse += e * e;
         }
-      }
-      float z[MAXL], zz[8];
-      if (own) compute_z(a, i, j, z);
-#pragma unroll
-      for (int c = 0; c < 7; ++c) zz[c] = (own && c < L) ? z[c] : 0.0f;
-      zz[7] = own ? 1.0f : 0.0f;
-      __syncthreads();  // the frames are dead: the pool becomes phase-6 staging
-      float* P6 = pool + wave * P6W;
-      int wz = 0;  // opaque zero: weight reads stay where they are used
-      asm volatile("" : "+s"(wz));
-      const f32x4* W1q = reinterpret_cast<const f32x4*>(&sw.W1p[0][0]) + wz;
-      const f32x4* W2q = reinterpret_cast<const f32x4*>(&sw.W2t[0][0]) + wz;
-      uint32_t pmask[(HS + 31) / 32] = {};  // signs of the first layer's pre-activations
-      // (a) W2, b2 from (g_pre_t, [a, 1]), one staged row per pixel
-      {
-        float* X2 = P6;
-        float* Y2 = P6 + 64 * LX2;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) X2[lane * LX2 + c] = gpt[c];
-#pragma unroll 4
-        for (int f = 0; f < HS; ++f) {
-          const f32x4 w0 = W1q[2 * f], w1 = W1q[2 * f + 1];
-          const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] +
-                            w1.y * zz[5] + w1.z * zz[6] + w1.w * zz[7];
-          Y2[lane * LY2 + f] = fmaxf(pre, 0.0f);
-          if (pre > 0.0f) pmask[f >> 5] |= 1u << (f & 31);
-        }
-        Y2[lane * LY2 + HS] = own ? 1.0f : 0.0f;
-        wave_lds_sync();
-        mfma_xty64(accW2, X2, LX2, 3, Y2, LY2, HS + 1, lane);
-        wave_lds_sync();
-      }
-      // (b) g_a = W2^T g_pre_t masked by the first layer's ReLU; W1, b1 from
-      // (g_a, [z, 1]); dL/dz = W1^T g_a
-      {
-        int wz2 = 0;
-        asm volatile("" : "+s"(wz2));
-        W1q += wz2;
-        W2q += wz2;
-        float* X1 = P6;
-        float* Y1 = P6 + 64 * LX1;
-        float gz[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) gz[c] = 0.0f;
-#pragma unroll 4
-        for (int f = 0; f < HS; ++f) {
-          const f32x4 w0 = W1q[2 * f], w1 = W1q[2 * f + 1];
-          const f32x4 w2 = W2q[f];
-          float g = w2.x * gpt[0] + w2.y * gpt[1] + w2.z * gpt[2];
-          g = ((pmask[f >> 5] >> (f & 31)) & 1u) ? g : 0.0f;
-          X1[lane * LX1 + f] = g;
-          gz[0] += w0.x * g; gz[1] += w0.y * g; gz[2] += w0.z * g; gz[3] += w0.w * g;
-          gz[4] += w1.x * g; gz[5] += w1.y * g; gz[6] += w1.z * g;
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) Y1[lane * LY1 + c] = zz[c];
-        if (own) {
-          a.g_y[i * W + j] = gz[0];
-#pragma unroll
-          for (int c = 1; c < MAXL; ++c)
-            if (c < L) a.gz[(size_t)(c - 1) * H * W + i * W + j] = gz[c];
-        }
-        wave_lds_sync();
-        mfma_xty64(accW1, X1, LX1, HS, Y1, LY1, 8, lane);
-        wave_lds_sync();
       }
     }
     __syncthreads();
   }
 
-  // ---- block partials
-  const int n_syn = HS * L + HS + 3 * HS + 3 + NRES * 84;
-  const int oW1 = 0, ob1 = HS * L, oW2 = ob1 + HS, ob2 = oW2 + 3 * HS, ores = ob2 + 3;
-  static_assert(4 * (HS * MAXL + HS + 3 * HS + 3 + NRES * 84) <= POOL, "partials fit");
-  float* red = pool;  // [waves][n_syn]
-  float* rw = red + wave * n_syn;
+  // ---- block partials: residual conv r as W (81) then b (3)
+  constexpr int NR = NRES * 84;
+  static_assert(4 * NR <= POOL, "partials fit");
+  float* red = pool;  // [waves][NR]
+  float* rw = red + wave * NR;
   const int lg = lane >> 4, lc = lane & 15;
 #pragma unroll
-  for (int bm = 0; bm < BMA; ++bm)
+  for (int rr = 0; rr < NRES; ++rr) {
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int oc = 4 * lg + r, k = 16 * bn + lc;
+        if (oc < 3) {
+          if (k < 27) rw[rr * 84 + oc * 27 + k] = accR[rr][0][bn][r];
+          else if (k == 27) rw[rr * 84 + 81 + oc] = accR[rr][0][bn][r];
+        }
+      }
+  }
+  __shared__ float s_red[SYN_THREADS / 64];
+  sse = wave_sum(sse);
+  if (lane == 0) s_red[wave] = sse;
+  __syncthreads();
+  for (int p = tid0; p < NR; p += SYN_THREADS) {
+    float acc = 0.0f;
+    for (int k = 0; k < SYN_THREADS / 64; ++k) acc += red[k * NR + p];
+    a.wpart[(size_t)bid * NR + p] = acc;
+  }
+  if (tid0 == 0) {
+    float acc = 0.0f;
+    for (int k = 0; k < SYN_THREADS / 64; ++k) acc += s_red[k];
+    a.spart[bid] = acc;
+  }
+}
+
+// Backward of the two 1x1 layers over a SYN_HD x SYN_HD tile, one pixel per
+// thread: z recomputed as in syn_t0_body, the layers recomputed, g_a = W2^T
+// g_pre_t masked by the first layer's ReLU, dL/dz = W1^T g_a written out
+// (level 0 into g_y, the upsampled channels into gz).  Weight gradients: per
+// 16-wide chunk of hidden units, each wave stages the chunk's a and g_a of
+// its 64 pixels and accumulates X^T Y on v_mfma_f32_16x16x4f32; the bias
+// columns ride along (z[7] = 1, hidden unit HS = 1).
+template <int HS, int NRES>
+__device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bid) {
+  constexpr int T = SYN_HD, RS = T / 2 + 4;
+  constexpr int NC = (HS + 1 + 15) / 16;  // chunks of the hidden units (+ the bias unit)
+  constexpr int NCG = (HS + 15) / 16;     // chunks holding hidden units
+  constexpr int SYZ = 9, SXT = 3, SYA = 17, SXG = 17;      // staged row lengths
+  constexpr int STG = 64 * (SYZ + SXT + SYA + SXG);        // per wave
+  constexpr int ZPOOL = (MAXL - 1) * RS * (RS + 1) + (MAXL - 1) * T * (RS + 1);
+  constexpr int NH = HS * MAXL + HS + 3 * HS + 3;          // head parameters (upper bound over L)
+  constexpr int P1 = 4 * STG > ZPOOL ? 4 * STG : ZPOOL;
+  constexpr int POOL = P1 > 4 * NH ? P1 : 4 * NH;
+  __shared__ SynW<HS, NRES> sw;
+  __shared__ __align__(16) float pool[POOL];
+  float (*s_s)[RS][RS + 1] = reinterpret_cast<float (*)[RS][RS + 1]>(pool);
+  float (*s_v)[T][RS + 1] = reinterpret_cast<float (*)[T][RS + 1]>(pool + (MAXL - 1) * RS * (RS + 1));
+  const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h1 = a.geo.lh[1], w1 = a.geo.lw[1], lo1 = a.geo.loff[1];
+  const int ntx = (W + T - 1) / T;
+  const int i0 = (bid / ntx) * T, j0 = (bid % ntx) * T;
+  const int r0 = i0 / 2 - 2, c0 = j0 / 2 - 2;
+  const int nch = L - 1;
+  float kv[UPS_K], kh[UPS_K];
+  load_taps(a.ups0, kv, kh);
+  stage_weights(sw, a.w, L, tid);
+  // ---- z (the computation of syn_t0_body on this tile)
+  for (int p = tid; p < nch * RS * RS; p += 256) {
+    const int c = p / (RS * RS), rem = p % (RS * RS), rr = rem / RS, cc = rem % RS;
+    const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
+    s_s[c][rr][cc] = c == 0 ? quantise(a.y, a.u, lo1 + q, a.quant) : a.up1[(size_t)(c - 1) * h1 * w1 + q];
+  }
+  __syncthreads();
+  for (int p = tid; p < nch * T * RS; p += 256) {
+    const int c = p / (T * RS), rem = p % (T * RS), ti = rem / RS, cc = rem % RS;
+    const int i = i0 + ti;
+    float vt[4];
+    parity_taps(kv, i & 1, vt);
+    float v = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ky = 2 * q + 1 - (i & 1);
+      v = __builtin_fmaf(vt[q], s_s[c][((i + UPS_P - ky) >> 1) - r0][cc], v);
+    }
+    s_v[c][ti][cc] = v;
+  }
+  __syncthreads();
+  const int ti = tid / T, tj = tid % T, pi = i0 + ti, pj = j0 + tj;
+  const bool own = pi < H && pj < W;
+  const int i = min(pi, H - 1), j = min(pj, W - 1);
+  float zz[8], gpt[3], gz[7];
+  zz[0] = own ? quantise(a.y, a.u, i * W + j, a.quant) : 0.0f;
+  {
+    int col[4];
+    float ht[4];
+    parity_taps(kh, pj & 1, ht);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kx = 2 * q + 1 - (pj & 1);
+      col[q] = ((pj + UPS_P - kx) >> 1) - c0;
+    }
+#pragma unroll
+    for (int c = 1; c < 7; ++c) {
+      float acc = 0.0f;
+      if (c < L) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+      }
+      zz[c] = own ? acc : 0.0f;
+    }
+  }
+  zz[7] = own ? 1.0f : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gpt[c] = own ? a.gpt[(size_t)c * H * W + i * W + j] : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) gz[c] = 0.0f;
+  __syncthreads();  // the z staging is dead: the pool becomes per-wave staging
+  float* Yz = pool + wave * STG;
+  float* Xt = Yz + 64 * SYZ;
+  float* Ya = Xt + 64 * SXT;
+  float* Xg = Ya + 64 * SYA;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) Yz[lane * SYZ + c] = zz[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Xt[lane * SXT + c] = gpt[c];
+  f32x4 accW1[NCG][1], accW2[1][NC];
+  zero_acc(accW1);
+  zero_acc(accW2);
+  const int col = lane & 15;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    // opaque zero: this chunk's weight reads stay in this chunk
+    int wz = 0;
+    asm volatile("" : "+s"(wz));
+    const SynW<HS, NRES>& swl = *reinterpret_cast<const SynW<HS, NRES>*>(reinterpret_cast<const char*>(&sw) + wz);
+#pragma unroll 4
+    for (int u = 0; u < 16; ++u) {
+      const int f = 16 * k + u;
+      float av = 0.0f, gv = 0.0f;
+      if (f < HS) {
+        const f32x4 w0 = *reinterpret_cast<const f32x4*>(&swl.W1p[f][0]);
+        const f32x4 w1 = *reinterpret_cast<const f32x4*>(&swl.W1p[f][4]);
+        const f32x4 w2 = *reinterpret_cast<const f32x4*>(&swl.W2t[f][0]);
+        const float pre = w0.x * zz[0] + w0.y * zz[1] + w0.z * zz[2] + w0.w * zz[3] + w1.x * zz[4] + w1.y * zz[5] +
+                          w1.z * zz[6] + w1.w * zz[7];
+        float g = w2.x * gpt[0] + w2.y * gpt[1] + w2.z * gpt[2];
+        g = pre > 0.0f ? g : 0.0f;
+        av = fmaxf(pre, 0.0f);
+        gv = g;
+        gz[0] += w0.x * g; gz[1] += w0.y * g; gz[2] += w0.z * g; gz[3] += w0.w * g;
+        gz[4] += w1.x * g; gz[5] += w1.y * g; gz[6] += w1.z * g;
+      } else if (f == HS) {
+        av = own ? 1.0f : 0.0f;  // the bias unit of the second layer
+      }
+      Ya[lane * SYA + u] = av;
+      Xg[lane * SXG + u] = gv;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int item = 4 * t + (lane >> 4);
+      const float xt = Xt[item * SXT + min(col, 2)];
+      const float ya = Ya[item * SYA + col];
+      accW2[0][k] = mfma16x16x4(col < 3 ? xt : 0.0f, ya, accW2[0][k]);
+      if (k < NCG) {
+        const float xg = Xg[item * SXG + col];
+        const float yz = Yz[item * SYZ + min(col, 7)];
+        accW1[k < NCG ? k : 0][0] = mfma16x16x4(xg, col < 8 ? yz : 0.0f, accW1[k < NCG ? k : 0][0]);
+      }
+    }
+    wave_lds_sync();
+  }
+  if (own) {
+    const int px = pi * W + pj;
+    a.g_y[px] = gz[0];
+#pragma unroll
+    for (int c = 1; c < 7; ++c)
+      if (c < L) a.gz[(size_t)(c - 1) * H * W + px] = gz[c];
+  }
+  // ---- block partials: W1 [HS][L], b1 [HS], W2 [3][HS], b2 [3]
+  __syncthreads();
+  const int nh = HS * L + HS + 3 * HS + 3;
+  const int oW1 = 0, ob1 = HS * L, oW2 = ob1 + HS, ob2 = oW2 + 3 * HS;
+  float* rw = pool + wave * nh;
+  const int lg = lane >> 4, lc = lane & 15;
+#pragma unroll
+  for (int bm = 0; bm < NCG; ++bm)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int f = 16 * bm + 4 * lg + r, c = lc;  // X index = hidden unit, Y index = z channel (7 = bias)
@@ -634,7 +745,7 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
       }
     }
 #pragma unroll
-  for (int bn = 0; bn < BNA; ++bn)
+  for (int bn = 0; bn < NC; ++bn)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = 4 * lg + r, f = 16 * bn + lc;  // X index = output channel, Y index = hidden unit (HS = bias)
@@ -643,33 +754,9 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
         else if (f == HS) rw[ob2 + c] = accW2[0][bn][r];
       }
     }
-#pragma unroll
-  for (int rr = 0; rr < NRES; ++rr) {
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int oc = 4 * lg + r, k = 16 * bn + lc;
-        if (oc < 3) {
-          if (k < 27) rw[ores + rr * 84 + oc * 27 + k] = accR[rr][0][bn][r];
-          else if (k == 27) rw[ores + rr * 84 + 81 + oc] = accR[rr][0][bn][r];
-        }
-      }
-  }
-  __shared__ float s_red[SYN_THREADS / 64];
-  sse = wave_sum(sse);
-  if (lane == 0) s_red[wave] = sse;
   __syncthreads();
-  for (int p = tid0; p < n_syn; p += SYN_THREADS) {
-    float acc = 0.0f;
-    for (int k = 0; k < SYN_THREADS / 64; ++k) acc += red[k * n_syn + p];
-    a.wpart[(size_t)bid * n_syn + p] = acc;
-  }
-  if (tid0 == 0) {
-    float acc = 0.0f;
-    for (int k = 0; k < SYN_THREADS / 64; ++k) acc += s_red[k];
-    a.spart[bid] = acc;
-  }
+  for (int p = tid; p < nh; p += 256)
+    a.hpart[(size_t)bid * nh + p] = ((pool[p] + pool[nh + p]) + pool[2 * nh + p]) + pool[3 * nh + p];
 }
 
 template <int HS, int NRES>
@@ -702,6 +789,17 @@ __global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel_batch(const Syn
   syn_bwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
 }
 
+template <int HS, int NRES>
+__global__ __launch_bounds__(256) void syn_head_bwd_kernel(SynArgs a) {
+  syn_head_bwd_body<HS, NRES>(a, blockIdx.x);
+}
+template <int HS, int NRES>
+__global__ __launch_bounds__(256) void syn_head_bwd_kernel_batch(const SynArgs* __restrict__ d,
+                                                                 const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  syn_head_bwd_body<HS, NRES>(d[it.img], it.bid);
+}
+
 #define CC_SYN_TABLE(KERNEL)                                         \
   if (nres == 1) switch (Hs) {                                       \
       case 8: return (const void*)KERNEL<8, 1>;                                   \
@@ -728,6 +826,10 @@ const void* syn_t0_kernel_for(int Hs, int nres, bool batch) {
 const void* syn_res_fwd_kernel_for(int Hs, int nres, bool batch) {
   if (batch) { CC_SYN_TABLE(syn_res_fwd_kernel_batch) }
   CC_SYN_TABLE(syn_res_fwd_kernel)
+}
+const void* syn_head_bwd_kernel_for(int Hs, int nres, bool batch) {
+  if (batch) { CC_SYN_TABLE(syn_head_bwd_kernel_batch) }
+  CC_SYN_TABLE(syn_head_bwd_kernel)
 }
 const void* syn_bwd_kernel_for(int Hs, int nres, bool batch) {
   if (batch) { CC_SYN_TABLE(syn_bwd_kernel_batch) }
