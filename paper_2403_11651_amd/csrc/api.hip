@@ -106,13 +106,12 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   P->syn_grid = syn_grid > 0 ? std::min(syn_grid, P->syn_tiles) : std::min(P->syn_tiles, MAX_GRID);
   for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);  // tiles
   P->fold_grid = cdiv(g.n_lat, 256);
-  // column reductions: 16 columns per block for the wide ARM / synthesis
-  // partials (at most MAX_GRID rows), one column per block for the tall
-  // upsampling partials (tiles x channels rows)
-  P->red_blocks_arm = cdiv((int)P->n_arm, 16);
+  // column reductions, one column per block (256 row groups: every column
+  // has hundreds to thousands of partial rows)
+  P->red_blocks_arm = (int)P->n_arm;
   P->n_head = P->Hs * L + 4 * P->Hs + 3;
   P->head_grid = cdiv(p->H, SYN_HD) * cdiv(p->W, SYN_HD);
-  P->red_blocks_syn = cdiv(P->nres * 84, 16) + cdiv(P->n_head, 16);
+  P->red_blocks_syn = P->nres * 84 + P->n_head;
   P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
   for (int s = 0; s + 1 < L; ++s) {
     P->red_blocks_ups[s] = 2 * UPS_K;
@@ -351,11 +350,11 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     blk += cdiv(cols, cpb);
     ++ns;
   };
-  add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 16, g_arm);
+  add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 1, g_arm);
   for (int s = 0; s + 1 < L; ++s)
     add(W + P.upart[s], P.ups_grid[s] * (L - 1 - s), 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
-  add(W + P.hpart, P.head_grid, P.n_head, 16, g_syn);                                // W1, b1, W2, b2
-  add(W + P.wpart_syn, P.syn_grid, P.nres * 84, 16, g_syn + (P.n_syn - P.nres * 84));  // residual convs
+  add(W + P.hpart, P.head_grid, P.n_head, 1, g_syn);                                 // W1, b1, W2, b2
+  add(W + P.wpart_syn, P.syn_grid, P.nres * 84, 1, g_syn + (P.n_syn - P.nres * 84));  // residual convs
   ca.nseg = ns;
   ca.block_start[ns] = blk;
   ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
