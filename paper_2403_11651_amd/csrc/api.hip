@@ -16,10 +16,11 @@ namespace {
 
 constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
 constexpr int MAX_GRID = 512;
-// Default ARM grid: the ARM launch runs beside the upsampling / synthesis
-// launches and each of its work-groups holds ~78 KB of LDS; 384 work-groups
-// (1.5 per CU of the 256-CU MI355X) leave part of the CUs to the other stream
-// (measured: 319.6 us per 768x512 iteration against 328.9 us with 512).
+// Default ARM grid: the ARM launch runs beside the head backward and the
+// upsampling-adjoint launches, and each of its work-groups holds ~78 KB of
+// LDS; 384 work-groups (1.5 per CU of the 256-CU MI355X) leave part of the
+// CUs to the other stream (measured: 296.9 us per 768x512 iteration against
+// 318.1 us with 512 and 321.0 us with 768).
 constexpr int ARM_DEFAULT_GRID = 384;
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -394,11 +395,13 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   Side* sd = nullptr;
   if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
-  if ((rc = fork_to(sd, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
   if (b.upf_grid && (rc = launch((const void*)ups_fwd_kernel, b.upf_grid, 256, &b.upf, st))) return rc;
   if ((rc = launch(t0k, b.t0_grid, 256, &b.syn, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, bwk, P.syn_grid, SYN_THREADS, &b.syn, st))) return rc;
+  // the ARM (independent of the synthesis chain) on the side stream, beside
+  // the head backward and the latency-bound upsampling adjoint launches
+  if ((rc = fork_to(sd, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
@@ -617,6 +620,9 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   Side* sd = nullptr;
   if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
+  if ((rc = go(CC_STAGE_NONE, (const void*)ups_fwd_kernel_batch, B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
+  if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
+  if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
   if ((rc = fork_to(sd, st))) return rc;
   {
     // the ARM launch goes to the side stream
@@ -628,9 +634,6 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (hipLaunchKernel(B.armk, dim3(B.n_arm), dim3(ARM_THREADS), argv, 0, sd->stream) != hipSuccess) return CC_EHIP;
     if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
   }
-  if ((rc = go(CC_STAGE_NONE, (const void*)ups_fwd_kernel_batch, B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
-  if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
-  if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
   if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
   for (int s = 0; s + 1 < B.L; ++s)
     if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
