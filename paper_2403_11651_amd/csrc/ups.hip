@@ -109,6 +109,7 @@ constexpr int UT = 16;                 // input positions per tile side
 constexpr int UP_N = UT + 4;           // padded indices per tile side: [m0-2, m0+UT+2)
 constexpr int UR_N = 2 * UT + 14;      // output rows / columns read: [2m0-7, 2m0+2UT+7)
 
+// (explicit FMAs: every kernel built from this body rounds identically)
 __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid, const int ntiles, const int ch) {
   __shared__ float s_g[UR_N * UR_N];
   __shared__ float s_T[UR_N * UP_N];   // [output row][padded column]
@@ -149,14 +150,14 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
         const int row = p / UP_N, pc = p % UP_N;
         float acc = 0.0f;
 #pragma unroll
-        for (int k = 0; k < UPS_K; ++k) acc += hh[k] * s_g[row * UR_N + 2 * pc + k];
+        for (int k = 0; k < UPS_K; ++k) acc = __builtin_fmaf(hh[k], s_g[row * UR_N + 2 * pc + k], acc);
         s_T[p] = acc;
       }
       {  // T2[pr][col] = sum_ky v[ky] g[2 pr + ky][col]
         const int pr = p / UR_N, col = p % UR_N;
         float acc = 0.0f;
 #pragma unroll
-        for (int k = 0; k < UPS_K; ++k) acc += v[k] * s_g[(2 * pr + k) * UR_N + col];
+        for (int k = 0; k < UPS_K; ++k) acc = __builtin_fmaf(v[k], s_g[(2 * pr + k) * UR_N + col], acc);
         s_T2[p] = acc;
       }
     }
@@ -165,7 +166,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
       const int pr = p / UP_N, pc = p % UP_N;
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k < UPS_K; ++k) acc += v[k] * s_T[(2 * pr + k) * UP_N + pc];
+      for (int k = 0; k < UPS_K; ++k) acc = __builtin_fmaf(v[k], s_T[(2 * pr + k) * UP_N + pc], acc);
       s_P[p] = acc;
     }
     __syncthreads();
@@ -182,8 +183,8 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
           gsum += s_P[ca[i] * UP_N + cb[j]];
 #pragma unroll
           for (int k = 0; k < UPS_K; ++k) {
-            gv[k] += inval * s_T[(2 * ca[i] + k) * UP_N + cb[j]];
-            gh[k] += inval * s_T2[ca[i] * UR_N + 2 * cb[j] + k];
+            gv[k] = __builtin_fmaf(inval, s_T[(2 * ca[i] + k) * UP_N + cb[j]], gv[k]);
+            gh[k] = __builtin_fmaf(inval, s_T2[ca[i] * UR_N + 2 * cb[j] + k], gh[k]);
           }
         }
       }
