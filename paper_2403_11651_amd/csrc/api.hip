@@ -34,6 +34,7 @@ struct Plan {
   int arm_grid, syn_grid, syn_tiles_x, syn_tiles, fold_grid, red_grid;
   int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
+  int ups_cpb[MAXL], ups_chunks[MAXL];  // channels per upsampling-adjoint block, blocks per tile
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
@@ -110,7 +111,13 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   P->syn_tiles_x = cdiv(p->W, SYN_T);
   P->syn_tiles = P->syn_tiles_x * cdiv(p->H, SYN_T);
   P->syn_grid = syn_grid > 0 ? std::min(syn_grid, P->syn_tiles) : std::min(P->syn_tiles, MAX_GRID);
-  for (int s = 0; s + 1 < L; ++s) P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);  // tiles
+  for (int s = 0; s + 1 < L; ++s) {
+    P->ups_grid[s] = cdiv(g.lh[s + 1], 16) * cdiv(g.lw[s + 1], 16);  // tiles
+    // a level with enough tiles to fill the device takes every channel of a
+    // tile in one block; the small levels keep one channel per block
+    P->ups_cpb[s] = P->ups_grid[s] >= 256 ? L - 1 - s : 1;
+    P->ups_chunks[s] = cdiv(L - 1 - s, P->ups_cpb[s]);
+  }
   P->fold_grid = cdiv(g.n_lat, 256);
   // column reductions, one column per block (256 row groups: every column
   // has hundreds to thousands of partial rows)
@@ -137,7 +144,7 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->gpt = take(cur, (size_t)3 * p->H * p->W);
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
     P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
-    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * (L - 1 - s) * 2 * UPS_K);
+    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * P->ups_chunks[s] * 2 * UPS_K);
     P->flags = take(cur, (size_t)P->red_grid + P->fold_grid);
   }
   P->total = cur;
@@ -347,6 +354,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ua.g_y = g_y + P.geo.loff[s + 1];
     ua.g_out = (s + 1 <= L - 2) ? W + P.gb[s + 1] : nullptr;
     ua.part = W + P.upart[s];
+    ua.cpb = P.ups_cpb[s];
   }
   CombineArgs& ca = b->comb;
   int ns = 0, blk = 0;
@@ -358,7 +366,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   };
   add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 1, g_arm);
   for (int s = 0; s + 1 < L; ++s)
-    add(W + P.upart[s], P.ups_grid[s] * (L - 1 - s), 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
+    add(W + P.upart[s], P.ups_grid[s] * P.ups_chunks[s], 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
   add(W + P.hpart, P.head_grid, P.n_head, 1, g_syn);                                 // W1, b1, W2, b2
   add(W + P.wpart_syn, P.syn_grid, P.nres * 84, 1, g_syn + (P.n_syn - P.nres * 84));  // residual convs
   ca.nseg = ns;
@@ -405,7 +413,7 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
-    if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], L - 1 - s), dim3(256), argv, 0, st) !=
+    if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0, st) !=
         hipSuccess)
       return CC_EHIP;
   }
@@ -482,7 +490,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     const Plan& P = plans[k];
     items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
-    for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * (L - 1 - s);
+    for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
   blk(sizeof(WorkItem) * items + 256 * (L + 8));
   *total_bytes = cur + d;
@@ -560,8 +568,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
     for (int i = 0; i < P.head_grid; ++i) w_head.push_back(WorkItem{k, i, P.head_grid, 0});
     for (int s = 0; s + 1 < L; ++s)
-      for (int ch = 0; ch < L - 1 - s; ++ch)
-        for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], ch});
+      for (int c = 0; c < P.ups_chunks[s]; ++c)
+        for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], c});
     for (int i = 0; i < b->comb_grid; ++i) w_comb.push_back(WorkItem{k, i, b->comb_grid, 0});
   }
   delete b;
@@ -681,8 +689,10 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
     return CC_EINVAL;
   AdamArgs a{theta, grad, m, v, n, step, lr, beta1, beta2, eps};
   const bool vec = ((uintptr_t)theta | (uintptr_t)grad | (uintptr_t)m | (uintptr_t)v) % 16 == 0;
-  // at most 512 blocks: the completion counter takes one atomic per block
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 512));
+  // one pass of ADAM_U float4 groups per thread where that takes at most
+  // 512 blocks (the completion counter takes one atomic per block)
+  const int64_t per_block = 256 * 4 * ADAM_U;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 512));
   (void)hipGetLastError();
   int rc = launch(vec ? (const void*)adam_kernel<true> : (const void*)adam_kernel<false>, grid, 256, &a,
                   (hipStream_t)stream);

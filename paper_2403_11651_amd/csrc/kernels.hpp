@@ -68,7 +68,8 @@ struct UpsBwdArgs {
   const float* g_in;   // [(L-1-s)][h_s][w_s]: gradient of U_s's output
   float* g_y;          // level s+1 of the packed latent gradient (channel 0 of g_stack_{s+1})
   float* g_out;        // [(L-2-s)][h_{s+1}][w_{s+1}]: channels 1.. of g_stack_{s+1}; null when s = L-2
-  float* part;         // [gridDim][2K] tap-gradient partials
+  float* part;         // [chunks][tiles][2K] tap-gradient partials
+  int cpb;             // channels of stack_{s+1} per block: block (tile, chunk) takes [chunk cpb, chunk cpb + cpb)
 };
 __global__ void ups_bwd_kernel(UpsBwdArgs a);
 __global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
@@ -149,6 +150,7 @@ struct AdamArgs {
   int32_t* step;
   float lr, beta1, beta2, eps;
 };
+constexpr int ADAM_U = 4;  // float4 groups per thread and pass (vector form)
 template <bool VEC>
 __global__ void adam_kernel(AdamArgs a);
 __global__ void noise_kernel(float* u, int64_t n, uint32_t k0, uint32_t k1, const int32_t* step, uint32_t stream_id);

@@ -16,20 +16,23 @@ __device__ bool arm_fold_one(const FoldArgs& a, int q) {
   const int wl = a.geo.lw[l], local = q - a.geo.loff[l];
   const int i = local / wl, j = local % wl;
   const int ti = i / ARM_TH, tj = j / ARM_TW;
-  float G = 0.0f;
-  for (int da = 0; da <= 1; ++da) {
-    const int ta = ti + da;
-    if (ta >= a.tiles.nth[l]) continue;
-    for (int db = -1; db <= 1; ++db) {
-      const int tb = tj + db;
-      if (tb < 0 || tb >= a.tiles.ntw[l]) continue;
-      const int fa = i - (ta * ARM_TH - 3), fb = j - (tb * ARM_TW - 3);
-      if (fa < 0 || fa >= ARM_EH || fb < 0 || fb >= ARM_EW) continue;
-      const int tile = a.tiles.base[l] + ta * a.tiles.ntw[l] + tb;
-      G += a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb];
-    }
+  // all six candidate frames are read at once (0 where the tile does not
+  // exist or its frame misses q), then added in fixed order
+  float f[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int ta = ti + k / 3, tb = tj + k % 3 - 1;
+    const int fa = i - (ta * ARM_TH - 3), fb = j - (tb * ARM_TW - 3);
+    const bool ok = ta < a.tiles.nth[l] && tb >= 0 && tb < a.tiles.ntw[l] && fa >= 0 && fa < ARM_EH && fb >= 0 &&
+                    fb < ARM_EW;
+    const int tile = a.tiles.base[l] + ta * a.tiles.ntw[l] + tb;
+    f[k] = ok ? a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb] : 0.0f;
   }
-  const float v = a.g_y[q] + G;
+  const float gy = a.g_y[q];
+  float G = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) G += f[k];
+  const float v = gy + G;
   a.g_y[q] = v;
   return finitef(v);
 }
@@ -53,8 +56,10 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
     const int cl = tid % cpb, rg = tid / cpb;
     const int col = (bid - a.block_start[sg]) * cpb + cl;
     float acc = 0.0f;
-    if (col < S.cols)
+    if (col < S.cols) {
+#pragma unroll 4
       for (int r = rg; r < S.rows; r += ngroups) acc += S.src[(size_t)r * S.ld + col];
+    }
     s_p[tid] = acc;
     __syncthreads();
     for (int stride = ngroups / 2; stride >= 1; stride >>= 1) {
@@ -77,27 +82,38 @@ __global__ __launch_bounds__(256) void combine_kernel_batch(const CombineArgs* _
   combine_body(d[it.img], it.bid);
 }
 
-__device__ float block_sum_fixed(const float* src, int n, float* s_tmp) {
+// Three block sums in one pass: each thread adds its strided share of every
+// array in index order (the loads of a share are issued together), then one
+// fixed tree per array.
+__device__ void block_sum3(const float* const src[3], const int n[3], float* s_tmp, float out[3]) {
   const int tid = threadIdx.x;
-  float acc = 0.0f;
-  for (int i = tid; i < n; i += 256) acc += src[i];
-  s_tmp[tid] = acc;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int i = tid; i < n[k]; i += 256) acc += src[k][i];
+    s_tmp[k * 256 + tid] = acc;
+  }
   __syncthreads();
   for (int stride = 128; stride >= 1; stride >>= 1) {
-    if (tid < stride) s_tmp[tid] += s_tmp[tid + stride];
+    if (tid < stride) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s_tmp[k * 256 + tid] += s_tmp[k * 256 + tid + stride];
+    }
     __syncthreads();
   }
-  const float v = s_tmp[0];
-  __syncthreads();
-  return v;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = s_tmp[k * 256];
 }
 
 // loss4 = {D + lambda R / (HW), D, R, non-finite flag} (Eq. (1); D = SSE / 3HW).
 __device__ __forceinline__ void finalize_body(const FinalArgs& a) {
-  __shared__ float s_tmp[256];
-  const float R = a.have_rate ? block_sum_fixed(a.rpart, a.nr, s_tmp) : 0.0f;
-  const float sse = a.have_sse ? block_sum_fixed(a.spart, a.ns, s_tmp) : 0.0f;
-  const float fl = a.nflags ? block_sum_fixed(a.flags, a.nflags, s_tmp) : 0.0f;
+  __shared__ float s_tmp[3 * 256];
+  const float* const src[3] = {a.rpart, a.spart, a.flags};
+  const int n[3] = {a.have_rate ? a.nr : 0, a.have_sse ? a.ns : 0, a.nflags};
+  float sums[3];
+  block_sum3(src, n, s_tmp, sums);
+  const float R = sums[0], sse = sums[1], fl = sums[2];
   if (threadIdx.x == 0) {
     // explicit rounding steps, so that every kernel built from this body
     // (single image or batched) computes the loss the same way
@@ -136,19 +152,34 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const int64_t stride = (int64_t)gridDim.x * 256, first = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t done = 0;
   if (VEC) {
+    // ADAM_U float4 groups per thread and pass, all loads issued before any
+    // store (the four arrays do not overlap)
     const int64_t n4 = a.n / 4;
-    for (int64_t i = first; i < n4; i += stride) {
-      float4 th = reinterpret_cast<float4*>(a.theta)[i];
-      const float4 g = reinterpret_cast<const float4*>(a.g)[i];
-      float4 m = reinterpret_cast<float4*>(a.m)[i];
-      float4 v = reinterpret_cast<float4*>(a.v)[i];
-      adam_one(a, k1, k2, th.x, g.x, m.x, v.x);
-      adam_one(a, k1, k2, th.y, g.y, m.y, v.y);
-      adam_one(a, k1, k2, th.z, g.z, m.z, v.z);
-      adam_one(a, k1, k2, th.w, g.w, m.w, v.w);
-      reinterpret_cast<float4*>(a.m)[i] = m;
-      reinterpret_cast<float4*>(a.v)[i] = v;
-      reinterpret_cast<float4*>(a.theta)[i] = th;
+    float4* __restrict__ th4 = reinterpret_cast<float4*>(a.theta);
+    const float4* __restrict__ g4 = reinterpret_cast<const float4*>(a.g);
+    float4* __restrict__ m4 = reinterpret_cast<float4*>(a.m);
+    float4* __restrict__ v4 = reinterpret_cast<float4*>(a.v);
+    const int64_t base = (int64_t)blockIdx.x * 256 * ADAM_U + threadIdx.x;
+    for (int64_t i0 = base; i0 < n4; i0 += stride * ADAM_U) {
+      float4 th[ADAM_U], g[ADAM_U], m[ADAM_U], v[ADAM_U];
+#pragma unroll
+      for (int u = 0; u < ADAM_U; ++u) {
+        const int64_t i = i0 + u * 256;
+        if (i < n4) { th[u] = th4[i]; g[u] = g4[i]; m[u] = m4[i]; v[u] = v4[i]; }
+      }
+#pragma unroll
+      for (int u = 0; u < ADAM_U; ++u) {
+        const int64_t i = i0 + u * 256;
+        if (i < n4) {
+          adam_one(a, k1, k2, th[u].x, g[u].x, m[u].x, v[u].x);
+          adam_one(a, k1, k2, th[u].y, g[u].y, m[u].y, v[u].y);
+          adam_one(a, k1, k2, th[u].z, g[u].z, m[u].z, v[u].z);
+          adam_one(a, k1, k2, th[u].w, g[u].w, m[u].w, v[u].w);
+          m4[i] = m[u];
+          v4[i] = v[u];
+          th4[i] = th[u];
+        }
+      }
     }
     done = n4 * 4;
   }

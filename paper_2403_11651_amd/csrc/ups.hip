@@ -95,7 +95,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
 }
 
 // Adjoint of step s.  One work-group per UT x UT tile of input positions
-// (level s+1) and channel, one thread per position.  With padded input
+// (level s+1) and chunk of channels, one thread per position.  With padded input
 // indices m' (before clamping), the transpose of the clamped gather is
 //   g_pad[m'_r][m'_c] = sum_{ky, kx} v[ky] h[kx] g_out[2m'_r+ky-3][2m'_c+kx-3]
 // (outputs outside the level-s grid are zero), and an input takes the sum of
@@ -109,18 +109,22 @@ constexpr int UT = 16;                 // input positions per tile side
 constexpr int UP_N = UT + 4;           // padded indices per tile side: [m0-2, m0+UT+2)
 constexpr int UR_N = 2 * UT + 14;      // output rows / columns read: [2m0-7, 2m0+2UT+7)
 
+// A block takes one input tile and the channels [chunk cpb, chunk cpb + cpb)
+// of stack_{s+1} in turn (the next channel's output-gradient region is
+// fetched into registers while the current one is processed); the tap
+// gradients of all its channels go to one partial row.
 // (explicit FMAs: every kernel built from this body rounds identically)
-__device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid, const int ntiles, const int ch) {
+__device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid, const int ntiles, const int chunk) {
   __shared__ float s_g[UR_N * UR_N];
   __shared__ float s_T[UR_N * UP_N];   // [output row][padded column]
   __shared__ float s_T2[UP_N * UR_N];  // [padded row][output column]
   __shared__ float s_P[UP_N * UP_N];   // g_pad
+  constexpr int NPF = (UR_N * UR_N + 255) / 256;
   const int s = a.s, L = a.geo.L, tid = threadIdx.x;
   const int ho = a.geo.lh[s], wo = a.geo.lw[s], hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1];
   const int ntx = (wi + UT - 1) / UT;
-  const int r0 = (bid / ntx) * UT, c0 = (bid % ntx) * UT;  // ch: channel of stack_{s+1} handled here
-  const int tr = tid / UT, tc = tid % UT, r = r0 + tr, c = c0 + tc;
-  const bool in_tile = r < hi && c < wi;
+  const int r0 = (bid / ntx) * UT, c0 = (bid % ntx) * UT;
+  const int c_lo = chunk * a.cpb, c_hi = min(L - 1 - s, c_lo + a.cpb);
   float v[UPS_K], hh[UPS_K], gv[UPS_K], gh[UPS_K];
 #pragma unroll
   for (int k = 0; k < UPS_K; ++k) {
@@ -129,23 +133,47 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     gv[k] = 0.0f;
     gh[k] = 0.0f;
   }
-  // padded indices (local to the tile frame) that clamp to r / c; -1 = none
-  int ca[5], cb[5];
-  ca[0] = tr + 2; ca[1] = r == 0 ? 1 : -1; ca[2] = r == 0 ? 0 : -1;
-  ca[3] = r == hi - 1 ? tr + 3 : -1; ca[4] = r == hi - 1 ? tr + 4 : -1;
-  cb[0] = tc + 2; cb[1] = c == 0 ? 1 : -1; cb[2] = c == 0 ? 0 : -1;
-  cb[3] = c == wi - 1 ? tc + 3 : -1; cb[4] = c == wi - 1 ? tc + 4 : -1;
   const int jr0 = 2 * r0 - 7, jc0 = 2 * c0 - 7;
   const int lo = a.geo.loff[s + 1];
-  (void)L;
-  {
+  float pf[NPF];
+  auto fetch = [&](int ch) {
     const float* gin = a.g_in + (size_t)ch * ho * wo;
-    for (int p = tid; p < UR_N * UR_N; p += 256) {
+    int t = tid;
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int p = t + 256 * q;
       const int jr = jr0 + p / UR_N, jc = jc0 + p % UR_N;
-      s_g[p] = (jr >= 0 && jr < ho && jc >= 0 && jc < wo) ? gin[jr * wo + jc] : 0.0f;
+      pf[q] = (p < UR_N * UR_N && jr >= 0 && jr < ho && jc >= 0 && jc < wo) ? gin[jr * wo + jc] : 0.0f;
+    }
+  };
+  fetch(c_lo);
+  for (int ch = c_lo; ch < c_hi; ++ch) {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int p = tid + 256 * q;
+      if (p < UR_N * UR_N) s_g[p] = pf[q];
     }
     __syncthreads();
-    for (int p = tid; p < UR_N * UP_N; p += 256) {
+    if (ch + 1 < c_hi) fetch(ch + 1);
+    // the thread's indices pass through an empty asm statement so that the
+    // LDS addresses below are formed per channel rather than held in
+    // registers across the loop
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    const int tr = t / UT, tc = t % UT, r = r0 + tr, c = c0 + tc;
+    const bool in_tile = r < hi && c < wi;
+    // padded indices (local to the tile frame) that clamp to r / c; -1 = none
+    int ca[5], cb[5];
+    ca[0] = tr + 2; ca[1] = r == 0 ? 1 : -1; ca[2] = r == 0 ? 0 : -1;
+    ca[3] = r == hi - 1 ? tr + 3 : -1; ca[4] = r == hi - 1 ? tr + 4 : -1;
+    cb[0] = tc + 2; cb[1] = c == 0 ? 1 : -1; cb[2] = c == 0 ? 0 : -1;
+    cb[3] = c == wi - 1 ? tc + 3 : -1; cb[4] = c == wi - 1 ? tc + 4 : -1;
+    const int idx = r * wi + c;
+    float inval = 0.0f;
+    if (in_tile)
+      inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant) : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
+    for (int p = t; p < UR_N * UP_N; p += 256) {
       {  // T[row][pc] = sum_kx h[kx] g[row][2 pc + kx]
         const int row = p / UP_N, pc = p % UP_N;
         float acc = 0.0f;
@@ -162,7 +190,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
       }
     }
     __syncthreads();
-    for (int p = tid; p < UP_N * UP_N; p += 256) {
+    for (int p = t; p < UP_N * UP_N; p += 256) {
       const int pr = p / UP_N, pc = p % UP_N;
       float acc = 0.0f;
 #pragma unroll
@@ -171,8 +199,6 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     }
     __syncthreads();
     if (in_tile) {
-      const int idx = r * wi + c;
-      const float inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant) : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
       float gsum = 0.0f;
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
@@ -204,7 +230,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
   if (tid < 2 * UPS_K) {
     float acc = 0.0f;
     for (int wv = 0; wv < 4; ++wv) acc += s_red[wv][tid];
-    a.part[((size_t)ch * ntiles + bid) * 2 * UPS_K + tid] = acc;
+    a.part[((size_t)chunk * ntiles + bid) * 2 * UPS_K + tid] = acc;
   }
 }
 
