@@ -214,6 +214,31 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
 // (fi0, fj0).  Values at frame positions outside the image are the values at
 // the clamped position (replicate border), so the conv reads its neighbours
 // around the clamped position.  INSIDE: the frame lies inside the image.
+template <int FS, bool INSIDE>
+__device__ __forceinline__ void res_pre(const float* wr, const float* src, int fa, int fb, int fi0, int fj0, int H,
+                                        int W, float (&pre)[3]) {
+  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  int ca = fa, cb = fb;
+  if (!INSIDE) {
+    ca = clampi(fi0 + fa, 0, H - 1) - fi0;
+    cb = clampi(fj0 + fb, 0, W - 1) - fj0;
+  }
+  float nb[3][9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 9; ++d) nb[c][d] = src[c * FA + (ca + d / 3 - 1) * FS + cb + d % 3 - 1];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    float acc = nb[o][4] + wr[81 + o];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 9; ++d) acc += wr[o * 27 + c * 9 + d] * nb[c][d];
+    pre[o] = acc;
+  }
+}
+
 template <int FS, int LO, bool INSIDE>
 __device__ __forceinline__ void res_layer(const float* wr, const float* src, float* dst, int fi0, int fj0, int H,
                                           int W, bool relu, int tid) {
@@ -223,24 +248,37 @@ __device__ __forceinline__ void res_layer(const float* wr, const float* src, flo
   wr += zo;
   for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
     const int fa = LO + p / SIDE, fb = LO + p % SIDE;
-    int ca = fa, cb = fb;
-    if (!INSIDE) {
-      ca = clampi(fi0 + fa, 0, H - 1) - fi0;
-      cb = clampi(fj0 + fb, 0, W - 1) - fj0;
-    }
-    float nb[3][9];
+    float pre[3];
+    res_pre<FS, INSIDE>(wr, src, fa, fb, fi0, fj0, H, W, pre);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int d = 0; d < 9; ++d) nb[c][d] = src[c * FA + (ca + d / 3 - 1) * FS + cb + d % 3 - 1];
+    for (int o = 0; o < 3; ++o) dst[o * FA + fa * FS + fb] = relu ? fmaxf(pre[o], 0.0f) : pre[o];
+  }
+}
+
+// The last residual layer of the backward pass: x_hat on the frame region
+// [LO, FS-LO) is not stored; the region receives dL/dx_hat = dscale (x_hat -
+// x) (zero outside the image) and the tile's own pixels add their squared
+// error to sse.
+template <int FS, int LO, bool INSIDE>
+__device__ __forceinline__ void res_layer_last(const float* wr, const float* src, float* g, int fi0, int fj0,
+                                               int H, int W, const float* __restrict__ img, float dscale, float& sse,
+                                               int tid) {
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX, E = FS / 2 - SYN_T / 2;
+  int zo = 0;
+  asm volatile("" : "+s"(zo));
+  wr += zo;
+  for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
+    const int fa = LO + p / SIDE, fb = LO + p % SIDE;
+    const int ii = fi0 + fa, jj = fj0 + fb;
+    const bool in = ii >= 0 && ii < H && jj >= 0 && jj < W;
+    const bool own = in && fa >= E && fa < E + SYN_T && fb >= E && fb < E + SYN_T;
+    float pre[3];
+    res_pre<FS, INSIDE>(wr, src, fa, fb, fi0, fj0, H, W, pre);
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-      float pre = nb[o][4] + wr[81 + o];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 9; ++d) pre += wr[o * 27 + c * 9 + d] * nb[c][d];
-      dst[o * FA + fa * FS + fb] = relu ? fmaxf(pre, 0.0f) : pre;
+      const float e = in ? pre[o] - img[(size_t)o * H * W + ii * W + jj] : 0.0f;
+      g[o * FA + fa * FS + fb] = dscale * e;
+      if (own) sse += e * e;
     }
   }
 }
@@ -356,6 +394,39 @@ __device__ __forceinline__ void mfma_xty64(f32x4 (&acc)[BM][BN], const float* Xs
   }
 }
 
+// Weight gradient of a residual conv over the tile's own pixels, on the
+// matrix cores with operands read straight from the LDS frames: acc[0][bn]
+// += X^T Y, X[pixel][oc] = g (the gradient at the layer's pre-activation,
+// oc < 3), Y[pixel][k] = the layer input's 3x3 neighbourhood (k = 9 c + d)
+// and a ones column (k = 27).  Wave w takes pixels 64 w .. 64 w + 63 of the
+// tile, four per 16x16x4 step; accumulator r of lane l holds (oc = 4 (l/16)
+// + r, k = 16 bn + l % 16).
+template <int FS, int E>
+__device__ __forceinline__ void conv_wgrad(f32x4 (&acc)[1][2], const float* g, const float* t, int i0, int j0,
+                                           int H, int W, int wave, int lane) {
+  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  const int col = lane & 15, kq = lane >> 4;
+  int ko[2];
+#pragma unroll
+  for (int bn = 0; bn < 2; ++bn) {
+    const int k = 16 * bn + col;
+    ko[bn] = k < 27 ? (k / 9) * FA + ((k % 9) / 3 - 1) * FS + (k % 3) - 1 : 0;
+  }
+#pragma unroll 4
+  for (int step = 0; step < 16; ++step) {
+    const int item = 64 * wave + 4 * step + kq, ty = item / SYN_T, tx = item % SYN_T;
+    const bool own = i0 + ty < H && j0 + tx < W;
+    const int fp = (E + ty) * FS + E + tx;
+    const float av = (own && col < 3) ? g[col * FA + fp] : 0.0f;
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) {
+      const int k = 16 * bn + col;
+      const float bv = !own ? 0.0f : (k < 27 ? t[fp + ko[bn]] : (k == 27 ? 1.0f : 0.0f));
+      acc[0][bn] = mfma16x16x4(av, bv, acc[0][bn]);
+    }
+  }
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
 #pragma unroll
@@ -439,19 +510,16 @@ __device__ __forceinline__ void relu_mask(const float* t, float* g, int tid) {
 template <int HS, int NRES>
 __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, const int nblk) {
   constexpr int FA = SYN_FMAX * SYN_FMAX, E = 2 * NRES, FS = SYN_T + 2 * E;
-  // LDS pool: residual-conv frames (t_0..t_NRES, two gradient buffers) and the
-  // per-wave staging of the conv weight gradients.
-  constexpr int FRAMES = (NRES + 1 + 2) * 3 * FA;
-  constexpr int STG_R = 32 * (3 + (28 | 1));                 // conv staging per wave (32 items)
-  constexpr int POOL = FRAMES + 4 * STG_R;
+  // LDS pool: residual-conv frames t_0..t_{NRES-1} and two gradient buffers
+  // (x_hat = t_NRES is never stored)
+  constexpr int POOL = (NRES + 2) * 3 * FA;
   __shared__ SynW<HS, NRES> sw;
   __shared__ float pool[POOL];
   float (*s_t)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool);
-  float (*s_g)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool + (NRES + 1) * 3 * FA);
+  float (*s_g)[3 * FA] = reinterpret_cast<float (*)[3 * FA]>(pool + NRES * 3 * FA);
 
   const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid0 = threadIdx.x, lane = tid0 & 63, wave = tid0 >> 6;
   stage_weights(sw, a.w, L, tid0);
-  float* stg = pool + FRAMES + wave * STG_R;
 
   f32x4 accR[NRES][1][2];
 #pragma unroll
@@ -468,6 +536,7 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     const int ty = tid / SYN_T, tx = tid % SYN_T;
+    const float* __restrict__ img = a.img;
     // 1. t0 on the frame (clamped coordinates)
     for (int p = tid; p < FS * FS; p += SYN_THREADS) {
       const int fa = p / FS, fb = p % FS;
@@ -476,28 +545,17 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
       for (int c = 0; c < 3; ++c) s_t[0][c * FA + fa * FS + fb] = a.t0[(size_t)c * H * W + ii * W + jj];
     }
     __syncthreads();
-    // 2. residual layers forward, layer r on halo E - r
-    if (inside) res_layer<FS, 1, true>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
-    else res_layer<FS, 1, false>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, NRES > 1, tid);
-    __syncthreads();
+    // 2. residual layers forward, layer r on halo E - r; the last one yields
+    // dL/dx_hat on halo NRES (zero outside the image) and the squared error
     if constexpr (NRES >= 2) {
-      if (inside) res_layer<FS, 2, true>(sw.conv[1], s_t[1], s_t[2], fi0, fj0, H, W, false, tid);
-      else res_layer<FS, 2, false>(sw.conv[1], s_t[1], s_t[2], fi0, fj0, H, W, false, tid);
+      if (inside) res_layer<FS, 1, true>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
+      else res_layer<FS, 1, false>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
       __syncthreads();
-    }
-    // 3. dL/dx_hat on halo NRES; zero outside the image
-    {
-      constexpr int LO = E - NRES, SIDE = SYN_T + 2 * NRES;
-      for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
-        const int fa = LO + p / SIDE, fb = LO + p % SIDE;
-        const int ii = fi0 + fa, jj = fj0 + fb;
-        const bool in = ii >= 0 && ii < H && jj >= 0 && jj < W;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int fp = c * FA + fa * FS + fb;
-          s_g[0][fp] = in ? a.dscale * (s_t[NRES][fp] - a.img[(size_t)c * H * W + ii * W + jj]) : 0.0f;
-        }
-      }
+      if (inside) res_layer_last<FS, 2, true>(sw.conv[1], s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      else res_layer_last<FS, 2, false>(sw.conv[1], s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+    } else {
+      if (inside) res_layer_last<FS, 1, true>(sw.conv[0], s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      else res_layer_last<FS, 1, false>(sw.conv[0], s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
     }
     __syncthreads();
     // 4. residual layers backward: weight gradient over the tile's own pixels,
@@ -511,17 +569,7 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
         relu_mask<FS, E - NRES + 1>(s_t[r], s_g[cur], tid);  // layer r < NRES: halo r = NRES - 1 here
         __syncthreads();
       }
-      {
-        float xv[3], yv[28];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xv[c] = own ? s_g[cur][c * FA + fpo] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int d = 0; d < 9; ++d) yv[c * 9 + d] = own ? s_t[r - 1][c * FA + fpo + (d / 3 - 1) * FS + d % 3 - 1] : 0.0f;
-        yv[27] = own ? 1.0f : 0.0f;
-        xty_accumulate(accR[r - 1], stg, xv, yv, lane);
-      }
+      conv_wgrad<FS, E>(accR[r - 1], s_g[cur], s_t[r - 1], i0, j0, H, W, wave, lane);
       if (r == 2) {
         if (inside) res_adjoint<FS, E - 1, true>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
         else res_adjoint<FS, E - 1, false>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
@@ -532,7 +580,7 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
       cur ^= 1;
       __syncthreads();
     }
-    // 5. per pixel: the gradient at the pre-activation of t0, and the distortion
+    // 5. per pixel: the gradient at the pre-activation of t0
     {
       const int i = i0 + ty, j = j0 + tx;
       if (own) {
@@ -541,8 +589,6 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
           const size_t gi = (size_t)c * H * W + i * W + j;
           const float t0v = s_t[0][c * FA + fpo];
           a.gpt[gi] = t0v > 0.0f ? s_g[cur][c * FA + fpo] : 0.0f;
-          const float e = s_t[NRES][c * FA + fpo] - a.img[gi];
-          sse += e * e;
         }
       }
     }
@@ -779,11 +825,11 @@ __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel_batch(const Sy
   syn_res_fwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
 }
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel(SynArgs a) {
+__global__ __launch_bounds__(SYN_THREADS, 3) void syn_bwd_kernel(SynArgs a) {
   syn_bwd_body<HS, NRES>(a, blockIdx.x, gridDim.x);
 }
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS, 2) void syn_bwd_kernel_batch(const SynArgs* __restrict__ d,
+__global__ __launch_bounds__(SYN_THREADS, 3) void syn_bwd_kernel_batch(const SynArgs* __restrict__ d,
                                                                        const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
   syn_bwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
