@@ -30,20 +30,22 @@ namespace cc {
 
 // Causal neighbour sets (dy, dx), raster order: the C positions of the 7x7
 // window that precede the latent, nearest first (ties in raster order).
-__constant__ signed char c_ctx8[8][2] = {{-2, -1}, {-2, 0}, {-2, 1}, {-1, -1}, {-1, 0}, {-1, 1}, {0, -2}, {0, -1}};
-__constant__ signed char c_ctx16[16][2] = {{-3, -1}, {-3, 0}, {-3, 1}, {-2, -2}, {-2, -1}, {-2, 0}, {-2, 1}, {-2, 2},
-                                           {-1, -2}, {-1, -1}, {-1, 0}, {-1, 1}, {-1, 2}, {0, -3}, {0, -2}, {0, -1}};
-__constant__ signed char c_ctx24[24][2] = {{-3, -3}, {-3, -2}, {-3, -1}, {-3, 0}, {-3, 1}, {-3, 2}, {-3, 3}, {-2, -3},
-                                           {-2, -2}, {-2, -1}, {-2, 0},  {-2, 1}, {-2, 2}, {-2, 3}, {-1, -3}, {-1, -2},
-                                           {-1, -1}, {-1, 0},  {-1, 1},  {-1, 2}, {-1, 3}, {0, -3}, {0, -2},  {0, -1}};
-
+// (compile-time tables: with the loops over k unrolled, every offset is an
+// immediate)
 template <int C>
-__device__ __forceinline__ int ctx_dy(int k) {
-  return C == 8 ? c_ctx8[k][0] : (C == 16 ? c_ctx16[k][0] : c_ctx24[k][0]);
+__device__ __forceinline__ constexpr int ctx_dy(int k) {
+  constexpr signed char t8[8] = {-2, -2, -2, -1, -1, -1, 0, 0};
+  constexpr signed char t16[16] = {-3, -3, -3, -2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0};
+  constexpr signed char t24[24] = {-3, -3, -3, -3, -3, -3, -3, -2, -2, -2, -2, -2,
+                                   -2, -2, -1, -1, -1, -1, -1, -1, -1, 0,  0,  0};
+  return C == 8 ? t8[k] : (C == 16 ? t16[k] : t24[k]);
 }
 template <int C>
-__device__ __forceinline__ int ctx_dx(int k) {
-  return C == 8 ? c_ctx8[k][1] : (C == 16 ? c_ctx16[k][1] : c_ctx24[k][1]);
+__device__ __forceinline__ constexpr int ctx_dx(int k) {
+  constexpr signed char t8[8] = {-1, 0, 1, -1, 0, 1, -2, -1};
+  constexpr signed char t16[16] = {-1, 0, 1, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -3, -2, -1};
+  constexpr signed char t24[24] = {-3, -2, -1, 0, 1, 2, 3, -3, -2, -1, 0, 1, 2, 3, -3, -2, -1, 0, 1, 2, 3, -3, -2, -1};
+  return C == 8 ? t8[k] : (C == 16 ? t16[k] : t24[k]);
 }
 
 constexpr int STG = 36;  // row stride of the per-wave staging matrices
@@ -63,8 +65,9 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
   __shared__ float s_stage[BWD ? ARM_WAVES * 2 * 32 * STG : 1];
 
   // MFMA A operands of every layer, per lane and k-step, in the order the
-  // accumulators hold the features: [0] forward W (A[m = out][k = in]),
-  // [1] transpose (A[m = in][k = out]) for the input gradient
+  // accumulators hold the features: [0] forward W + I (A[m = out][k = in];
+  // the identity carries the residual connection), [1] its transpose
+  // (A[m = in][k = out]) for the input gradient
   __shared__ float s_A[BWD ? 2 : 1][NH][NR][64];
 
   const float* __restrict__ w = a.w;
@@ -72,7 +75,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
     const int ln = idx & 63, t = (idx >> 6) % NR, j = (idx / (64 * NR)) % NH, tr = idx / (64 * NR * NH);
     const int nn = ln & 31, f = dfeat(t, ln >> 5);
     const float* Wj = w + j * (C * C + C);
-    s_A[tr][j][t][ln] = nn < C ? (tr ? Wj[f * C + nn] : Wj[nn * C + f]) : 0.0f;
+    s_A[tr][j][t][ln] = nn < C ? (tr ? Wj[f * C + nn] : Wj[nn * C + f]) + (nn == f ? 1.0f : 0.0f) : 0.0f;
   }
   // per-lane constants: context offsets in the LDS frame, biases and output
   // weights of the features this lane holds
@@ -137,13 +140,14 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
       const float yq = s_yq[own];
 #pragma unroll
       for (int jl = 0; jl < NH; ++jl) {
+        // h <- ReLU((W + I) h + b): the bias is the accumulators' start
         f32x16 acc;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+        for (int r = 0; r < 16; ++r) acc[r] = r < NR ? bias[jl][r] : 0.0f;
 #pragma unroll
         for (int t = 0; t < NR; ++t) acc = mfma32x32x2(s_A[0][jl][t][lane], H[jl][t], acc);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) H[jl + 1][r] = fmaxf(acc[r] + bias[jl][r] + H[jl][r], 0.0f);
+        for (int r = 0; r < NR; ++r) H[jl + 1][r] = fmaxf(acc[r], 0.0f);
       }
       float mu = 0.0f, sg = 0.0f;
 #pragma unroll
@@ -186,14 +190,14 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
             accW[jl] = mfma32x32x2(X[row], Y[row], accW[jl]);
           }
           wave_lds_sync();
-          // input gradient: W^T gp + gp (residual)
+          // input gradient: (W + I)^T gp
           f32x16 acc;
 #pragma unroll
           for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
           for (int t = 0; t < NR; ++t) acc = mfma32x32x2(s_A[BWD ? 1 : 0][jl][t][lane], gp[t], acc);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) gH[r] = acc[r] + gp[r];
+          for (int r = 0; r < NR; ++r) gH[r] = acc[r];
         }
         const int li = rr * ARM_TW + cc0 + n;
 #pragma unroll
@@ -206,13 +210,22 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
       float* ge = a.gext + (size_t)tile * ARM_EXT;
       for (int idx = tid; idx < ARM_EXT; idx += ARM_THREADS) {
         const int fa = idx / ARM_EW, fb = idx % ARM_EW;
-        float G = 0.0f;
+        // every candidate read is issued (from a valid address), then the
+        // in-tile ones are added in order k = 0 .. C-1
+        float v[C];
+        bool ok[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           const int pr = fa - 3 - ctx_dy<C>(k), pc = fb - 3 - ctx_dx<C>(k);
-          if (pr >= 0 && pr < ARM_TH && pc >= 0 && pc < ARM_TW) G += s_gc[(pr * ARM_TW + pc) * CS + k];
+          ok[k] = pr >= 0 && pr < ARM_TH && pc >= 0 && pc < ARM_TW;
+          v[k] = s_gc[(ok[k] ? pr * ARM_TW + pc : 0) * CS + k];
         }
-        if (fa >= 3 && fb >= 3 && fb < ARM_TW + 3) G += s_own[(fa - 3) * ARM_TW + fb - 3];
+        const bool own_in = fa >= 3 && fb >= 3 && fb < ARM_TW + 3;
+        const float vo = s_own[own_in ? (fa - 3) * ARM_TW + fb - 3 : 0];
+        float G = 0.0f;
+#pragma unroll
+        for (int k = 0; k < C; ++k) G += ok[k] ? v[k] : 0.0f;
+        if (own_in) G += vo;
         ge[idx] = G;
       }
       __syncthreads();
