@@ -53,13 +53,17 @@ constexpr int STG = 36;  // row stride of the per-wave staging matrices
 template <int C, int NH, bool BWD>
 __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const int nblk) {
   constexpr int NR = C / 2;            // accumulator rows holding features < C
-  constexpr int CS = C + 1;            // row stride of the context-gradient buffer
+  constexpr int TL = ARM_TH * ARM_TW;  // latents per tile
+  // context gradients of the tile, k-major ([k][latent]) after GC_PAD
+  // padding floats: a frame position's C reads share one base address
+  constexpr int GC_PAD = 256;
   constexpr int NW = NH * (C * C + C) + 2 * C + 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 31, g = lane >> 5;
 
   __shared__ float s_yq[ARM_EXT];
   // context gradients of the tile; reused at the end for per-wave partials
-  constexpr int GC_SIZE = ARM_TH * ARM_TW * CS > ARM_WAVES * NW ? ARM_TH * ARM_TW * CS : ARM_WAVES * NW;
+  constexpr int GC_NEED = 2 * GC_PAD + C * TL;
+  constexpr int GC_SIZE = GC_NEED > ARM_WAVES * NW ? GC_NEED : ARM_WAVES * NW;
   __shared__ float s_gc[BWD ? GC_SIZE : 4 * 64];
   __shared__ float s_own[BWD ? ARM_TH * ARM_TW : 1];
   __shared__ float s_stage[BWD ? ARM_WAVES * 2 * 32 * STG : 1];
@@ -114,6 +118,27 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
 #pragma unroll
   for (int r = 0; r < NR; ++r) { accWo0[r] = 0.0f; accWo1[r] = 0.0f; }
 
+  // the quantised latents of a tile's frame (zero outside the grid), NPF per
+  // thread; the next tile's are fetched while the current one is processed
+  constexpr int NPF = (ARM_EXT + ARM_THREADS - 1) / ARM_THREADS;
+  float pf[NPF];
+  auto fetch = [&](int tile) {
+    int l = 0;
+    while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
+    const int local = tile - a.tiles.base[l];
+    const int i0 = (local / a.tiles.ntw[l]) * ARM_TH, j0 = (local % a.tiles.ntw[l]) * ARM_TW;
+    const int h = a.geo.lh[l], wl = a.geo.lw[l], base = a.geo.loff[l];
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int idx = tid + ARM_THREADS * q;
+      const int ii = i0 - 3 + idx / ARM_EW, jj = j0 - 3 + idx % ARM_EW;
+      float v = 0.0f;
+      if (idx < ARM_EXT && ii >= 0 && ii < h && jj >= 0 && jj < wl) v = quantise(a.y, a.u, base + ii * wl + jj, a.quant);
+      pf[q] = v;
+    }
+  };
+  if (bid < a.tiles.n_tiles) fetch(bid);
+
   for (int tile = bid; tile < a.tiles.n_tiles; tile += nblk) {
     int l = 0;
     while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
@@ -121,13 +146,13 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
     const int i0 = (local / a.tiles.ntw[l]) * ARM_TH, j0 = (local % a.tiles.ntw[l]) * ARM_TW;
     const int h = a.geo.lh[l], wl = a.geo.lw[l], base = a.geo.loff[l];
 
-    for (int idx = tid; idx < ARM_EXT; idx += ARM_THREADS) {
-      const int ii = i0 - 3 + idx / ARM_EW, jj = j0 - 3 + idx % ARM_EW;
-      float v = 0.0f;
-      if (ii >= 0 && ii < h && jj >= 0 && jj < wl) v = quantise(a.y, a.u, base + ii * wl + jj, a.quant);
-      s_yq[idx] = v;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int idx = tid + ARM_THREADS * q;
+      if (idx < ARM_EXT) s_yq[idx] = pf[q];
     }
     __syncthreads();
+    if (tile + nblk < a.tiles.n_tiles) fetch(tile + nblk);
 
     for (int c = wave; c < ARM_TH * ARM_TW / 32; c += ARM_WAVES) {
       const int rr = c / (ARM_TW / 32), cc0 = (c % (ARM_TW / 32)) * 32;
@@ -201,7 +226,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
         }
         const int li = rr * ARM_TW + cc0 + n;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s_gc[li * CS + dfeat(r, g)] = gH[r];
+        for (int r = 0; r < NR; ++r) s_gc[GC_PAD + dfeat(r, g) * TL + li] = gH[r];
         if (g == 0) s_own[li] = valid ? a.scale * ro.dd : 0.0f;
       }
     }
@@ -210,21 +235,23 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
       float* ge = a.gext + (size_t)tile * ARM_EXT;
       for (int idx = tid; idx < ARM_EXT; idx += ARM_THREADS) {
         const int fa = idx / ARM_EW, fb = idx % ARM_EW;
-        // every candidate read is issued (from a valid address), then the
-        // in-tile ones are added in order k = 0 .. C-1
-        float v[C];
-        bool ok[C];
+        // the latent whose k-th neighbour is (fa, fb) is (fa - 3 - dy_k,
+        // fb - 3 - dx_k): every read is base + a constant (inside the padded
+        // buffer), and the in-tile ones are added in order k = 0 .. C-1
+        const int gbase = GC_PAD + (fa - 3) * ARM_TW + fb - 3;
+        bool rv[4], cv[7];  // row valid for dy = -j, column valid for dx = i - 3
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-          const int pr = fa - 3 - ctx_dy<C>(k), pc = fb - 3 - ctx_dx<C>(k);
-          ok[k] = pr >= 0 && pr < ARM_TH && pc >= 0 && pc < ARM_TW;
-          v[k] = s_gc[(ok[k] ? pr * ARM_TW + pc : 0) * CS + k];
-        }
+        for (int j = 0; j < 4; ++j) rv[j] = fa - 3 + j >= 0 && fa - 3 + j < ARM_TH;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) cv[i] = fb - i >= 0 && fb - i < ARM_TW;
+        float v[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = s_gc[gbase + k * TL - ctx_dy<C>(k) * ARM_TW - ctx_dx<C>(k)];
         const bool own_in = fa >= 3 && fb >= 3 && fb < ARM_TW + 3;
         const float vo = s_own[own_in ? (fa - 3) * ARM_TW + fb - 3 : 0];
         float G = 0.0f;
 #pragma unroll
-        for (int k = 0; k < C; ++k) G += ok[k] ? v[k] : 0.0f;
+        for (int k = 0; k < C; ++k) G += (rv[-ctx_dy<C>(k)] && cv[ctx_dx<C>(k) + 3]) ? v[k] : 0.0f;
         if (own_in) G += vo;
         ge[idx] = G;
       }
