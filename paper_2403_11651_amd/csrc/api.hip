@@ -175,7 +175,7 @@ int launch_stage(int stage, const void* fn, int grid, int block, void* args, hip
 // Created once per device on first use (default priority, non-blocking).
 struct Side {
   hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, head = nullptr;
 };
 constexpr int MAX_DEVICES = 64;
 Side g_side[MAX_DEVICES];
@@ -189,6 +189,7 @@ int side_for_current_device(Side** out) {
     if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return CC_EHIP;
     if (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess) return CC_EHIP;
     if (hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) return CC_EHIP;
+    if (hipEventCreateWithFlags(&sd.head, hipEventDisableTiming) != hipSuccess) return CC_EHIP;
   }
   *out = &sd;
   return CC_OK;
@@ -197,6 +198,12 @@ int side_for_current_device(Side** out) {
 int fork_to(Side* sd, hipStream_t main) {
   if (hipEventRecord(sd->fork, main) != hipSuccess) return CC_EHIP;
   return hipStreamWaitEvent(sd->stream, sd->fork, 0) == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+// the side stream waits for the work enqueued on main so far
+int side_waits(Side* sd, hipStream_t main) {
+  if (hipEventRecord(sd->head, main) != hipSuccess) return CC_EHIP;
+  return hipStreamWaitEvent(sd->stream, sd->head, 0) == hipSuccess ? CC_OK : CC_EHIP;
 }
 
 int join_from(Side* sd, hipStream_t main) {
@@ -318,9 +325,9 @@ struct BwdSet {
   UpsFwdArgs upf;
   SynArgs syn;
   UpsBwdArgs upb[MAXL];
-  CombineArgs comb;
+  CombineArgs comb_side, comb_main;
   FinalArgs fin;
-  int upf_grid, t0_grid, comb_grid;
+  int upf_grid, t0_grid, comb_side_grid, comb_main_grid;
 };
 
 void build_backward(const cc_problem* p, const Plan& P, float* W, const float* img, const float* y, const float* u,
@@ -356,27 +363,40 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ua.part = W + P.upart[s];
     ua.cpb = P.ups_cpb[s];
   }
-  CombineArgs& ca = b->comb;
-  int ns = 0, blk = 0;
-  auto add = [&](const float* src, int rows, int cols, int cpb, float* dst) {
-    ca.seg[ns] = RedSeg{src, rows, cols, cols, cpb, dst};
+  // two combine launches: the side one (after the ARM, beside the
+  // upsampling adjoint) sums the ARM and synthesis weight-gradient partials;
+  // the final one sums the upsampling tap partials and folds the ARM context
+  // gradients into g_y
+  auto build = [&](CombineArgs& ca, int* grid, int flag_off, bool final_part) {
+    int ns = 0, blk = 0;
+    auto add = [&](const float* src, int rows, int cols, float* dst) {
+      ca.seg[ns] = RedSeg{src, rows, cols, cols, 1, dst};
+      ca.block_start[ns] = blk;
+      blk += cols;
+      ++ns;
+    };
+    if (!final_part) {
+      add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, g_arm);
+      add(W + P.hpart, P.head_grid, P.n_head, g_syn);                                 // W1, b1, W2, b2
+      add(W + P.wpart_syn, P.syn_grid, P.nres * 84, g_syn + (P.n_syn - P.nres * 84));  // residual convs
+    } else {
+      for (int s = 0; s + 1 < L; ++s)
+        add(W + P.upart[s], P.ups_grid[s] * P.ups_chunks[s], 2 * UPS_K, g_ups + (size_t)s * 2 * UPS_K);
+    }
+    ca.nseg = ns;
     ca.block_start[ns] = blk;
-    blk += cdiv(cols, cpb);
-    ++ns;
+    ca.flags = W + P.flags + flag_off;
+    if (final_part) {
+      ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
+      blk += P.fold_grid;
+    }
+    *grid = blk;
   };
-  add(W + P.wpart_arm, P.arm_grid, (int)P.n_arm, 1, g_arm);
-  for (int s = 0; s + 1 < L; ++s)
-    add(W + P.upart[s], P.ups_grid[s] * P.ups_chunks[s], 2 * UPS_K, 1, g_ups + (size_t)s * 2 * UPS_K);
-  add(W + P.hpart, P.head_grid, P.n_head, 1, g_syn);                                 // W1, b1, W2, b2
-  add(W + P.wpart_syn, P.syn_grid, P.nres * 84, 1, g_syn + (P.n_syn - P.nres * 84));  // residual convs
-  ca.nseg = ns;
-  ca.block_start[ns] = blk;
-  ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
-  ca.flags = W + P.flags;
-  b->comb_grid = blk + P.fold_grid;
+  build(b->comb_side, &b->comb_side_grid, 0, false);
+  build(b->comb_main, &b->comb_main_grid, b->comb_side_grid, true);
   FinalArgs& fa = b->fin;
   fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
-  fa.flags = W + P.flags; fa.nflags = b->comb_grid;
+  fa.flags = W + P.flags; fa.nflags = b->comb_side_grid + b->comb_main_grid;
   fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
   fa.have_rate = 1; fa.have_sse = 1; fa.loss4 = loss4;
 }
@@ -411,6 +431,8 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if ((rc = fork_to(sd, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
+  if ((rc = side_waits(sd, st))) return rc;
+  if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, sd->stream))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
     if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0, st) !=
@@ -418,7 +440,7 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
       return CC_EHIP;
   }
   if ((rc = join_from(sd, st))) return rc;
-  if ((rc = launch((const void*)combine_kernel, b.comb_grid, 256, &b.comb, st))) return rc;
+  if ((rc = launch((const void*)combine_kernel, b.comb_main_grid, 256, &b.comb_main, st))) return rc;
   if ((rc = launch((const void*)finalize_kernel, 1, 256, &b.fin, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
@@ -437,11 +459,11 @@ struct BatchPlan {
   UpsFwdArgs* d_upf = nullptr;
   SynArgs* d_syn = nullptr;
   UpsBwdArgs* d_upb[MAXL] = {};
-  CombineArgs* d_comb = nullptr;
+  CombineArgs *d_comb_side = nullptr, *d_comb_main = nullptr;
   FinalArgs* d_fin = nullptr;
   WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_head = nullptr,
-           *w_upb[MAXL] = {}, *w_comb = nullptr;
-  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb = 0;
+           *w_upb[MAXL] = {}, *w_comb_side = nullptr, *w_comb_main = nullptr;
+  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb_side = 0, n_comb_main = 0;
 };
 
 int share(int total, long long part, long long whole, int cap) {
@@ -483,6 +505,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   blk(sizeof(UpsFwdArgs) * n);
   blk(sizeof(SynArgs) * n);
   for (int s = 0; s + 1 < L; ++s) blk(sizeof(UpsBwdArgs) * n);
+  blk(sizeof(CombineArgs) * n);
   blk(sizeof(CombineArgs) * n);
   blk(sizeof(FinalArgs) * n);
   long long items = 0;
@@ -548,9 +571,9 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   std::vector<UpsFwdArgs> h_upf(n);
   std::vector<SynArgs> h_syn(n);
   std::vector<std::vector<UpsBwdArgs>> h_upb(L, std::vector<UpsBwdArgs>(n));
-  std::vector<CombineArgs> h_comb(n);
+  std::vector<CombineArgs> h_comb_side(n), h_comb_main(n);
   std::vector<FinalArgs> h_fin(n);
-  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_comb;
+  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_comb_side, w_comb_main;
   std::vector<std::vector<WorkItem>> w_upb(L);
   BwdSet* b = new (std::nothrow) BwdSet;
   if (!b) return CC_EINVAL;
@@ -560,7 +583,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     float* W = (float*)((char*)ws + img_off[k]);
     build_backward(&probs[k], P, W, q.img, q.y, q.u, q.arm_w, q.ups_w, q.syn_w, dloss, q.loss4, q.g_y, q.g_arm,
                    q.g_ups, q.g_syn, b);
-    h_arm[k] = b->arm; h_upf[k] = b->upf; h_syn[k] = b->syn; h_comb[k] = b->comb; h_fin[k] = b->fin;
+    h_arm[k] = b->arm; h_upf[k] = b->upf; h_syn[k] = b->syn;
+    h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main; h_fin[k] = b->fin;
     for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
     for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
     for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
@@ -570,7 +594,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     for (int s = 0; s + 1 < L; ++s)
       for (int c = 0; c < P.ups_chunks[s]; ++c)
         for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], c});
-    for (int i = 0; i < b->comb_grid; ++i) w_comb.push_back(WorkItem{k, i, b->comb_grid, 0});
+    for (int i = 0; i < b->comb_side_grid; ++i) w_comb_side.push_back(WorkItem{k, i, b->comb_side_grid, 0});
+    for (int i = 0; i < b->comb_main_grid; ++i) w_comb_main.push_back(WorkItem{k, i, b->comb_main_grid, 0});
   }
   delete b;
   // upload: argument blocks, then work-lists
@@ -587,7 +612,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.d_upf = (UpsFwdArgs*)put(h_upf.data(), sizeof(UpsFwdArgs) * n);
   B.d_syn = (SynArgs*)put(h_syn.data(), sizeof(SynArgs) * n);
   for (int s = 0; s + 1 < L; ++s) B.d_upb[s] = (UpsBwdArgs*)put(h_upb[s].data(), sizeof(UpsBwdArgs) * n);
-  B.d_comb = (CombineArgs*)put(h_comb.data(), sizeof(CombineArgs) * n);
+  B.d_comb_side = (CombineArgs*)put(h_comb_side.data(), sizeof(CombineArgs) * n);
+  B.d_comb_main = (CombineArgs*)put(h_comb_main.data(), sizeof(CombineArgs) * n);
   B.d_fin = (FinalArgs*)put(h_fin.data(), sizeof(FinalArgs) * n);
   auto putw = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) {
     *cnt = (int)v.size();
@@ -599,7 +625,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   putw(w_syn, &B.w_syn, &B.n_syn);
   putw(w_head, &B.w_head, &B.n_head);
   for (int s = 0; s + 1 < L; ++s) putw(w_upb[s], &B.w_upb[s], &B.n_upb[s]);
-  putw(w_comb, &B.w_comb, &B.n_comb);
+  putw(w_comb_side, &B.w_comb_side, &B.n_comb_side);
+  putw(w_comb_main, &B.w_comb_main, &B.n_comb_main);
   if (err || desc_off + d > ws_bytes) return err ? CC_EHIP : CC_EWORKSPACE;
   cc_batch* h = new (std::nothrow) cc_batch;
   if (!h) return CC_EINVAL;
@@ -643,11 +670,21 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
   }
   if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
+  if ((rc = side_waits(sd, st))) return rc;
+  if (B.n_comb_side > 0) {
+    void* descs = B.d_comb_side;
+    void* work = B.w_comb_side;
+    void* argv[] = {&descs, &work};
+    if (hipLaunchKernel((const void*)combine_kernel_batch, dim3(B.n_comb_side), dim3(256), argv, 0, sd->stream) !=
+        hipSuccess)
+      return CC_EHIP;
+  }
   for (int s = 0; s + 1 < B.L; ++s)
     if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
       return rc;
   if ((rc = join_from(sd, st))) return rc;
-  if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb, 256, B.d_comb, B.w_comb))) return rc;
+  if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb_main, 256, B.d_comb_main, B.w_comb_main)))
+    return rc;
   {
     void* descs = B.d_fin;
     void* argv[] = {&descs};
@@ -846,6 +883,7 @@ int warm_plan(const cc_warm_problem* p, int which, WarmPlan* P, float* base) {
     a.part_th = put((size_t)B * 33 * a.n_theta);
     // column sums of every partial block into the gradient, in layout order
     CombineArgs& ca = P->comb;
+    std::memset(&ca, 0, sizeof(ca));
     int nsg = 0, blk = 0;
     auto seg = [&](const float* src, int rows, int cols, int dst_off) {
       ca.seg[nsg] = RedSeg{src, rows, cols, cols, 16, (float*)(intptr_t)dst_off};

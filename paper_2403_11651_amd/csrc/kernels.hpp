@@ -117,6 +117,15 @@ struct RedSeg {
   int cpb;             // columns per block: 16 (16 row groups) or 1 (256 row groups)
   float* dst;          // [cols]
 };
+struct FinalArgs {
+  const float* rpart; int nr;    // rate partials (bits)
+  const float* spart; int ns;    // squared-error partials
+  const float* flags; int nflags;
+  float lambda, inv_hw, inv_3hw;
+  int have_rate, have_sse;
+  float* loss4;
+};
+
 // One launch does two independent jobs: blocks [0, n_red) sum partial
 // matrices column by column (segments in order), blocks [n_red, n_red +
 // fold blocks) fold the ARM context gradients into g_y.
@@ -129,15 +138,6 @@ struct CombineArgs {
 };
 __global__ void combine_kernel(CombineArgs a);
 __global__ void combine_kernel_batch(const CombineArgs* d, const WorkItem* w);
-
-struct FinalArgs {
-  const float* rpart; int nr;    // rate partials (bits)
-  const float* spart; int ns;    // squared-error partials
-  const float* flags; int nflags;
-  float lambda, inv_hw, inv_3hw;
-  int have_rate, have_sse;
-  float* loss4;
-};
 __global__ void finalize_kernel(FinalArgs a);
 __global__ void finalize_kernel_batch(const FinalArgs* d);
 

@@ -37,6 +37,50 @@ __device__ bool arm_fold_one(const FoldArgs& a, int q) {
   return finitef(v);
 }
 
+// Three block sums in one pass: each thread adds its strided share of every
+// array in index order (the loads of a share are issued together), then one
+// fixed tree per array.
+__device__ void block_sum3(const float* const src[3], const int n[3], float* s_tmp, float out[3]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int i = tid; i < n[k]; i += 256) acc += src[k][i];
+    s_tmp[k * 256 + tid] = acc;
+  }
+  __syncthreads();
+  for (int stride = 128; stride >= 1; stride >>= 1) {
+    if (tid < stride) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s_tmp[k * 256 + tid] += s_tmp[k * 256 + tid + stride];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = s_tmp[k * 256];
+}
+
+// loss4 = {D + lambda R / (HW), D, R, non-finite flag} (Eq. (1); D = SSE / 3HW).
+__device__ __forceinline__ void finalize_body(const FinalArgs& a) {
+  __shared__ float s_tmp[3 * 256];
+  const float* const src[3] = {a.rpart, a.spart, a.flags};
+  const int n[3] = {a.have_rate ? a.nr : 0, a.have_sse ? a.ns : 0, a.nflags};
+  float sums[3];
+  block_sum3(src, n, s_tmp, sums);
+  const float R = sums[0], sse = sums[1], fl = sums[2];
+  if (threadIdx.x == 0) {
+    // explicit rounding steps, so that every kernel built from this body
+    // (single image or batched) computes the loss the same way
+    const float D = sse * a.inv_3hw;
+    const float L = __builtin_fmaf(a.lambda * R, a.inv_hw, D);
+    a.loss4[0] = L;
+    a.loss4[1] = D;
+    a.loss4[2] = R;
+    a.loss4[3] = (fl > 0.0f || !finitef(L) || !finitef(D) || !finitef(R)) ? 1.0f : 0.0f;
+  }
+}
+
 // Column sums of [rows][ld] partial matrices, and the ARM fold (see
 // CombineArgs).  A reduction block owns cpb columns of one segment; its
 // 256 / cpb row groups each sum a strided set of rows, then a fixed-order
@@ -80,50 +124,6 @@ __global__ __launch_bounds__(256) void combine_kernel_batch(const CombineArgs* _
                                                             const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
   combine_body(d[it.img], it.bid);
-}
-
-// Three block sums in one pass: each thread adds its strided share of every
-// array in index order (the loads of a share are issued together), then one
-// fixed tree per array.
-__device__ void block_sum3(const float* const src[3], const int n[3], float* s_tmp, float out[3]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    float acc = 0.0f;
-#pragma unroll 8
-    for (int i = tid; i < n[k]; i += 256) acc += src[k][i];
-    s_tmp[k * 256 + tid] = acc;
-  }
-  __syncthreads();
-  for (int stride = 128; stride >= 1; stride >>= 1) {
-    if (tid < stride) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s_tmp[k * 256 + tid] += s_tmp[k * 256 + tid + stride];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) out[k] = s_tmp[k * 256];
-}
-
-// loss4 = {D + lambda R / (HW), D, R, non-finite flag} (Eq. (1); D = SSE / 3HW).
-__device__ __forceinline__ void finalize_body(const FinalArgs& a) {
-  __shared__ float s_tmp[3 * 256];
-  const float* const src[3] = {a.rpart, a.spart, a.flags};
-  const int n[3] = {a.have_rate ? a.nr : 0, a.have_sse ? a.ns : 0, a.nflags};
-  float sums[3];
-  block_sum3(src, n, s_tmp, sums);
-  const float R = sums[0], sse = sums[1], fl = sums[2];
-  if (threadIdx.x == 0) {
-    // explicit rounding steps, so that every kernel built from this body
-    // (single image or batched) computes the loss the same way
-    const float D = sse * a.inv_3hw;
-    const float L = __builtin_fmaf(a.lambda * R, a.inv_hw, D);
-    a.loss4[0] = L;
-    a.loss4[1] = D;
-    a.loss4[2] = R;
-    a.loss4[3] = (fl > 0.0f || !finitef(L) || !finitef(D) || !finitef(R)) ? 1.0f : 0.0f;
-  }
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) { finalize_body(a); }
