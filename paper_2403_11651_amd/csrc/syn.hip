@@ -439,9 +439,13 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
 // (in-image ones; others get 0): g_{r-1}[q] = g_pre[q] + sum over padded
 // positions q' that clamp to q of sum_d W_d^T g_pre[q' - d], in-image terms
 // only (the replicate border folds the padded positions onto the edge).
-template <int FS, int LO, bool INSIDE>
-__device__ __forceinline__ void res_adjoint(const float* wr, const float* g, float* gout, int fi0, int fj0, int H,
-                                            int W, int tid) {
+// The result, masked by ReLU'(tm) (tm = the layer input, which is the output
+// of a ReLU), is the gradient at the previous pre-activation: OUT = 1 writes
+// it to the frame gout, OUT = 2 (region = the tile's own pixels) to the
+// image-sized gpt.
+template <int FS, int LO, bool INSIDE, int OUT>
+__device__ __forceinline__ void res_adjoint(const float* wr, const float* g, float* gout, const float* tm,
+                                            float* __restrict__ gpt, int fi0, int fj0, int H, int W, int tid) {
   constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
   int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
   asm volatile("" : "+s"(zo));
@@ -485,20 +489,16 @@ __device__ __forceinline__ void res_adjoint(const float* wr, const float* g, flo
         }
       }
     }
+    if (OUT == 1) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gout[c * FA + fp] = out[c];
-  }
-}
-
-// g_pre_r = g_t_r * ReLU'(t_r) in place on region [LO, FS-LO)
-template <int FS, int LO>
-__device__ __forceinline__ void relu_mask(const float* t, float* g, int tid) {
-  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
-  for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
-    const int fp = (LO + p / SIDE) * FS + LO + p % SIDE;
+      for (int c = 0; c < 3; ++c) gout[c * FA + fp] = tm[c * FA + fp] > 0.0f ? out[c] : 0.0f;
+    } else {
+      const int ii = fi0 + fa, jj = fj0 + fb;
+      if (ii < H && jj < W) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!(t[c * FA + fp] > 0.0f)) g[c * FA + fp] = 0.0f;
+        for (int c = 0; c < 3; ++c) gpt[(size_t)c * H * W + ii * W + jj] = tm[c * FA + fp] > 0.0f ? out[c] : 0.0f;
+      }
+    }
   }
 }
 
@@ -526,6 +526,22 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
   for (int r = 0; r < NRES; ++r) zero_acc(accR[r]);
   float sse = 0.0f;
 
+  // t0 on a tile's frame (clamped coordinates), NPF positions per thread;
+  // the next tile's frame is fetched while the current one is processed
+  constexpr int NPF = (FS * FS + SYN_THREADS - 1) / SYN_THREADS;
+  float pf[NPF][3];
+  auto fetch = [&](int tile) {
+    const int fi = (tile / a.n_tiles_x) * SYN_T - E, fj = (tile % a.n_tiles_x) * SYN_T - E;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int p = tid0 + SYN_THREADS * q;
+      const int ii = clampi(fi + p / FS, 0, H - 1), jj = clampi(fj + p % FS, 0, W - 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pf[q][c] = p < FS * FS ? a.t0[(size_t)c * H * W + ii * W + jj] : 0.0f;
+    }
+  };
+  if (bid < a.n_tiles) fetch(bid);
+
   for (int tile = bid; tile < a.n_tiles; tile += nblk) {
     const int i0 = (tile / a.n_tiles_x) * SYN_T, j0 = (tile % a.n_tiles_x) * SYN_T;
     const int fi0 = i0 - E, fj0 = j0 - E;
@@ -535,16 +551,18 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
     // out of the tile loop (where it would have to live in registers)
     int tid = tid0;
     asm volatile("" : "+v"(tid));
-    const int ty = tid / SYN_T, tx = tid % SYN_T;
     const float* __restrict__ img = a.img;
-    // 1. t0 on the frame (clamped coordinates)
-    for (int p = tid; p < FS * FS; p += SYN_THREADS) {
-      const int fa = p / FS, fb = p % FS;
-      const int ii = clampi(fi0 + fa, 0, H - 1), jj = clampi(fj0 + fb, 0, W - 1);
+    // 1. t0 on the frame
 #pragma unroll
-      for (int c = 0; c < 3; ++c) s_t[0][c * FA + fa * FS + fb] = a.t0[(size_t)c * H * W + ii * W + jj];
+    for (int q = 0; q < NPF; ++q) {
+      const int p = tid0 + SYN_THREADS * q;
+      if (p < FS * FS) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_t[0][c * FA + p] = pf[q][c];
+      }
     }
     __syncthreads();
+    if (tile + nblk < a.n_tiles) fetch(tile + nblk);
     // 2. residual layers forward, layer r on halo E - r; the last one yields
     // dL/dx_hat on halo NRES (zero outside the image) and the squared error
     if constexpr (NRES >= 2) {
@@ -558,40 +576,20 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
       else res_layer_last<FS, 1, false>(sw.conv[0], s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
     }
     __syncthreads();
-    // 4. residual layers backward: weight gradient over the tile's own pixels,
-    // then the adjoint one ring smaller
-    const bool own = (i0 + ty) < H && (j0 + tx) < W;
-    const int fpo = (E + ty) * FS + E + tx;
-    int cur = 0;
-#pragma unroll
-    for (int r = NRES; r >= 1; --r) {
-      if (r < NRES) {
-        relu_mask<FS, E - NRES + 1>(s_t[r], s_g[cur], tid);  // layer r < NRES: halo r = NRES - 1 here
-        __syncthreads();
-      }
-      conv_wgrad<FS, E>(accR[r - 1], s_g[cur], s_t[r - 1], i0, j0, H, W, wave, lane);
-      if (r == 2) {
-        if (inside) res_adjoint<FS, E - 1, true>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
-        else res_adjoint<FS, E - 1, false>(sw.conv[1], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
-      } else {
-        if (inside) res_adjoint<FS, E, true>(sw.conv[0], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
-        else res_adjoint<FS, E, false>(sw.conv[0], s_g[cur], s_g[cur ^ 1], fi0, fj0, H, W, tid);
-      }
-      cur ^= 1;
+    // 3. residual layers backward: weight gradient over the tile's own pixels,
+    // then the adjoint one ring smaller, masked by the ReLU of the layer
+    // input; the first layer's lands, as the gradient at the pre-activation
+    // of t0, in gpt
+    if constexpr (NRES >= 2) {
+      conv_wgrad<FS, E>(accR[1], s_g[0], s_t[1], i0, j0, H, W, wave, lane);
+      if (inside) res_adjoint<FS, E - 1, true, 1>(sw.conv[1], s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
+      else res_adjoint<FS, E - 1, false, 1>(sw.conv[1], s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
       __syncthreads();
     }
-    // 5. per pixel: the gradient at the pre-activation of t0
-    {
-      const int i = i0 + ty, j = j0 + tx;
-      if (own) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const size_t gi = (size_t)c * H * W + i * W + j;
-          const float t0v = s_t[0][c * FA + fpo];
-          a.gpt[gi] = t0v > 0.0f ? s_g[cur][c * FA + fpo] : 0.0f;
-        }
-      }
-    }
+    constexpr int G1 = NRES >= 2 ? 1 : 0;
+    conv_wgrad<FS, E>(accR[0], s_g[G1], s_t[0], i0, j0, H, W, wave, lane);
+    if (inside) res_adjoint<FS, E, true, 2>(sw.conv[0], s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
+    else res_adjoint<FS, E, false, 2>(sw.conv[0], s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
     __syncthreads();
   }
 
