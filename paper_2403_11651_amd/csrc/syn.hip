@@ -214,8 +214,8 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
 // (fi0, fj0).  Values at frame positions outside the image are the values at
 // the clamped position (replicate border), so the conv reads its neighbours
 // around the clamped position.  INSIDE: the frame lies inside the image.
-template <int FS, bool INSIDE>
-__device__ __forceinline__ void res_pre(const float* wr, const float* src, int fa, int fb, int fi0, int fj0, int H,
+template <int FS, bool INSIDE, typename WP>
+__device__ __forceinline__ void res_pre(WP wr, const float* src, int fa, int fb, int fi0, int fj0, int H,
                                         int W, float (&pre)[3]) {
   constexpr int FA = SYN_FMAX * SYN_FMAX;
   int ca = fa, cb = fb;
@@ -239,8 +239,8 @@ __device__ __forceinline__ void res_pre(const float* wr, const float* src, int f
   }
 }
 
-template <int FS, int LO, bool INSIDE>
-__device__ __forceinline__ void res_layer(const float* wr, const float* src, float* dst, int fi0, int fj0, int H,
+template <int FS, int LO, bool INSIDE, typename WP>
+__device__ __forceinline__ void res_layer(WP wr, const float* src, float* dst, int fi0, int fj0, int H,
                                           int W, bool relu, int tid) {
   constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
   int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
@@ -249,7 +249,7 @@ __device__ __forceinline__ void res_layer(const float* wr, const float* src, flo
   for (int p = tid; p < SIDE * SIDE; p += SYN_THREADS) {
     const int fa = LO + p / SIDE, fb = LO + p % SIDE;
     float pre[3];
-    res_pre<FS, INSIDE>(wr, src, fa, fb, fi0, fj0, H, W, pre);
+    res_pre<FS, INSIDE, WP>(wr, src, fa, fb, fi0, fj0, H, W, pre);
 #pragma unroll
     for (int o = 0; o < 3; ++o) dst[o * FA + fa * FS + fb] = relu ? fmaxf(pre[o], 0.0f) : pre[o];
   }
@@ -259,8 +259,8 @@ __device__ __forceinline__ void res_layer(const float* wr, const float* src, flo
 // [LO, FS-LO) is not stored; the region receives dL/dx_hat = dscale (x_hat -
 // x) (zero outside the image) and the tile's own pixels add their squared
 // error to sse.
-template <int FS, int LO, bool INSIDE>
-__device__ __forceinline__ void res_layer_last(const float* wr, const float* src, float* g, int fi0, int fj0,
+template <int FS, int LO, bool INSIDE, typename WP>
+__device__ __forceinline__ void res_layer_last(WP wr, const float* src, float* g, int fi0, int fj0,
                                                int H, int W, const float* __restrict__ img, float dscale, float& sse,
                                                int tid) {
   constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX, E = FS / 2 - SYN_T / 2;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void res_layer_last(const float* wr, const float* src
     const bool in = ii >= 0 && ii < H && jj >= 0 && jj < W;
     const bool own = in && fa >= E && fa < E + SYN_T && fb >= E && fb < E + SYN_T;
     float pre[3];
-    res_pre<FS, INSIDE>(wr, src, fa, fb, fi0, fj0, H, W, pre);
+    res_pre<FS, INSIDE, WP>(wr, src, fa, fb, fi0, fj0, H, W, pre);
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
       const float e = in ? pre[o] - img[(size_t)o * H * W + ii * W + jj] : 0.0f;
@@ -443,8 +443,8 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
 // of a ReLU), is the gradient at the previous pre-activation: OUT = 1 writes
 // it to the frame gout, OUT = 2 (region = the tile's own pixels) to the
 // image-sized gpt.
-template <int FS, int LO, bool INSIDE, int OUT>
-__device__ __forceinline__ void res_adjoint(const float* wr, const float* g, float* gout, const float* tm,
+template <int FS, int LO, bool INSIDE, int OUT, typename WP>
+__device__ __forceinline__ void res_adjoint(WP wr, const float* g, float* gout, const float* tm,
                                             float* __restrict__ gpt, int fi0, int fj0, int H, int W, int tid) {
   constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
   int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
@@ -520,6 +520,11 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
 
   const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid0 = threadIdx.x, lane = tid0 & 63, wave = tid0 >> 6;
   stage_weights(sw, a.w, L, tid0);
+  // the convs' weights are read as wave-uniform scalar loads (constant
+  // address space) rather than from LDS
+  typedef const float __attribute__((address_space(4))) cf;
+  cf* wc0 = (cf*)(a.w + a.res_off);
+  cf* wc1 = (cf*)(a.w + a.res_off + 84);
 
   f32x4 accR[NRES][1][2];
 #pragma unroll
@@ -566,14 +571,14 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
     // 2. residual layers forward, layer r on halo E - r; the last one yields
     // dL/dx_hat on halo NRES (zero outside the image) and the squared error
     if constexpr (NRES >= 2) {
-      if (inside) res_layer<FS, 1, true>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
-      else res_layer<FS, 1, false>(sw.conv[0], s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
+      if (inside) res_layer<FS, 1, true>(wc0, s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
+      else res_layer<FS, 1, false>(wc0, s_t[0], s_t[1], fi0, fj0, H, W, true, tid);
       __syncthreads();
-      if (inside) res_layer_last<FS, 2, true>(sw.conv[1], s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
-      else res_layer_last<FS, 2, false>(sw.conv[1], s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      if (inside) res_layer_last<FS, 2, true>(wc1, s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      else res_layer_last<FS, 2, false>(wc1, s_t[1], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
     } else {
-      if (inside) res_layer_last<FS, 1, true>(sw.conv[0], s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
-      else res_layer_last<FS, 1, false>(sw.conv[0], s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      if (inside) res_layer_last<FS, 1, true>(wc0, s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
+      else res_layer_last<FS, 1, false>(wc0, s_t[0], s_g[0], fi0, fj0, H, W, img, a.dscale, sse, tid);
     }
     __syncthreads();
     // 3. residual layers backward: weight gradient over the tile's own pixels,
@@ -582,14 +587,14 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
     // of t0, in gpt
     if constexpr (NRES >= 2) {
       conv_wgrad<FS, E>(accR[1], s_g[0], s_t[1], i0, j0, H, W, wave, lane);
-      if (inside) res_adjoint<FS, E - 1, true, 1>(sw.conv[1], s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
-      else res_adjoint<FS, E - 1, false, 1>(sw.conv[1], s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
+      if (inside) res_adjoint<FS, E - 1, true, 1>(wc1, s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
+      else res_adjoint<FS, E - 1, false, 1>(wc1, s_g[0], s_g[1], s_t[1], nullptr, fi0, fj0, H, W, tid);
       __syncthreads();
     }
     constexpr int G1 = NRES >= 2 ? 1 : 0;
     conv_wgrad<FS, E>(accR[0], s_g[G1], s_t[0], i0, j0, H, W, wave, lane);
-    if (inside) res_adjoint<FS, E, true, 2>(sw.conv[0], s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
-    else res_adjoint<FS, E, false, 2>(sw.conv[0], s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
+    if (inside) res_adjoint<FS, E, true, 2>(wc0, s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
+    else res_adjoint<FS, E, false, 2>(wc0, s_g[G1], nullptr, s_t[0], a.gpt, fi0, fj0, H, W, tid);
     __syncthreads();
   }
 
