@@ -75,12 +75,16 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
   __shared__ float s_A[BWD ? 2 : 1][NH][NR][64];
 
   const float* __restrict__ w = a.w;
-  for (int idx = tid; idx < (BWD ? 2 : 1) * NH * NR * 64; idx += ARM_THREADS) {
-    const int ln = idx & 63, t = (idx >> 6) % NR, j = (idx / (64 * NR)) % NH, tr = idx / (64 * NR * NH);
-    const int nn = ln & 31, f = dfeat(t, ln >> 5);
-    const float* Wj = w + j * (C * C + C);
-    s_A[tr][j][t][ln] = nn < C ? (tr ? Wj[f * C + nn] : Wj[nn * C + f]) + (nn == f ? 1.0f : 0.0f) : 0.0f;
-  }
+  constexpr int NA = (BWD ? 2 : 1) * NH * NR * 64;
+  batched_stage<(NA + ARM_THREADS - 1) / ARM_THREADS, ARM_THREADS>(
+      tid, NA,
+      [&](int idx) -> float {
+        const int ln = idx & 63, t = (idx >> 6) % NR, j = (idx / (64 * NR)) % NH, tr = idx / (64 * NR * NH);
+        const int nn = ln & 31, f = dfeat(t, ln >> 5);
+        const float* Wj = w + j * (C * C + C);
+        return nn < C ? (tr ? Wj[f * C + nn] : Wj[nn * C + f]) + (nn == f ? 1.0f : 0.0f) : 0.0f;
+      },
+      [&](int idx, float v) { (&s_A[0][0][0][0])[idx] = v; });
   // per-lane constants: context offsets in the LDS frame, biases and output
   // weights of the features this lane holds
   int ctxoff[NR];
@@ -121,7 +125,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
   // the quantised latents of a tile's frame (zero outside the grid), NPF per
   // thread; the next tile's are fetched while the current one is processed
   constexpr int NPF = (ARM_EXT + ARM_THREADS - 1) / ARM_THREADS;
-  float pf[NPF];
+  float pf[NPF], pu[NPF];  // raw latents (and noise), quantised when staged
   auto fetch = [&](int tile) {
     int l = 0;
     while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
@@ -132,9 +136,12 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
     for (int q = 0; q < NPF; ++q) {
       const int idx = tid + ARM_THREADS * q;
       const int ii = i0 - 3 + idx / ARM_EW, jj = j0 - 3 + idx % ARM_EW;
-      float v = 0.0f;
-      if (idx < ARM_EXT && ii >= 0 && ii < h && jj >= 0 && jj < wl) v = quantise(a.y, a.u, base + ii * wl + jj, a.quant);
-      pf[q] = v;
+      pf[q] = 0.0f;
+      pu[q] = 0.0f;
+      if (idx < ARM_EXT && ii >= 0 && ii < h && jj >= 0 && jj < wl) {
+        pf[q] = a.y[base + ii * wl + jj];
+        if (a.quant == 1) pu[q] = a.u[base + ii * wl + jj];
+      }
     }
   };
   if (bid < a.tiles.n_tiles) fetch(bid);
@@ -149,7 +156,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       const int idx = tid + ARM_THREADS * q;
-      if (idx < ARM_EXT) s_yq[idx] = pf[q];
+      if (idx < ARM_EXT) s_yq[idx] = quantise_raw(pf[q], pu[q], a.quant);
     }
     __syncthreads();
     if (tile + nblk < a.tiles.n_tiles) fetch(tile + nblk);

@@ -31,6 +31,14 @@ __device__ __forceinline__ float quantise(const float* __restrict__ y, const flo
   return v;
 }
 
+// The same from values already read (uv is read only for mode 1), so that a
+// thread can issue all its reads before it uses any.
+__device__ __forceinline__ float quantise_raw(float yv, float uv, int mode) {
+  if (mode == 0) return __builtin_rintf(yv);
+  if (mode == 1) return yv + uv;
+  return yv;
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Wave-local ordering of LDS traffic: stops the compiler from moving LDS
@@ -65,6 +73,60 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
+
+// Fills n LDS values (n <= NQ * NT): store(p, load(p)) for p = tid, tid + NT,
+// ..., with every global read of the thread issued before its first LDS
+// write (a plain loop would wait for each read in turn).
+template <int NQ, int NT, typename Load, typename Store>
+__device__ __forceinline__ void batched_stage(int tid, int n, Load load, Store store) {
+  float r[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int p = tid + NT * q;
+    r[q] = p < n ? load(p) : 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int p = tid + NT * q;
+    if (p < n) store(p, r[q]);
+  }
+}
+
+// Stages n values of a latent stack into LDS the same way: for p, src(p)
+// gives (idx, plane): plane < 0 reads the latent y[idx] (quantised with
+// mode; the noise u[idx] is read too in mode 1), plane >= 0 the float
+// planes[idx] (already a stack channel).  All reads first, then the writes.
+template <int NQ, int NT, typename Src, typename Store>
+__device__ __forceinline__ void batched_stage_stack(int tid, int n, const float* __restrict__ y,
+                                                    const float* __restrict__ u, int mode,
+                                                    const float* __restrict__ planes, Src src, Store store) {
+  float ry[NQ], ru[NQ];
+  bool lat[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int p = tid + NT * q;
+    ry[q] = 0.0f;
+    ru[q] = 0.0f;
+    lat[q] = false;
+    if (p < n) {
+      int idx;
+      bool is_lat;
+      src(p, idx, is_lat);
+      lat[q] = is_lat;
+      if (is_lat) {
+        ry[q] = y[idx];
+        if (mode == 1) ru[q] = u[idx];
+      } else {
+        ry[q] = planes[idx];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int p = tid + NT * q;
+    if (p < n) store(p, lat[q] ? quantise_raw(ry[q], ru[q], mode) : ry[q]);
+  }
+}
 
 // One work-group of a batched launch: the image whose argument block it
 // uses, its block index and the block count of that image's share, and a

@@ -89,20 +89,30 @@ struct SynW {
 
 template <int HS, int NRES>
 __device__ __forceinline__ void stage_weights(SynW<HS, NRES>& sw, const float* __restrict__ w, int L, int tid) {
+  // SynW is [W1p | W2t | b2 | conv] without padding: one flat index
   const int b1 = HS * L, W2 = b1 + HS, b2 = W2 + 3 * HS, res0 = b2 + 3;
-  for (int i = tid; i < HS * 8; i += SYN_THREADS) {
-    const int f = i / 8, c = i % 8;
-    sw.W1p[f][c] = c < L ? w[f * L + c] : (c == 7 ? w[b1 + f] : 0.0f);
-  }
-  for (int i = tid; i < HS * 4; i += SYN_THREADS) {
-    const int f = i / 4, c = i % 4;
-    sw.W2t[f][c] = c < 3 ? w[W2 + c * HS + f] : 0.0f;
-  }
-  if (tid < 4) sw.b2[tid] = tid < 3 ? w[b2 + tid] : 0.0f;
-  for (int i = tid; i < NRES * 88; i += SYN_THREADS) {
-    const int r = i / 88, k = i % 88;
-    sw.conv[r][k] = k < 84 ? w[res0 + r * 84 + k] : 0.0f;
-  }
+  constexpr int N1 = HS * 8, N2 = HS * 4, N3 = 4, N = N1 + N2 + N3 + NRES * 88;
+  static_assert(sizeof(SynW<HS, NRES>) == N * sizeof(float), "flat weight layout");
+  float* dst = reinterpret_cast<float*>(&sw);
+  batched_stage<(N + SYN_THREADS - 1) / SYN_THREADS, SYN_THREADS>(
+      tid, N,
+      [&](int i) -> float {
+        if (i < N1) {
+          const int f = i / 8, c = i % 8;
+          return c < L ? w[f * L + c] : (c == 7 ? w[b1 + f] : 0.0f);
+        }
+        i -= N1;
+        if (i < N2) {
+          const int f = i / 4, c = i % 4;
+          return c < 3 ? w[W2 + c * HS + f] : 0.0f;
+        }
+        i -= N2;
+        if (i < N3) return i < 3 ? w[b2 + i] : 0.0f;
+        i -= N3;
+        const int r = i / 88, k = i % 88;
+        return k < 84 ? w[res0 + r * 84 + k] : 0.0f;
+      },
+      [&](int i, float v) { dst[i] = v; });
 }
 
 // The two 1x1 layers, a = ReLU(W1 z + b1) (z[7] = 1 carries the bias) and
@@ -149,11 +159,18 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   float kv[UPS_K], kh[UPS_K];
   load_taps(a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
-  for (int p = tid; p < nch * RH * RW; p += 256) {
-    const int c = p / (RH * RW), rem = p % (RH * RW), rr = rem / RW, cc = rem % RW;
-    const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
-    s_s[c][rr][cc] = c == 0 ? quantise(a.y, a.u, lo1 + q, a.quant) : a.up1[(size_t)(c - 1) * h1 * w1 + q];
-  }
+  batched_stage_stack<((MAXL - 1) * RH * RW + 255) / 256, 256>(
+      tid, nch * RH * RW, a.y, a.u, a.quant, a.up1,
+      [&](int p, int& idx, bool& is_lat) {
+        const int c = p / (RH * RW), rem = p % (RH * RW), rr = rem / RW, cc = rem % RW;
+        const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
+        is_lat = c == 0;
+        idx = c == 0 ? lo1 + q : (c - 1) * h1 * w1 + q;
+      },
+      [&](int p, float v) {
+        const int c = p / (RH * RW), rem = p % (RH * RW);
+        s_s[c][rem / RW][rem % RW] = v;
+      });
   __syncthreads();
   for (int p = tid; p < nch * SYN_T0_H * RW; p += 256) {
     const int c = p / (SYN_T0_H * RW), rem = p % (SYN_T0_H * RW), ti = rem / RW, cc = rem % RW;
@@ -665,11 +682,18 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
   load_taps(a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
   // ---- z (the computation of syn_t0_body on this tile)
-  for (int p = tid; p < nch * RS * RS; p += 256) {
-    const int c = p / (RS * RS), rem = p % (RS * RS), rr = rem / RS, cc = rem % RS;
-    const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
-    s_s[c][rr][cc] = c == 0 ? quantise(a.y, a.u, lo1 + q, a.quant) : a.up1[(size_t)(c - 1) * h1 * w1 + q];
-  }
+  batched_stage_stack<((MAXL - 1) * RS * RS + 255) / 256, 256>(
+      tid, nch * RS * RS, a.y, a.u, a.quant, a.up1,
+      [&](int p, int& idx, bool& is_lat) {
+        const int c = p / (RS * RS), rem = p % (RS * RS), rr = rem / RS, cc = rem % RS;
+        const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
+        is_lat = c == 0;
+        idx = c == 0 ? lo1 + q : (c - 1) * h1 * w1 + q;
+      },
+      [&](int p, float v) {
+        const int c = p / (RS * RS), rem = p % (RS * RS);
+        s_s[c][rem / RS][rem % RS] = v;
+      });
   __syncthreads();
   for (int p = tid; p < nch * T * RS; p += 256) {
     const int c = p / (T * RS), rem = p % (T * RS), ti = rem / RS, cc = rem % RS;
