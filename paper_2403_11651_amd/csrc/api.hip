@@ -35,7 +35,6 @@ struct Plan {
   int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
   int ups_cpb[MAXL], ups_chunks[MAXL];  // channels per upsampling-adjoint block, blocks per tile
-  int ups_s0;     // first adjoint step of the per-chain tail launch (L - 1: none)
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
@@ -119,15 +118,6 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->ups_cpb[s] = P->ups_grid[s] >= 256 ? L - 1 - s : 1;
     P->ups_chunks[s] = cdiv(L - 1 - s, P->ups_cpb[s]);
   }
-  P->ups_s0 = L - 1;
-  for (int s = 1; s + 1 < L; ++s) {
-    const int hs = g.lh[s], ws = g.lw[s], hi = g.lh[s + 1], wi = g.lw[s + 1];
-    if (hs * ws <= UT_G && hs * (wi + 4) <= UT_T && (hi + 4) * ws <= UT_T2 && (hi + 4) * (wi + 4) <= UT_P &&
-        hi * wi <= UT_G / 4) {
-      P->ups_s0 = s;
-      break;
-    }
-  }
   P->fold_grid = cdiv(g.n_lat, 256);
   // column reductions, one column per block (256 row groups: every column
   // has hundreds to thousands of partial rows)
@@ -154,8 +144,7 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->gpt = take(cur, (size_t)3 * p->H * p->W);
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
     P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
-    for (int s = 0; s + 1 < L; ++s)
-      P->upart[s] = take(cur, (size_t)(s < P->ups_s0 ? P->ups_grid[s] * P->ups_chunks[s] : L - 1 - s) * 2 * UPS_K);
+    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * P->ups_chunks[s] * 2 * UPS_K);
     P->flags = take(cur, (size_t)P->red_grid + P->fold_grid);
   }
   P->total = cur;
@@ -336,7 +325,6 @@ struct BwdSet {
   UpsFwdArgs upf;
   SynArgs syn;
   UpsBwdArgs upb[MAXL];
-  UpsTailArgs tail;
   CombineArgs comb_side, comb_main;
   FinalArgs fin;
   int upf_grid, t0_grid, comb_side_grid, comb_main_grid;
@@ -393,8 +381,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
       add(W + P.wpart_syn, P.syn_grid, P.nres * 84, g_syn + (P.n_syn - P.nres * 84));  // residual convs
     } else {
       for (int s = 0; s + 1 < L; ++s)
-        add(W + P.upart[s], s < P.ups_s0 ? P.ups_grid[s] * P.ups_chunks[s] : L - 1 - s, 2 * UPS_K,
-            g_ups + (size_t)s * 2 * UPS_K);
+        add(W + P.upart[s], P.ups_grid[s] * P.ups_chunks[s], 2 * UPS_K, g_ups + (size_t)s * 2 * UPS_K);
     }
     ca.nseg = ns;
     ca.block_start[ns] = blk;
@@ -405,12 +392,6 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     }
     *grid = blk;
   };
-  UpsTailArgs& ut = b->tail;
-  ut.geo = P.geo; ut.s0 = P.ups_s0; ut.y = y; ut.u = u; ut.quant = p->quant; ut.ups_w = ups_w;
-  for (int s = 1; s + 1 < L; ++s) ut.up_in[s] = W + P.up[s];
-  ut.g_in = P.ups_s0 + 1 < L ? W + P.gb[P.ups_s0] : nullptr;
-  ut.g_y = g_y;
-  for (int s = P.ups_s0; s + 1 < L; ++s) ut.part[s] = W + P.upart[s];
   build(b->comb_side, &b->comb_side_grid, 0, false);
   build(b->comb_main, &b->comb_main_grid, b->comb_side_grid, true);
   FinalArgs& fa = b->fin;
@@ -452,15 +433,9 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
   if ((rc = side_waits(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, sd->stream))) return rc;
-  for (int s = 0; s < P.ups_s0; ++s) {
+  for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
     if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0, st) !=
-        hipSuccess)
-      return CC_EHIP;
-  }
-  if (P.ups_s0 + 1 < L) {
-    void* argv[] = {&b.tail};
-    if (hipLaunchKernel((const void*)ups_tail_kernel, dim3(L - 1 - P.ups_s0), dim3(UT_THREADS), argv, 0, st) !=
         hipSuccess)
       return CC_EHIP;
   }
@@ -484,13 +459,11 @@ struct BatchPlan {
   UpsFwdArgs* d_upf = nullptr;
   SynArgs* d_syn = nullptr;
   UpsBwdArgs* d_upb[MAXL] = {};
-  UpsTailArgs* d_tail = nullptr;
   CombineArgs *d_comb_side = nullptr, *d_comb_main = nullptr;
   FinalArgs* d_fin = nullptr;
   WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_head = nullptr,
-           *w_upb[MAXL] = {}, *w_tail = nullptr, *w_comb_side = nullptr, *w_comb_main = nullptr;
-  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_tail = 0, n_comb_side = 0,
-      n_comb_main = 0;
+           *w_upb[MAXL] = {}, *w_comb_side = nullptr, *w_comb_main = nullptr;
+  int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb_side = 0, n_comb_main = 0;
 };
 
 int share(int total, long long part, long long whole, int cap) {
@@ -532,7 +505,6 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   blk(sizeof(UpsFwdArgs) * n);
   blk(sizeof(SynArgs) * n);
   for (int s = 0; s + 1 < L; ++s) blk(sizeof(UpsBwdArgs) * n);
-  blk(sizeof(UpsTailArgs) * n);
   blk(sizeof(CombineArgs) * n);
   blk(sizeof(CombineArgs) * n);
   blk(sizeof(FinalArgs) * n);
@@ -541,8 +513,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     const Plan& P = plans[k];
     items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
-    for (int s = 0; s < P.ups_s0; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
-    items += L - 1 - P.ups_s0;
+    for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
   blk(sizeof(WorkItem) * items + 256 * (L + 8));
   *total_bytes = cur + d;
@@ -600,10 +571,9 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   std::vector<UpsFwdArgs> h_upf(n);
   std::vector<SynArgs> h_syn(n);
   std::vector<std::vector<UpsBwdArgs>> h_upb(L, std::vector<UpsBwdArgs>(n));
-  std::vector<UpsTailArgs> h_tail(n);
   std::vector<CombineArgs> h_comb_side(n), h_comb_main(n);
   std::vector<FinalArgs> h_fin(n);
-  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_tail, w_comb_side, w_comb_main;
+  std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_comb_side, w_comb_main;
   std::vector<std::vector<WorkItem>> w_upb(L);
   BwdSet* b = new (std::nothrow) BwdSet;
   if (!b) return CC_EINVAL;
@@ -615,15 +585,13 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
                    q.g_ups, q.g_syn, b);
     h_arm[k] = b->arm; h_upf[k] = b->upf; h_syn[k] = b->syn;
     h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main; h_fin[k] = b->fin;
-    h_tail[k] = b->tail;
-    for (int c = 0; c + 1 < L - P.ups_s0; ++c) w_tail.push_back(WorkItem{k, c, L - 1 - P.ups_s0, 0});
     for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
     for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
     for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
     for (int i = 0; i < b->t0_grid; ++i) w_t0.push_back(WorkItem{k, i, b->t0_grid, 0});
     for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
     for (int i = 0; i < P.head_grid; ++i) w_head.push_back(WorkItem{k, i, P.head_grid, 0});
-    for (int s = 0; s < P.ups_s0; ++s)
+    for (int s = 0; s + 1 < L; ++s)
       for (int c = 0; c < P.ups_chunks[s]; ++c)
         for (int i = 0; i < P.ups_grid[s]; ++i) w_upb[s].push_back(WorkItem{k, i, P.ups_grid[s], c});
     for (int i = 0; i < b->comb_side_grid; ++i) w_comb_side.push_back(WorkItem{k, i, b->comb_side_grid, 0});
@@ -644,7 +612,6 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.d_upf = (UpsFwdArgs*)put(h_upf.data(), sizeof(UpsFwdArgs) * n);
   B.d_syn = (SynArgs*)put(h_syn.data(), sizeof(SynArgs) * n);
   for (int s = 0; s + 1 < L; ++s) B.d_upb[s] = (UpsBwdArgs*)put(h_upb[s].data(), sizeof(UpsBwdArgs) * n);
-  B.d_tail = (UpsTailArgs*)put(h_tail.data(), sizeof(UpsTailArgs) * n);
   B.d_comb_side = (CombineArgs*)put(h_comb_side.data(), sizeof(CombineArgs) * n);
   B.d_comb_main = (CombineArgs*)put(h_comb_main.data(), sizeof(CombineArgs) * n);
   B.d_fin = (FinalArgs*)put(h_fin.data(), sizeof(FinalArgs) * n);
@@ -657,7 +624,6 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   putw(w_t0, &B.w_t0, &B.n_t0);
   putw(w_syn, &B.w_syn, &B.n_syn);
   putw(w_head, &B.w_head, &B.n_head);
-  putw(w_tail, &B.w_tail, &B.n_tail);
   for (int s = 0; s + 1 < L; ++s) putw(w_upb[s], &B.w_upb[s], &B.n_upb[s]);
   putw(w_comb_side, &B.w_comb_side, &B.n_comb_side);
   putw(w_comb_main, &B.w_comb_main, &B.n_comb_main);
@@ -716,8 +682,6 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   for (int s = 0; s + 1 < B.L; ++s)
     if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
       return rc;
-  if ((rc = go(CC_STAGE_NONE, (const void*)ups_tail_kernel_batch, B.n_tail, UT_THREADS, B.d_tail, B.w_tail)))
-    return rc;
   if ((rc = join_from(sd, st))) return rc;
   if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb_main, 256, B.d_comb_main, B.w_comb_main)))
     return rc;

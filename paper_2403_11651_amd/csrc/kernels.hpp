@@ -74,28 +74,6 @@ struct UpsBwdArgs {
 __global__ void ups_bwd_kernel(UpsBwdArgs a);
 __global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
 
-// The coarse steps of the adjoint, from step s0 on: the gradient path of
-// each latent level l is a chain of its own (channel l - s - 1 of stack_{s+1}
-// at step s; the channels never mix), so one 1024-thread work-group per
-// chain (l = s0 + 1 + blockIdx) runs steps s0 .. l - 1 with whole planes in
-// LDS.  s0 is the first step whose planes fit the UT_* capacities (small, so
-// that the work-group fits beside the ARM work-groups).
-constexpr int UT_G = 2048, UT_T = 1280, UT_T2 = 1280, UT_P = 768;  // floats
-constexpr int UT_THREADS = 256;
-struct UpsTailArgs {
-  Geo geo;
-  int s0;
-  const float* y;
-  const float* u;
-  int quant;
-  const float* ups_w;          // [L-1][2][K] all taps
-  const float* up_in[MAXL];    // U_s output (channels 1.. of stack_s), s = 1..L-2
-  const float* g_in;           // [(L-1-s0)][h_s0][w_s0]: gradient of U_s0's output
-  float* g_y;                  // packed latent gradient
-  float* part[MAXL];           // step s >= s0: [(L-1-s)][2K] tap partials, row = channel of stack_{s+1}
-};
-__global__ void ups_tail_kernel(UpsTailArgs a);
-__global__ void ups_tail_kernel_batch(const UpsTailArgs* d, const WorkItem* w);
 
 // ---------------------------------------------------------------- synthesis
 constexpr int SYN_T = 16;                  // output tile side (pixels)

@@ -263,133 +263,6 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
   }
 }
 
-// One chain of the coarse adjoint steps (see UpsTailArgs), UT_THREADS threads.  A
-// step maps the gradient plane G of level s (h_s x w_s, in LDS) to level s+1:
-//   T [row][pc] = sum_kx h[kx] G[row][2 pc + kx - 7]      (pc: padded column pc - 2)
-//   T2[pr][col] = sum_ky v[ky] G[2 pr + ky - 7][col]      (pr: padded row pr - 2)
-//   P [pr][pc]  = sum_ky v[ky] T[2 pr + ky - 7][pc]        (= g_pad)
-//   out[r][m]   = sum of P over the padded indices that clamp to (r, m)
-//   dL/dv[ky]  += in_pad[pr][pc] T[2 pr + ky - 7][pc],  dL/dh[kx] += in_pad[pr][pc] T2[pr][2 pc + kx - 7]
-// and out becomes the next step's G, until the chain reaches its own level,
-// whose out is the latent gradient.
-__device__ __forceinline__ void ups_tail_body(const UpsTailArgs& a, const int b) {
-  __shared__ float sG[UT_G], sT[UT_T], sT2[UT_T2], sP[UT_P], sIn[UT_G / 4];
-  __shared__ float s_red[UT_THREADS / 64][2 * UPS_K];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int s0 = a.s0, lvl = s0 + 1 + b;
-  {
-    const int n = a.geo.lh[s0] * a.geo.lw[s0];
-    const float* src = a.g_in + (size_t)b * n;
-    batched_stage<UT_G / UT_THREADS, UT_THREADS>(
-        tid, n, [&](int p) { return src[p]; }, [&](int p, float v) { sG[p] = v; });
-  }
-  __syncthreads();
-  for (int s = s0; s < lvl; ++s) {
-    const int hs = a.geo.lh[s], ws = a.geo.lw[s], hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1];
-    const int HP = hi + 4, WP = wi + 4, cs = lvl - s - 1;  // channel of stack_{s+1} on this chain
-    float v[UPS_K], hh[UPS_K], gv[UPS_K], gh[UPS_K];
-#pragma unroll
-    for (int k = 0; k < UPS_K; ++k) {
-      v[k] = a.ups_w[(size_t)s * 2 * UPS_K + k];
-      hh[k] = a.ups_w[(size_t)s * 2 * UPS_K + UPS_K + k];
-      gv[k] = 0.0f;
-      gh[k] = 0.0f;
-    }
-    // this chain's channel of stack_{s+1} (the input of U_s), fetched while
-    // the two partial passes run
-    const int lo = a.geo.loff[s + 1];
-    constexpr int NIN = UT_G / 4 / UT_THREADS + 1;
-    float inr[NIN], inu[NIN];
-#pragma unroll
-    for (int q = 0; q < NIN; ++q) {
-      const int p = tid + UT_THREADS * q;
-      inr[q] = 0.0f;
-      inu[q] = 0.0f;
-      if (p < hi * wi) {
-        if (cs == 0) {
-          inr[q] = a.y[lo + p];
-          if (a.quant == 1) inu[q] = a.u[lo + p];
-        } else {
-          inr[q] = a.up_in[s + 1][(size_t)(cs - 1) * hi * wi + p];
-        }
-      }
-    }
-    for (int p = tid; p < hs * WP; p += UT_THREADS) {
-      const int row = p / WP, pc = p % WP;
-      float acc = 0.0f;
-#pragma unroll
-      for (int k = 0; k < UPS_K; ++k) {
-        const int col = 2 * pc + k - 7;
-        if (col >= 0 && col < ws) acc = __builtin_fmaf(hh[k], sG[row * ws + col], acc);
-      }
-      sT[p] = acc;
-    }
-    for (int p = tid; p < HP * ws; p += UT_THREADS) {
-      const int pr = p / ws, col = p % ws;
-      float acc = 0.0f;
-#pragma unroll
-      for (int k = 0; k < UPS_K; ++k) {
-        const int row = 2 * pr + k - 7;
-        if (row >= 0 && row < hs) acc = __builtin_fmaf(v[k], sG[row * ws + col], acc);
-      }
-      sT2[p] = acc;
-    }
-#pragma unroll
-    for (int q = 0; q < NIN; ++q) {
-      const int p = tid + UT_THREADS * q;
-      if (p < hi * wi) sIn[p] = cs == 0 ? quantise_raw(inr[q], inu[q], a.quant) : inr[q];
-    }
-    __syncthreads();
-    for (int p = tid; p < HP * WP; p += UT_THREADS) {
-      const int pr = p / WP, pc = p % WP;
-      const float inp = sIn[clampi(pr - 2, 0, hi - 1) * wi + clampi(pc - 2, 0, wi - 1)];
-      float acc = 0.0f;
-#pragma unroll
-      for (int k = 0; k < UPS_K; ++k) {
-        const int row = 2 * pr + k - 7;
-        if (row >= 0 && row < hs) {
-          const float t = sT[row * WP + pc];
-          acc = __builtin_fmaf(v[k], t, acc);
-          gv[k] = __builtin_fmaf(inp, t, gv[k]);
-        }
-        const int col = 2 * pc + k - 7;
-        if (col >= 0 && col < ws) gh[k] = __builtin_fmaf(inp, sT2[pr * ws + col], gh[k]);
-      }
-      sP[p] = acc;
-    }
-    __syncthreads();
-    for (int p = tid; p < hi * wi; p += UT_THREADS) {
-      const int r = p / wi, m = p % wi;
-      const int pr0 = r == 0 ? 0 : r + 2, pr1 = r == hi - 1 ? hi + 3 : r + 2;
-      const int pc0 = m == 0 ? 0 : m + 2, pc1 = m == wi - 1 ? wi + 3 : m + 2;
-      float acc = 0.0f;
-      for (int pr = pr0; pr <= pr1; ++pr)
-        for (int pc = pc0; pc <= pc1; ++pc) acc += sP[pr * WP + pc];
-      if (cs == 0) a.g_y[lo + p] = acc;
-      else sG[p] = acc;
-    }
-#pragma unroll
-    for (int k = 0; k < UPS_K; ++k) {
-      gv[k] = wave_sum(gv[k]);
-      gh[k] = wave_sum(gh[k]);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < UPS_K; ++k) {
-        s_red[wave][k] = gv[k];
-        s_red[wave][UPS_K + k] = gh[k];
-      }
-    }
-    __syncthreads();
-    if (tid < 2 * UPS_K) {
-      float acc = 0.0f;
-      for (int w = 0; w < UT_THREADS / 64; ++w) acc += s_red[w][tid];
-      a.part[s][cs * 2 * UPS_K + tid] = acc;
-    }
-    __syncthreads();
-  }
-}
-
 __global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) { ups_fwd_body(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void ups_fwd_kernel_batch(const UpsFwdArgs* __restrict__ d,
                                                             const WorkItem* __restrict__ w) {
@@ -403,13 +276,6 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel_batch(const UpsBwdArgs* __
                                                             const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
   ups_bwd_body(d[it.img], it.bid, it.nblk, it.aux);
-}
-
-__global__ __launch_bounds__(UT_THREADS) void ups_tail_kernel(UpsTailArgs a) { ups_tail_body(a, blockIdx.x); }
-__global__ __launch_bounds__(UT_THREADS) void ups_tail_kernel_batch(const UpsTailArgs* __restrict__ d,
-                                                                    const WorkItem* __restrict__ w) {
-  const WorkItem it = w[blockIdx.x];
-  ups_tail_body(d[it.img], it.bid);
 }
 
 }  // namespace cc
