@@ -234,7 +234,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
 template <int FS, bool INSIDE, typename WP>
 __device__ __forceinline__ void res_pre(WP wr, const float* src, int fa, int fb, int fi0, int fj0, int H,
                                         int W, float (&pre)[3]) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  constexpr int FA = SYN_FA;
   int ca = fa, cb = fb;
   if (!INSIDE) {
     ca = clampi(fi0 + fa, 0, H - 1) - fi0;
@@ -259,7 +259,7 @@ __device__ __forceinline__ void res_pre(WP wr, const float* src, int fa, int fb,
 template <int FS, int LO, bool INSIDE, typename WP>
 __device__ __forceinline__ void res_layer(WP wr, const float* src, float* dst, int fi0, int fj0, int H,
                                           int W, bool relu, int tid) {
-  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FA;
   int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
   asm volatile("" : "+s"(zo));
   wr += zo;
@@ -280,7 +280,7 @@ template <int FS, int LO, bool INSIDE, typename WP>
 __device__ __forceinline__ void res_layer_last(WP wr, const float* src, float* g, int fi0, int fj0,
                                                int H, int W, const float* __restrict__ img, float dscale, float& sse,
                                                int tid) {
-  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX, E = FS / 2 - SYN_T / 2;
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FA, E = FS / 2 - SYN_T / 2;
   int zo = 0;
   asm volatile("" : "+s"(zo));
   wr += zo;
@@ -302,7 +302,7 @@ __device__ __forceinline__ void res_layer_last(WP wr, const float* src, float* g
 
 template <int HS, int NRES>
 __device__ __forceinline__ void syn_res_fwd_body(const SynArgs& a, const int bid, const int nblk) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX, E = NRES, FS = SYN_T + 2 * E;
+  constexpr int FA = SYN_FA, E = NRES, FS = SYN_T + 2 * E;
   __shared__ SynW<HS, NRES> sw;
   __shared__ float s_t[2][3 * FA];
   const int H = a.geo.H, W = a.geo.W, tid = threadIdx.x;
@@ -421,7 +421,7 @@ __device__ __forceinline__ void mfma_xty64(f32x4 (&acc)[BM][BN], const float* Xs
 template <int FS, int E>
 __device__ __forceinline__ void conv_wgrad(f32x4 (&acc)[1][2], const float* g, const float* t, int i0, int j0,
                                            int H, int W, int wave, int lane) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX;
+  constexpr int FA = SYN_FA;
   const int col = lane & 15, kq = lane >> 4;
   int ko[2];
 #pragma unroll
@@ -463,7 +463,7 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[BM][BN]) {
 template <int FS, int LO, bool INSIDE, int OUT, typename WP>
 __device__ __forceinline__ void res_adjoint(WP wr, const float* g, float* gout, const float* tm,
                                             float* __restrict__ gpt, int fi0, int fj0, int H, int W, int tid) {
-  constexpr int SIDE = FS - 2 * LO, FA = SYN_FMAX * SYN_FMAX;
+  constexpr int SIDE = FS - 2 * LO, FA = SYN_FA;
   int zo = 0;  // opaque zero: the weights are read here, not hoisted out of the caller's loops
   asm volatile("" : "+s"(zo));
   wr += zo;
@@ -526,7 +526,7 @@ __device__ __forceinline__ void res_adjoint(WP wr, const float* g, float* gout, 
 // the matrix cores.
 template <int HS, int NRES>
 __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, const int nblk) {
-  constexpr int FA = SYN_FMAX * SYN_FMAX, E = 2 * NRES, FS = SYN_T + 2 * E;
+  constexpr int FA = SYN_FA, E = 2 * NRES, FS = SYN_T + 2 * E;
   // LDS pool: residual-conv frames t_0..t_{NRES-1} and two gradient buffers
   // (x_hat = t_NRES is never stored)
   constexpr int POOL = (NRES + 2) * 3 * FA;
