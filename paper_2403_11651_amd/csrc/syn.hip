@@ -657,13 +657,21 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
 // 16-wide chunk of hidden units, each wave stages the chunk's a and g_a of
 // its 64 pixels and accumulates X^T Y on v_mfma_f32_16x16x4f32; the bias
 // columns ride along (z[7] = 1, hidden unit HS = 1).
-template <int HS, int NRES>
+// HALF: a chunk's a and g_a are staged for half a wave at a time (the same
+// items in the same order, so the same results), which halves that staging:
+// more work-groups per CU.  The batched launches use it; the single-image
+// launch keeps the full staging, which leaves more of each CU to the ARM
+// running beside it.
+template <int HS, int NRES, bool HALF>
 __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bid) {
   constexpr int T = SYN_HD, RS = T / 2 + 4;
   constexpr int NC = (HS + 1 + 15) / 16;  // chunks of the hidden units (+ the bias unit)
   constexpr int NCG = (HS + 15) / 16;     // chunks holding hidden units
   constexpr int SYZ = 9, SXT = 3, SYA = 17, SXG = 17;      // staged row lengths
-  constexpr int STG = 64 * (SYZ + SXT + SYA + SXG);        // per wave
+  // per wave: z and g_pre_t of its 64 pixels, and a chunk's a and g_a for
+  // 32 of them (the two halves of the wave are staged in turn)
+  constexpr int NSTG = HALF ? 32 : 64;  // pixels whose a, g_a are staged at once
+  constexpr int STG = 64 * (SYZ + SXT) + NSTG * (SYA + SXG);
   constexpr int ZPOOL = (MAXL - 1) * RS * (RS + 1) + (MAXL - 1) * T * (RS + 1);
   constexpr int NH = HS * MAXL + HS + 3 * HS + 3;          // head parameters (upper bound over L)
   constexpr int P1 = 4 * STG > ZPOOL ? 4 * STG : ZPOOL;
@@ -742,7 +750,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
   float* Yz = pool + wave * STG;
   float* Xt = Yz + 64 * SYZ;
   float* Ya = Xt + 64 * SXT;
-  float* Xg = Ya + 64 * SYA;
+  float* Xg = Ya + NSTG * SYA;
 #pragma unroll
   for (int c = 0; c < 8; ++c) Yz[lane * SYZ + c] = zz[c];
 #pragma unroll
@@ -757,6 +765,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
     int wz = 0;
     asm volatile("" : "+s"(wz));
     const SynW<HS, NRES>& swl = *reinterpret_cast<const SynW<HS, NRES>*>(reinterpret_cast<const char*>(&sw) + wz);
+    float avs[16], gvs[16];
 #pragma unroll 4
     for (int u = 0; u < 16; ++u) {
       const int f = 16 * k + u;
@@ -776,23 +785,34 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
       } else if (f == HS) {
         av = own ? 1.0f : 0.0f;  // the bias unit of the second layer
       }
-      Ya[lane * SYA + u] = av;
-      Xg[lane * SXG + u] = gv;
+      avs[u] = av;
+      gvs[u] = gv;
     }
-    wave_lds_sync();
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int item = 4 * t + (lane >> 4);
-      const float xt = Xt[item * SXT + min(col, 2)];
-      const float ya = Ya[item * SYA + col];
-      accW2[0][k] = mfma16x16x4(col < 3 ? xt : 0.0f, ya, accW2[0][k]);
-      if (k < NCG) {
-        const float xg = Xg[item * SXG + col];
-        const float yz = Yz[item * SYZ + min(col, 7)];
-        accW1[k < NCG ? k : 0][0] = mfma16x16x4(xg, col < 8 ? yz : 0.0f, accW1[k < NCG ? k : 0][0]);
+    for (int half = 0; half < 64 / NSTG; ++half) {
+      if (!HALF || (lane >> 5) == half) {
+        const int row = HALF ? lane & 31 : lane;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          Ya[row * SYA + u] = avs[u];
+          Xg[row * SXG + u] = gvs[u];
+        }
       }
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < NSTG / 4; ++t) {
+        const int item = 4 * t + (lane >> 4), px = NSTG * half + item;
+        const float xt = Xt[px * SXT + min(col, 2)];
+        const float ya = Ya[item * SYA + col];
+        accW2[0][k] = mfma16x16x4(col < 3 ? xt : 0.0f, ya, accW2[0][k]);
+        if (k < NCG) {
+          const float xg = Xg[item * SXG + col];
+          const float yz = Yz[px * SYZ + min(col, 7)];
+          accW1[k < NCG ? k : 0][0] = mfma16x16x4(xg, col < 8 ? yz : 0.0f, accW1[k < NCG ? k : 0][0]);
+        }
+      }
+      wave_lds_sync();
     }
-    wave_lds_sync();
   }
   if (own) {
     const int px = pi * W + pj;
@@ -864,13 +884,13 @@ __global__ __launch_bounds__(SYN_THREADS, 3) void syn_bwd_kernel_batch(const Syn
 
 template <int HS, int NRES>
 __global__ __launch_bounds__(256) void syn_head_bwd_kernel(SynArgs a) {
-  syn_head_bwd_body<HS, NRES>(a, blockIdx.x);
+  syn_head_bwd_body<HS, NRES, false>(a, blockIdx.x);
 }
 template <int HS, int NRES>
 __global__ __launch_bounds__(256) void syn_head_bwd_kernel_batch(const SynArgs* __restrict__ d,
                                                                  const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
-  syn_head_bwd_body<HS, NRES>(d[it.img], it.bid);
+  syn_head_bwd_body<HS, NRES, true>(d[it.img], it.bid);
 }
 
 #define CC_SYN_TABLE(KERNEL)                                         \
