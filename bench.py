@@ -295,33 +295,30 @@ def main():
     torch.cuda.synchronize()
     loss_start = loss4.clone()
 
-    # Per-launch kernel timing with HIP events on the library's stream.  The
-    # events are torch's (the same HIP runtime the library is bound to); the
-    # library records them around the named kernel's launch.
+    # Per-launch kernel timing with HIP events on the library's stream: the
+    # library records a pair of its timing events (timestamps without the
+    # system-scope cache fence of a default event) around the named kernel's
+    # launch in every timed iteration.
     K = args.steps
-    def events(n):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
-        for e in evs:
-            e.record(stream)  # creates the underlying hipEvent_t
-        return evs
-    arm_ev, syn_ev, t_ev = events(2 * K), events(2 * K), events(2)
+    st_ev = [(B.TimingEvent(), B.TimingEvent()) for _ in range(K)]
+    t_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
     t_ev[0].record(stream)
     t_wall = time.perf_counter()
     for k in range(K):
         # alternate the timed stage so both kernels are covered over the run
         if k % 2 == 0:
-            B.coolchic_set_stage_events(B.CC_STAGE_ARM, arm_ev[2 * k].cuda_event, arm_ev[2 * k + 1].cuda_event)
+            B.coolchic_set_stage_events(B.CC_STAGE_ARM, st_ev[k][0].handle, st_ev[k][1].handle)
         else:
-            B.coolchic_set_stage_events(B.CC_STAGE_SYNTHESIS, syn_ev[2 * k].cuda_event, syn_ev[2 * k + 1].cuda_event)
+            B.coolchic_set_stage_events(B.CC_STAGE_SYNTHESIS, st_ev[k][0].handle, st_ev[k][1].handle)
         one_step()
     B.coolchic_set_stage_events(B.CC_STAGE_NONE)
     t_ev[1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = t_ev[0].elapsed_time(t_ev[1])
-    arm_ms = [arm_ev[2 * k].elapsed_time(arm_ev[2 * k + 1]) for k in range(0, K, 2)]
-    syn_ms = [syn_ev[2 * k].elapsed_time(syn_ev[2 * k + 1]) for k in range(1, K, 2)]
+    arm_ms = [st_ev[k][0].elapsed_ms(st_ev[k][1]) for k in range(0, K, 2)]
+    syn_ms = [st_ev[k][0].elapsed_ms(st_ev[k][1]) for k in range(1, K, 2)]
     l4 = loss4.cpu().numpy()
     if l4[3] != 0.0 or not np.isfinite(l4[0]):
         print(f"non-finite loss during the timed run: {l4}", file=sys.stderr)

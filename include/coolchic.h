@@ -148,6 +148,20 @@ int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int6
 enum { CC_STAGE_NONE = 0, CC_STAGE_ARM = 1, CC_STAGE_SYNTHESIS = 2 };
 int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end);
 
+/* Timing events for the measurement hook (not part of the method).  A
+   timing event records a GPU timestamp without the system-scope cache fence
+   of a default HIP event: it orders nothing for the host or other devices,
+   and timing a stage on every call then costs the pass as little as
+   possible.  coolchic_timing_event_create stores a new hipEvent_t handle in
+   *ev (owned by the caller, released with coolchic_timing_event_destroy);
+   coolchic_timing_event_elapsed writes the milliseconds between two
+   recorded events to *ms (host pointer) once both have completed
+   (synchronise the stream first; HIP's not-ready error is returned as
+   CC_EHIP otherwise).  CC_EINVAL for a null argument. */
+int coolchic_timing_event_create(void** ev);
+int coolchic_timing_event_elapsed(void* ev_begin, void* ev_end, float* ms);
+int coolchic_timing_event_destroy(void* ev);
+
 /* Uniform noise u in [-1/2, 1/2) for the training proxy y_hat = y + u
    (Section II "Encoding": the latents are optimised through a
    differentiable proxy of the quantisation).  u[4g + e] = (w_e >> 8) 2^-24

@@ -25,7 +25,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_strerror", "coolchic_batch_workspace_bytes", "coolchic_batch_create",
            "coolchic_batch_backward", "coolchic_batch_destroy", "coolchic_warm_param_count",
            "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward",
-           "coolchic_uniform_noise", "coolchic_warm_backward_grad")
+           "coolchic_uniform_noise", "coolchic_warm_backward_grad", "coolchic_timing_event_create",
+           "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -74,6 +75,9 @@ def _load():
         "coolchic_decode_synth": (I, [pp, P, P, P, P, P, SZ, P]),
         "coolchic_adam_step": (I, [P, P, P, P, I64, P, F, F, F, F, P]),
         "coolchic_set_stage_events": (I, [I, P, P]),
+        "coolchic_timing_event_create": (I, [ctypes.POINTER(P)]),
+        "coolchic_timing_event_elapsed": (I, [P, P, ctypes.POINTER(F)]),
+        "coolchic_timing_event_destroy": (I, [P]),
         "coolchic_strerror": (ctypes.c_char_p, [I]),
         "coolchic_batch_workspace_bytes": (SZ, [I, pp, ctypes.POINTER(CCBatchTuning)]),
         "coolchic_batch_create": (I, [I, pp, ctypes.POINTER(CCImageIO), ctypes.POINTER(CCBatchTuning), F, P, SZ,
@@ -244,6 +248,27 @@ def coolchic_uniform_noise(u, seed: int, step=None, stream_id: int = 0, stream=N
 def coolchic_set_stage_events(stage: int, ev_begin=None, ev_end=None):
     """ev_begin / ev_end: raw hipEvent_t handles (ints) or None."""
     _check(_lib.coolchic_set_stage_events(int(stage), ev_begin, ev_end), "coolchic_set_stage_events")
+
+
+class TimingEvent:
+    """A fence-free timing event of the library (coolchic_timing_event_*);
+    .handle is the raw hipEvent_t for coolchic_set_stage_events."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(_lib.coolchic_timing_event_create(ctypes.byref(h)), "coolchic_timing_event_create")
+        self.handle = h.value
+
+    def elapsed_ms(self, end: "TimingEvent") -> float:
+        ms = ctypes.c_float()
+        _check(_lib.coolchic_timing_event_elapsed(self.handle, end.handle, ctypes.byref(ms)),
+               "coolchic_timing_event_elapsed")
+        return ms.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.coolchic_timing_event_destroy(self.handle)
+            self.handle = None
 
 
 def batch_workspace_bytes(probs, tune=(0, 0)) -> int:

@@ -152,3 +152,12 @@ def test_warm_workspace_and_invalid_problems(B):
     assert B.lib.coolchic_warm_forward(ctypes.byref(pc), d, d, d, d, d, f - 1, None) == B.CC_EWORKSPACE
     assert B.lib.coolchic_warm_backward(ctypes.byref(pc), d, d, d, d, d, None, d, b, None) == B.CC_EINVAL
     assert B.lib.coolchic_warm_backward(ctypes.byref(pc), d, d, d, d, d, d, d, b - 1, None) == B.CC_EWORKSPACE
+
+
+def test_timing_event_null_arguments(B):
+    d = ctypes.c_void_p(0x1000)
+    ms = ctypes.c_float()
+    assert B.lib.coolchic_timing_event_create(None) == -1
+    assert B.lib.coolchic_timing_event_elapsed(None, d, ctypes.byref(ms)) == -1
+    assert B.lib.coolchic_timing_event_elapsed(d, d, None) == -1
+    assert B.lib.coolchic_timing_event_destroy(None) == -1

@@ -205,3 +205,21 @@ def test_nonfinite_flag(B):
     assert gpu_backward(B, c)["loss4"][3] == 1.0
     c2 = CS.tiny()
     assert gpu_backward(B, c2)["loss4"][3] == 0.0
+
+
+def test_stage_timing_events(B):
+    """The measurement hook with the library's timing events: both stages
+    report a positive duration and the gradients are those of a call
+    without the hook, bit for bit."""
+    c = CS.tiny()
+    ref = gpu_backward(B, c)
+    for stage in (B.CC_STAGE_ARM, B.CC_STAGE_SYNTHESIS):
+        e0, e1 = B.TimingEvent(), B.TimingEvent()
+        B.coolchic_set_stage_events(stage, e0.handle, e1.handle)
+        try:
+            out = gpu_backward(B, c)
+        finally:
+            B.coolchic_set_stage_events(B.CC_STAGE_NONE)
+        assert e0.elapsed_ms(e1) > 0.0
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (stage, k)
