@@ -38,7 +38,7 @@ struct Plan {
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
-  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], flags, total;
+  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], total;
   int head_grid;  // tiles of the 1x1-layer backward
   int n_head;     // 1x1-layer parameters (W1, b1, W2, b2)
 };
@@ -145,7 +145,6 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
     P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
     for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * P->ups_chunks[s] * 2 * UPS_K);
-    P->flags = take(cur, (size_t)P->red_grid + P->fold_grid);
   }
   P->total = cur;
   return CC_OK;
@@ -354,6 +353,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   sa.hpart = W + P.hpart;
   sa.wpart = W + P.wpart_syn;
   sa.spart = W + P.spart;
+  sa.flag_clear = loss4 + 3;
   b->t0_grid = t0_tiles(p->H, p->W);
   for (int s = 0; s + 1 < L; ++s) {
     UpsBwdArgs& ua = b->upb[s];
@@ -366,11 +366,20 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ua.part = W + P.upart[s];
     ua.cpb = P.ups_cpb[s];
   }
+  // the loss of Eq. (1) from the rate and squared-error partials (complete
+  // once the ARM and the residual-conv backward have run); the non-finite
+  // flag loss4[3] is cleared by syn_t0_kernel and set by any combine block
+  // or the loss block that meets a non-finite value
+  FinalArgs& fa = b->fin;
+  fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
+  fa.flags = nullptr; fa.nflags = 0;
+  fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
+  fa.have_rate = 1; fa.have_sse = 1; fa.sticky = 1; fa.loss4 = loss4;
   // two combine launches: the side one (after the ARM, beside the
-  // upsampling adjoint) sums the ARM and synthesis weight-gradient partials;
-  // the final one sums the upsampling tap partials and folds the ARM context
-  // gradients into g_y
-  auto build = [&](CombineArgs& ca, int* grid, int flag_off, bool final_part) {
+  // upsampling adjoint) sums the ARM and synthesis weight-gradient partials
+  // and evaluates the loss in one more block; the final one sums the
+  // upsampling tap partials and folds the ARM context gradients into g_y
+  auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
     auto add = [&](const float* src, int rows, int cols, float* dst) {
       ca.seg[ns] = RedSeg{src, rows, cols, cols, 1, dst};
@@ -388,20 +397,20 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     }
     ca.nseg = ns;
     ca.block_start[ns] = blk;
-    ca.flags = W + P.flags + flag_off;
+    ca.flags = nullptr;
+    ca.bad = loss4 + 3;
+    ca.loss_block = -1;
     if (final_part) {
       ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
       blk += P.fold_grid;
+    } else {
+      ca.loss_block = blk++;
+      ca.fin = fa;
     }
     *grid = blk;
   };
-  build(b->comb_side, &b->comb_side_grid, 0, false);
-  build(b->comb_main, &b->comb_main_grid, b->comb_side_grid, true);
-  FinalArgs& fa = b->fin;
-  fa.rpart = W + P.rpart; fa.nr = P.arm_grid; fa.spart = W + P.spart; fa.ns = P.syn_grid;
-  fa.flags = W + P.flags; fa.nflags = b->comb_side_grid + b->comb_main_grid;
-  fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
-  fa.have_rate = 1; fa.have_sse = 1; fa.loss4 = loss4;
+  build(b->comb_side, &b->comb_side_grid, false);
+  build(b->comb_main, &b->comb_main_grid, true);
 }
 
 int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
@@ -444,7 +453,6 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   }
   if ((rc = join_from(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_main_grid, 256, &b.comb_main, st))) return rc;
-  if ((rc = launch((const void*)finalize_kernel, 1, 256, &b.fin, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
@@ -463,7 +471,6 @@ struct BatchPlan {
   SynArgs* d_syn = nullptr;
   UpsBwdArgs* d_upb[MAXL] = {};
   CombineArgs *d_comb_side = nullptr, *d_comb_main = nullptr;
-  FinalArgs* d_fin = nullptr;
   WorkItem *w_arm = nullptr, *w_upf = nullptr, *w_t0 = nullptr, *w_syn = nullptr, *w_head = nullptr,
            *w_upb[MAXL] = {}, *w_comb_side = nullptr, *w_comb_main = nullptr;
   int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb_side = 0, n_comb_main = 0;
@@ -510,11 +517,11 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   for (int s = 0; s + 1 < L; ++s) blk(sizeof(UpsBwdArgs) * n);
   blk(sizeof(CombineArgs) * n);
   blk(sizeof(CombineArgs) * n);
-  blk(sizeof(FinalArgs) * n);
   long long items = 0;
   for (int k = 0; k < n; ++k) {
     const Plan& P = plans[k];
-    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid;
+    // the combine launches: red_grid + fold_grid blocks and the loss block
+    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid + 1;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
@@ -575,7 +582,6 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   std::vector<SynArgs> h_syn(n);
   std::vector<std::vector<UpsBwdArgs>> h_upb(L, std::vector<UpsBwdArgs>(n));
   std::vector<CombineArgs> h_comb_side(n), h_comb_main(n);
-  std::vector<FinalArgs> h_fin(n);
   std::vector<WorkItem> w_arm, w_upf, w_t0, w_syn, w_head, w_comb_side, w_comb_main;
   std::vector<std::vector<WorkItem>> w_upb(L);
   BwdSet* b = new (std::nothrow) BwdSet;
@@ -587,7 +593,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     build_backward(&probs[k], P, W, q.img, q.y, q.u, q.arm_w, q.ups_w, q.syn_w, dloss, q.loss4, q.g_y, q.g_arm,
                    q.g_ups, q.g_syn, b);
     h_arm[k] = b->arm; h_upf[k] = b->upf; h_syn[k] = b->syn;
-    h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main; h_fin[k] = b->fin;
+    h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main;
     for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
     for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
     for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
@@ -617,7 +623,6 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   for (int s = 0; s + 1 < L; ++s) B.d_upb[s] = (UpsBwdArgs*)put(h_upb[s].data(), sizeof(UpsBwdArgs) * n);
   B.d_comb_side = (CombineArgs*)put(h_comb_side.data(), sizeof(CombineArgs) * n);
   B.d_comb_main = (CombineArgs*)put(h_comb_main.data(), sizeof(CombineArgs) * n);
-  B.d_fin = (FinalArgs*)put(h_fin.data(), sizeof(FinalArgs) * n);
   auto putw = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) {
     *cnt = (int)v.size();
     *dst = (WorkItem*)put(v.data(), sizeof(WorkItem) * v.size());
@@ -688,12 +693,6 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   if ((rc = join_from(sd, st))) return rc;
   if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb_main, 256, B.d_comb_main, B.w_comb_main)))
     return rc;
-  {
-    void* descs = B.d_fin;
-    void* argv[] = {&descs};
-    if (hipLaunchKernel((const void*)finalize_kernel_batch, dim3(B.n), dim3(256), argv, 0, st) != hipSuccess)
-      return CC_EHIP;
-  }
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 
@@ -905,6 +904,7 @@ int warm_plan(const cc_warm_problem* p, int which, WarmPlan* P, float* base) {
     // column sums of every partial block into the gradient, in layout order
     CombineArgs& ca = P->comb;
     std::memset(&ca, 0, sizeof(ca));
+    ca.loss_block = -1;
     int nsg = 0, blk = 0;
     auto seg = [&](const float* src, int rows, int cols, int dst_off) {
       ca.seg[nsg] = RedSeg{src, rows, cols, cols, 16, (float*)(intptr_t)dst_off};

@@ -107,6 +107,7 @@ struct SynArgs {
   float* wpart;        // backward: [gridDim][n_res * 84] residual-conv weight-gradient partials
   float* hpart;        // backward: [head tiles][Hs L + 4 Hs + 3] 1x1-layer weight-gradient partials
   float* spart;        // [gridDim] squared-error partial sums
+  float* flag_clear;   // optional: block 0 of syn_t0_kernel stores 0 here (the non-finite flag of the pass)
   int n_tiles_x, n_tiles;
 };
 const void* syn_t0_kernel_for(int Hs, int nres, bool batch);
@@ -128,23 +129,28 @@ struct FinalArgs {
   const float* flags; int nflags;
   float lambda, inv_hw, inv_3hw;
   int have_rate, have_sse;
+  int sticky;          // 1: loss4[3] is only ever set to 1 (cleared earlier in the pass), 0: written 0 or 1
   float* loss4;
 };
 
-// One launch does two independent jobs: blocks [0, n_red) sum partial
-// matrices column by column (segments in order), blocks [n_red, n_red +
-// fold blocks) fold the ARM context gradients into g_y.
+// One launch does up to three independent jobs: blocks [0, n_red) sum
+// partial matrices column by column (segments in order), blocks [n_red,
+// n_red + fold blocks) fold the ARM context gradients into g_y, and block
+// loss_block (when >= 0, in place of a fold block) evaluates the loss from
+// fin.
 struct CombineArgs {
   RedSeg seg[RED_MAXSEG];
   int nseg;
   int block_start[RED_MAXSEG + 1];
   FoldArgs fold;
-  float* flags;        // [gridDim] 1 if any result of the block is not finite
+  float* flags;        // [gridDim] 1 if any result of the block is not finite; or null, and then
+  float* bad;          // a block with a non-finite result stores 1 here (never 0)
+  int loss_block;
+  FinalArgs fin;
 };
 __global__ void combine_kernel(CombineArgs a);
 __global__ void combine_kernel_batch(const CombineArgs* d, const WorkItem* w);
 __global__ void finalize_kernel(FinalArgs a);
-__global__ void finalize_kernel_batch(const FinalArgs* d);
 
 struct AdamArgs {
   float* theta;

@@ -77,7 +77,8 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& a) {
     a.loss4[0] = L;
     a.loss4[1] = D;
     a.loss4[2] = R;
-    a.loss4[3] = (fl > 0.0f || !finitef(L) || !finitef(D) || !finitef(R)) ? 1.0f : 0.0f;
+    const bool bad = fl > 0.0f || !finitef(L) || !finitef(D) || !finitef(R);
+    if (bad || !a.sticky) a.loss4[3] = bad ? 1.0f : 0.0f;
   }
 }
 
@@ -88,6 +89,10 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& a) {
 __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid) {
   __shared__ float s_p[256];
   const int tid = threadIdx.x;
+  if (bid == a.loss_block) {
+    finalize_body(a.fin);
+    return;
+  }
   const int n_red = a.block_start[a.nseg];
   bool bad = false;
   if (bid >= n_red) {
@@ -117,7 +122,10 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
     }
   }
   const bool any = __syncthreads_or(bad);
-  if (tid == 0) a.flags[bid] = any ? 1.0f : 0.0f;
+  if (tid == 0) {
+    if (a.flags) a.flags[bid] = any ? 1.0f : 0.0f;
+    else if (any) *a.bad = 1.0f;
+  }
 }
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) { combine_body(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void combine_kernel_batch(const CombineArgs* __restrict__ d,
@@ -127,10 +135,6 @@ __global__ __launch_bounds__(256) void combine_kernel_batch(const CombineArgs* _
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) { finalize_body(a); }
-// one work-group per image
-__global__ __launch_bounds__(256) void finalize_kernel_batch(const FinalArgs* __restrict__ d) {
-  finalize_body(d[blockIdx.x]);
-}
 
 // Adam (Kingma & Ba) with bias correction; t = step[0] + 1.  Every block reads
 // step[0] before it adds itself to the completion counter step[1]; the block

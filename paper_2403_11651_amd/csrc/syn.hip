@@ -156,6 +156,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   const int i0 = (bid / ntx) * SYN_T0_H, j0 = (bid % ntx) * SYN_T0_W;
   const int r0 = i0 / 2 - 2, c0 = j0 / 2 - 2;
   const int nch = L - 1;
+  if (bid == 0 && tid == 0 && a.flag_clear) *a.flag_clear = 0.0f;
   float kv[UPS_K], kh[UPS_K];
   load_taps(a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
