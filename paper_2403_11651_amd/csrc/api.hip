@@ -31,7 +31,7 @@ struct Plan {
   ArmTiles tiles;
   int C, NH, K, Hs, nres;
   int64_t n_arm, n_ups, n_syn;
-  int arm_grid, syn_grid, syn_tiles_x, syn_tiles, fold_grid, red_grid;
+  int arm_grid, syn_grid, syn_tiles_x, syn_tiles, fold_split, fold_grid0, fold_grid1, red_grid;
   int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
   int ups_cpb[MAXL], ups_chunks[MAXL];  // channels per upsampling-adjoint block, blocks per tile
@@ -118,7 +118,11 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->ups_cpb[s] = P->ups_grid[s] >= 256 ? L - 1 - s : 1;
     P->ups_chunks[s] = cdiv(L - 1 - s, P->ups_cpb[s]);
   }
-  P->fold_grid = cdiv(g.n_lat, 256);
+  // the ARM context fold: level 0 (final once the head backward has run) and
+  // levels 1.. (final after the upsampling adjoint)
+  P->fold_split = L > 1 ? g.loff[1] : g.n_lat;
+  P->fold_grid0 = cdiv(P->fold_split, 256);
+  P->fold_grid1 = cdiv(g.n_lat - P->fold_split, 256);
   // column reductions, one column per block (256 row groups: every column
   // has hundreds to thousands of partial rows)
   P->red_blocks_arm = (int)P->n_arm;
@@ -375,10 +379,11 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   fa.flags = nullptr; fa.nflags = 0;
   fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
   fa.have_rate = 1; fa.have_sse = 1; fa.sticky = 1; fa.loss4 = loss4;
-  // two combine launches: the side one (after the ARM, beside the
-  // upsampling adjoint) sums the ARM and synthesis weight-gradient partials
-  // and evaluates the loss in one more block; the final one sums the
-  // upsampling tap partials and folds the ARM context gradients into g_y
+  // two combine launches: the side one (after the ARM and the head backward,
+  // beside the upsampling adjoint) sums the ARM and synthesis weight-gradient
+  // partials, folds the ARM context gradients of level 0 into g_y and
+  // evaluates the loss in one more block; the final one sums the upsampling
+  // tap partials and folds the context gradients of the other levels
   auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
     auto add = [&](const float* src, int rows, int cols, float* dst) {
@@ -400,10 +405,13 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ca.flags = nullptr;
     ca.bad = loss4 + 3;
     ca.loss_block = -1;
+    ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
     if (final_part) {
-      ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
-      blk += P.fold_grid;
+      ca.fold.q0 = P.fold_split; ca.fold.q1 = P.geo.n_lat;
+      blk += P.fold_grid1;
     } else {
+      ca.fold.q0 = 0; ca.fold.q1 = P.fold_split;
+      blk += P.fold_grid0;
       ca.loss_block = blk++;
       ca.fin = fa;
     }
@@ -520,8 +528,9 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   long long items = 0;
   for (int k = 0; k < n; ++k) {
     const Plan& P = plans[k];
-    // the combine launches: red_grid + fold_grid blocks and the loss block
-    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid + 1;
+    // the combine launches: reduction and fold blocks, and the loss block
+    items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid0 +
+             P.fold_grid1 + 1;
     items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }

@@ -42,6 +42,7 @@ struct FoldArgs {
   ArmTiles tiles;
   const float* gext;
   float* g_y;
+  int q0, q1;          // the latents [q0, q1) of the packed pyramid
 };
 
 

@@ -10,7 +10,7 @@ namespace cc {
 // contains latent q (own tile, left / right neighbours, and the three tiles of
 // the next tile row), in fixed order.
 __device__ bool arm_fold_one(const FoldArgs& a, int q) {
-  if (q >= a.geo.n_lat) return true;
+  if (q >= a.q1) return true;
   int l = 0;
   while (l + 1 < a.geo.L && q >= a.geo.loff[l + 1]) ++l;
   const int wl = a.geo.lw[l], local = q - a.geo.loff[l];
@@ -96,7 +96,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
   const int n_red = a.block_start[a.nseg];
   bool bad = false;
   if (bid >= n_red) {
-    bad = !arm_fold_one(a.fold, (bid - n_red) * 256 + tid);
+    bad = !arm_fold_one(a.fold, a.fold.q0 + (bid - n_red) * 256 + tid);
   } else {
     int sg = 0;
     while (sg + 1 < a.nseg && bid >= a.block_start[sg + 1]) ++sg;
