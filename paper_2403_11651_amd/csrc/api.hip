@@ -226,7 +226,7 @@ UpsFwdArgs ups_fwd_args(const Plan& P, float* ws, const float* y, const float* u
   std::memset(&a, 0, sizeof(a));
   a.geo = P.geo; a.y = y; a.u = u; a.quant = quant; a.ups_w = ups_w;
   for (int s = 1; s + 1 < L; ++s) a.up_out[s] = ws + P.up[s];
-  *grid = L < 3 ? 0 : cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+  *grid = L < 3 ? 0 : cdiv(P.geo.lh[1], UF_T) * cdiv(P.geo.lw[1], UF_T);
   return a;
 }
 
@@ -531,7 +531,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     // the combine launches: reduction and fold blocks, and the loss block
     items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid0 +
              P.fold_grid1 + 1;
-    items += cdiv(P.geo.lh[1], 32) * cdiv(P.geo.lw[1], 32);
+    items += cdiv(P.geo.lh[1], UF_T) * cdiv(P.geo.lw[1], UF_T);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
   blk(sizeof(WorkItem) * items + 256 * (L + 8));

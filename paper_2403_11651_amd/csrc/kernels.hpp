@@ -47,6 +47,7 @@ struct FoldArgs {
 
 
 // ---------------------------------------------------------------- upsampling
+constexpr int UF_T = 16;  // level-1 tile side of ups_fwd_kernel (one work-group per tile)
 struct UpsFwdArgs {
   Geo geo;
   const float* y;

@@ -18,12 +18,13 @@ namespace cc {
 // of level 1 and works from the coarsest level down: the region of
 // stack_{s+1} that U_s needs for the rows / columns [a, b) of level s is
 // [a/2 - 2, (b-1)/2 + 3) clipped to the grid (every clamped tap index falls in
-// it; at most 20 rows / columns for levels >= 2), so each work-group
+// it; at most UF_T/2 + 4 rows / columns for levels >= 2), so each work-group
 // recomputes, in LDS, the small coarse regions its tile depends on.  U_1 is
 // written for the tile; for s >= 2 the work-group writes the part of U_s that
 // lies under its tile, so every output is written exactly once.
-constexpr int UF_T = 32;       // level-1 tile side
-constexpr int UF_R = 20;       // largest region side at levels >= 2
+constexpr int UF_R = UF_T / 2 + 4;  // largest region side at levels >= 2
+// every level s <= L-2 keeps at least one row / column of the tile to write
+static_assert((UF_T >> (MAXL - 3)) >= 1 && UF_T % 2 == 0, "ups_fwd tile too small");
 constexpr int UF_CH = MAXL - 1;  // channels of stack_2 at most (L - 2 < 6)
 
 __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid) {
