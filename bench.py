@@ -273,14 +273,10 @@ def main():
     x = torch.from_numpy(img).to(dev).reshape(-1)
     loss4 = torch.zeros(4, device=dev)
     ws = B.workspace(p, B.CC_WS_BACKWARD, device=dev)
-    views = (theta[:ny], theta[ny:ny + na], theta[ny + na:ny + na + nu], theta[ny + na + nu:])
-    gviews = (grad[:ny], grad[ny:ny + na], grad[ny + na:ny + na + nu], grad[ny + na + nu:])
     stream = torch.cuda.current_stream()
 
-    def one_step():
-        B.coolchic_backward(p, x, views[0], None, views[1], views[2], views[3], 1.0, loss4, *gviews, ws=ws,
-                            stream=stream)
-        B.coolchic_adam_step(theta, grad, m, v, step, lr=1e-2, stream=stream)
+    def one_step():  # backward + Adam, the update fused into the gradient reductions
+        B.coolchic_train_step(p, x, None, 1.0, loss4, theta, grad, m, v, step, lr=1e-2, ws=ws, stream=stream)
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4

@@ -119,6 +119,20 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
                       float* loss4, float* g_y, float* g_arm, float* g_ups, float* g_syn,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* One training iteration: coolchic_backward, then one coolchic_adam_step
+   with the same arguments, on the packed vectors theta = [y | arm_w | ups_w |
+   syn_w] (N_lat + n_arm + n_ups + n_syn floats), with grad, m and v laid
+   out alike.  The Adam updates run inside the gradient reductions (each
+   parameter once its gradient is final and nothing of the pass reads it any
+   more), so there is no separate optimiser launch; theta, grad, m, v, step
+   and loss4 end up bit-identical to the two separate calls (loss4 and grad
+   are those of the parameters before the update).  u, dloss, ws, ws_bytes
+   as for coolchic_backward (workspace CC_WS_BACKWARD); step, lr, beta1,
+   beta2, eps as for coolchic_adam_step.  theta must not alias img or u. */
+int coolchic_train_step(const cc_problem* p, const float* img, const float* u, float dloss, float* loss4,
+                        float* theta, float* grad, float* m, float* v, int32_t* step, float lr, float beta1,
+                        float beta2, float eps, void* ws, size_t ws_bytes, void* stream);
+
 /* Decoder-side parallel work once the latents are known (Section II
    "Decoding", upsampling then synthesis): yq [N_lat] integer-valued latents
    (used as given), xhat [3][H][W] output, not clamped.  p->quant and

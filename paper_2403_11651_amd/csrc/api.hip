@@ -38,7 +38,7 @@ struct Plan {
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
-  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], total;
+  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], tslot, total;
   int head_grid;  // tiles of the 1x1-layer backward
   int n_head;     // 1x1-layer parameters (W1, b1, W2, b2)
 };
@@ -149,6 +149,7 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
     P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
     for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * P->ups_chunks[s] * 2 * UPS_K);
+    P->tslot = take(cur, 1);  // the fused Adam's step number, passed from the side combine to the final one
   }
   P->total = cur;
   return CC_OK;
@@ -421,9 +422,40 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   build(b->comb_main, &b->comb_main_grid, true);
 }
 
-int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
-                      const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
-                      float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace cc {
+namespace {
+// Adam fused into the two combine launches of a backward pass, for the
+// packed vectors theta = [y | arm_w | ups_w | syn_w] with grad, m, v laid out
+// alike: every gradient the combines finalise is applied to its parameter
+// there (level 0 of y and the ARM and synthesis weights in the side combine,
+// once nothing of the pass reads them any more; levels 1.. of y and the taps
+// in the final one, which advances the step counter).
+struct FusedAdam {
+  float *theta, *grad, *m, *v;
+  int32_t* step;
+  float lr, beta1, beta2, eps;
+};
+
+void fuse_adam(const FusedAdam& f, CombineArgs& ca, bool last, int32_t* t_slot) {
+  ca.adam.on = 1;
+  ca.adam.last = last ? 1 : 0;
+  ca.adam.step = f.step;
+  ca.adam.t_slot = t_slot;
+  ca.adam.lr = f.lr; ca.adam.beta1 = f.beta1; ca.adam.beta2 = f.beta2; ca.adam.eps = f.eps;
+  for (int k = 0; k < ca.nseg; ++k) {
+    RedSeg& S = ca.seg[k];
+    const ptrdiff_t o = S.dst - f.grad;
+    S.th = f.theta + o; S.m = f.m + o; S.v = f.v + o;
+  }
+  const ptrdiff_t o = ca.fold.g_y - f.grad;
+  ca.fold.th = f.theta + o; ca.fold.m = f.m + o; ca.fold.v = f.v + o;
+}
+
+int backward_impl(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
+                  const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
+                  float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream, const FusedAdam* fused) {
   Plan P;
   int rc = make_plan(p, CC_WS_BACKWARD, &P);
   if (rc) return rc;
@@ -439,6 +471,11 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   const int L = P.geo.L;
   static thread_local BwdSet b;
   build_backward(p, P, (float*)ws, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, g_y, g_arm, g_ups, g_syn, &b);
+  if (fused) {
+    int32_t* t_slot = (int32_t*)((float*)ws + P.tslot);
+    fuse_adam(*fused, b.comb_side, false, t_slot);
+    fuse_adam(*fused, b.comb_main, true, t_slot);
+  }
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side* sd = nullptr;
   if ((rc = side_for_current_device(&sd))) return rc;
@@ -462,6 +499,33 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
   if ((rc = join_from(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_main_grid, 256, &b.comb_main, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+int coolchic_backward(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
+                      const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
+                      float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream) {
+  return backward_impl(p, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, g_y, g_arm, g_ups, g_syn, ws, ws_bytes,
+                       stream, nullptr);
+}
+
+int coolchic_train_step(const cc_problem* p, const float* img, const float* u, float dloss, float* loss4,
+                        float* theta, float* grad, float* m, float* v, int32_t* step, float lr, float beta1,
+                        float beta2, float eps, void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !theta || !grad || !m || !v || !step) return CC_EINVAL;
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return CC_EINVAL;
+  int64_t na = 0, nu = 0, ns = 0;
+  if (coolchic_param_count(&p->arch, &na, &nu, &ns) <= 0) return CC_EUNSUPPORTED;
+  const int64_t ny = coolchic_latent_count(p);
+  if (ny <= 0) return CC_EINVAL;
+  const FusedAdam f{theta, grad, m, v, step, lr, beta1, beta2, eps};
+  return backward_impl(p, img, theta, u, theta + ny, theta + ny + na, theta + ny + na + nu, dloss, loss4, grad,
+                       grad + ny, grad + ny + na, grad + ny + na + nu, ws, ws_bytes, stream, &f);
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ struct FoldArgs {
   const float* gext;
   float* g_y;
   int q0, q1;          // the latents [q0, q1) of the packed pyramid
+  float *th, *m, *v;   // fused Adam: the latents and their moments (indexed like g_y)
 };
 
 
@@ -124,6 +125,7 @@ struct RedSeg {
   int rows, cols, ld;
   int cpb;             // columns per block: 16 (16 row groups) or 1 (256 row groups)
   float* dst;          // [cols]
+  float *th, *m, *v;   // fused Adam: the parameters of the columns and their moments, or null
 };
 struct FinalArgs {
   const float* rpart; int nr;    // rate partials (bits)
@@ -149,6 +151,17 @@ struct CombineArgs {
   float* bad;          // a block with a non-finite result stores 1 here (never 0)
   int loss_block;
   FinalArgs fin;
+  // Adam fused into the launch (on = 1): each final gradient value is
+  // applied to its parameter at once.  The first of the pass's two launches
+  // (last = 0) takes t = step[0] + 1 and its block 0 stores t in *t_slot; the
+  // last one (last = 1) reads t there and its block 0 stores it in step[0]
+  // (none of its blocks reads step[0], so no completion count is needed)
+  struct {
+    int on, last;
+    int32_t* step;
+    int32_t* t_slot;
+    float lr, beta1, beta2, eps;
+  } adam;
 };
 __global__ void combine_kernel(CombineArgs a);
 __global__ void combine_kernel_batch(const CombineArgs* d, const WorkItem* w);

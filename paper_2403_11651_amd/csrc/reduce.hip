@@ -6,10 +6,27 @@
 
 namespace cc {
 
+// Adam (Kingma & Ba) on one value with the bias corrections k1 = 1 / (1 -
+// beta1^t), k2 = 1 / (1 - beta2^t); every kernel that updates parameters
+// uses these two functions, so fused and separate updates agree bit for bit.
+__device__ __forceinline__ void adam_coeffs(float beta1, float beta2, int t, float& k1, float& k2) {
+  k1 = 1.0f / (1.0f - powf(beta1, (float)t));
+  k2 = 1.0f / (1.0f - powf(beta2, (float)t));
+}
+__device__ __forceinline__ void adam_apply(float lr, float beta1, float beta2, float eps, float k1, float k2,
+                                           float& th, float g, float& m, float& v) {
+  // explicit FMAs: the rounding does not depend on how the caller inlines it
+  m = __builtin_fmaf(beta1, m, (1.0f - beta1) * g);
+  v = __builtin_fmaf(beta2, v, (1.0f - beta2) * g * g);
+  th = __builtin_fmaf(-lr, (m * k1) / (sqrtf(v * k2) + eps), th);
+}
+
 // g_y[q] += sum of the extended-frame gradients of every ARM tile whose frame
 // contains latent q (own tile, left / right neighbours, and the three tiles of
-// the next tile row), in fixed order.
-__device__ bool arm_fold_one(const FoldArgs& a, int q) {
+// the next tile row), in fixed order; with the fused Adam, the latent is then
+// updated from that gradient.
+template <typename AD>
+__device__ bool arm_fold_one(const FoldArgs& a, int q, const AD& ad, float k1, float k2) {
   if (q >= a.q1) return true;
   int l = 0;
   while (l + 1 < a.geo.L && q >= a.geo.loff[l + 1]) ++l;
@@ -29,11 +46,17 @@ __device__ bool arm_fold_one(const FoldArgs& a, int q) {
     f[k] = ok ? a.gext[(size_t)tile * ARM_EXT + fa * ARM_EW + fb] : 0.0f;
   }
   const float gy = a.g_y[q];
+  float th = 0.0f, m = 0.0f, vv = 0.0f;
+  if (ad.on) { th = a.th[q]; m = a.m[q]; vv = a.v[q]; }
   float G = 0.0f;
 #pragma unroll
   for (int k = 0; k < 6; ++k) G += f[k];
   const float v = gy + G;
   a.g_y[q] = v;
+  if (ad.on) {
+    adam_apply(ad.lr, ad.beta1, ad.beta2, ad.eps, k1, k2, th, v, m, vv);
+    a.th[q] = th; a.m[q] = m; a.v[q] = vv;
+  }
   return finitef(v);
 }
 
@@ -93,10 +116,16 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
     finalize_body(a.fin);
     return;
   }
+  float k1 = 0.0f, k2 = 0.0f;
+  if (a.adam.on) {
+    const int t = a.adam.last ? *a.adam.t_slot : a.adam.step[0] + 1;
+    adam_coeffs(a.adam.beta1, a.adam.beta2, t, k1, k2);
+    if (bid == 0 && tid == 0) *(a.adam.last ? a.adam.step : a.adam.t_slot) = t;
+  }
   const int n_red = a.block_start[a.nseg];
   bool bad = false;
   if (bid >= n_red) {
-    bad = !arm_fold_one(a.fold, a.fold.q0 + (bid - n_red) * 256 + tid);
+    bad = !arm_fold_one(a.fold, a.fold.q0 + (bid - n_red) * 256 + tid, a.adam, k1, k2);
   } else {
     int sg = 0;
     while (sg + 1 < a.nseg && bid >= a.block_start[sg + 1]) ++sg;
@@ -119,6 +148,11 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
       const float v = s_p[cl];
       S.dst[col] = v;
       bad = !finitef(v);
+      if (a.adam.on && S.th) {
+        float th = S.th[col], m = S.m[col], vv = S.v[col];
+        adam_apply(a.adam.lr, a.adam.beta1, a.adam.beta2, a.adam.eps, k1, k2, th, v, m, vv);
+        S.th[col] = th; S.m[col] = m; S.v[col] = vv;
+      }
     }
   }
   const bool any = __syncthreads_or(bad);
@@ -143,16 +177,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs a) { finalize_b
 // and are read and written four values at a time.
 __device__ __forceinline__ void adam_one(const AdamArgs& a, float k1, float k2, float& th, float g, float& m,
                                          float& v) {
-  m = a.beta1 * m + (1.0f - a.beta1) * g;
-  v = a.beta2 * v + (1.0f - a.beta2) * g * g;
-  th -= a.lr * (m * k1) / (sqrtf(v * k2) + a.eps);
+  adam_apply(a.lr, a.beta1, a.beta2, a.eps, k1, k2, th, g, m, v);
 }
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   const int t = a.step[0] + 1;
-  const float k1 = 1.0f / (1.0f - powf(a.beta1, (float)t));
-  const float k2 = 1.0f / (1.0f - powf(a.beta2, (float)t));
+  float k1, k2;
+  adam_coeffs(a.beta1, a.beta2, t, k1, k2);
   const int64_t stride = (int64_t)gridDim.x * 256, first = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t done = 0;
   if (VEC) {

@@ -161,3 +161,16 @@ def test_timing_event_null_arguments(B):
     assert B.lib.coolchic_timing_event_elapsed(None, d, ctypes.byref(ms)) == -1
     assert B.lib.coolchic_timing_event_elapsed(d, d, None) == -1
     assert B.lib.coolchic_timing_event_destroy(None) == -1
+
+
+def test_train_step_rejects_invalid_arguments(B):
+    p = B.Problem(64, 64, B.LOW)
+    pc = p.c()
+    d = ctypes.c_void_p(0x1000)
+    need = B.workspace_bytes(p, 1)
+    args = lambda theta, b1: (ctypes.byref(pc), d, None, ctypes.c_float(1.0), d, theta, d, d, d, d,
+                              ctypes.c_float(0.01), ctypes.c_float(b1), ctypes.c_float(0.999), ctypes.c_float(1e-8),
+                              d, need, None)
+    assert B.lib.coolchic_train_step(*args(None, 0.9)) == -1     # null theta
+    assert B.lib.coolchic_train_step(*args(d, 1.0)) == -1        # beta1 outside [0, 1)
+    assert B.lib.coolchic_train_step(None, *args(d, 0.9)[1:]) == -1

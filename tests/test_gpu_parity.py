@@ -223,3 +223,41 @@ def test_stage_timing_events(B):
         assert e0.elapsed_ms(e1) > 0.0
         for k in ref:
             assert np.array_equal(out[k], ref[k]), (stage, k)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_noise", "full"])
+def test_train_step_matches_backward_then_adam(B, name):
+    """coolchic_train_step (Adam fused into the gradient reductions) against
+    coolchic_backward followed by coolchic_adam_step, over two iterations:
+    parameters, moments, gradients, loss and step counter bit for bit."""
+    c = CS.full() if name == "full" else CS.tiny()
+    if name == "tiny_noise":
+        c.u = np.random.default_rng(11).uniform(-0.5, 0.5, c.y.size).astype(np.float32)
+    p = _problem(B, c)
+    n = CS.n_latents(c.H, c.W, c.arch[0])
+    na, nu, ns = CS.sizes(c.arch)
+    theta0 = np.concatenate([c.y, c.arm, c.ups, c.syn]).astype(np.float32)
+    img, u = _dev(c.img), _dev(c.u)
+    runs = []
+    for fused in (False, True):
+        th = torch.from_numpy(theta0.copy()).cuda()
+        g = torch.full_like(th, float("nan"))
+        m = torch.zeros_like(th)
+        v = torch.zeros_like(th)
+        step = torch.zeros(2, dtype=torch.int32, device="cuda")
+        loss4 = torch.zeros(4, device="cuda")
+        losses = []
+        for _ in range(2):
+            if fused:
+                B.coolchic_train_step(p, img, u, 1.0, loss4, th, g, m, v, step)
+            else:
+                B.coolchic_backward(p, img, th[:n], u, th[n:n + na], th[n + na:n + na + nu], th[n + na + nu:], 1.0,
+                                    loss4, g[:n], g[n:n + na], g[n + na:n + na + nu], g[n + na + nu:])
+                B.coolchic_adam_step(th, g, m, v, step)
+            losses.append(loss4.clone())
+        torch.cuda.synchronize()
+        runs.append([t.cpu().numpy() for t in (th, g, m, v, step, *losses)])
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert np.array_equal(a, b), (name, k)
+    assert runs[1][4].tolist() == [2, 0]
+    assert not np.array_equal(runs[1][0], theta0)
