@@ -15,7 +15,7 @@ namespace cc {
 namespace {
 
 constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
-constexpr int MAX_GRID = 1024;
+constexpr int MAX_GRID = 1280;
 // Default ARM grid: the ARM launch runs beside the head backward and the
 // upsampling-adjoint launches, and each of its work-groups holds ~78 KB of
 // LDS; 384 work-groups (1.5 per CU of the 256-CU MI355X) leave part of the

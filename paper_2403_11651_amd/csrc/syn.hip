@@ -872,12 +872,14 @@ __global__ __launch_bounds__(SYN_THREADS) void syn_res_fwd_kernel_batch(const Sy
   const WorkItem it = w[blockIdx.x];
   syn_res_fwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
 }
+// five waves per SIMD (at most 96 VGPRs, no spills): with 30 KB of LDS per
+// work-group, five work-groups share a CU
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS, 3) void syn_bwd_kernel(SynArgs a) {
+__global__ __launch_bounds__(SYN_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void syn_bwd_kernel(SynArgs a) {
   syn_bwd_body<HS, NRES>(a, blockIdx.x, gridDim.x);
 }
 template <int HS, int NRES>
-__global__ __launch_bounds__(SYN_THREADS, 3) void syn_bwd_kernel_batch(const SynArgs* __restrict__ d,
+__global__ __launch_bounds__(SYN_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void syn_bwd_kernel_batch(const SynArgs* __restrict__ d,
                                                                        const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
   syn_bwd_body<HS, NRES>(d[it.img], it.bid, it.nblk);
