@@ -16,6 +16,7 @@ namespace {
 
 constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
 constexpr int MAX_GRID = 1280;
+constexpr int RED_CPB = 16;  // gradient columns per combine work-group (16 row groups each)
 // Default ARM grid: the ARM launch runs beside the head backward and the
 // upsampling-adjoint launches, and each of its work-groups holds ~78 KB of
 // LDS; 384 work-groups (1.5 per CU of the 256-CU MI355X) leave part of the
@@ -125,13 +126,13 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   P->fold_grid1 = cdiv(g.n_lat - P->fold_split, 256);
   // column reductions, one column per block (256 row groups: every column
   // has hundreds to thousands of partial rows)
-  P->red_blocks_arm = (int)P->n_arm;
+  P->red_blocks_arm = cdiv((int)P->n_arm, RED_CPB);
   P->n_head = P->Hs * L + 4 * P->Hs + 3;
   P->head_grid = cdiv(p->H, SYN_HD) * cdiv(p->W, SYN_HD);
-  P->red_blocks_syn = P->nres * 84 + P->n_head;
+  P->red_blocks_syn = cdiv(P->nres * 84, RED_CPB) + cdiv(P->n_head, RED_CPB);
   P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
   for (int s = 0; s + 1 < L; ++s) {
-    P->red_blocks_ups[s] = 2 * UPS_K;
+    P->red_blocks_ups[s] = cdiv(2 * UPS_K, RED_CPB);
     P->red_grid += P->red_blocks_ups[s];
   }
 
@@ -388,9 +389,10 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
     auto add = [&](const float* src, int rows, int cols, float* dst) {
-      ca.seg[ns] = RedSeg{src, rows, cols, cols, 1, dst};
+      const int cpb = RED_CPB;
+      ca.seg[ns] = RedSeg{src, rows, cols, cols, cpb, dst};
       ca.block_start[ns] = blk;
-      blk += cols;
+      blk += cdiv(cols, cpb);
       ++ns;
     };
     if (!final_part) {
