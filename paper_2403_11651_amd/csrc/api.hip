@@ -597,7 +597,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     // the combine launches: reduction and fold blocks, and the loss block
     items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid0 +
              P.fold_grid1 + 1;
-    items += cdiv(P.geo.lh[1], UF_T) * cdiv(P.geo.lw[1], UF_T);
+    items += cdiv(P.geo.lh[1], UF_T_BATCH) * cdiv(P.geo.lw[1], UF_T_BATCH);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
   blk(sizeof(WorkItem) * items + 256 * (L + 8));
@@ -671,7 +671,9 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main;
     for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
     for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
-    for (int i = 0; i < b->upf_grid; ++i) w_upf.push_back(WorkItem{k, i, b->upf_grid, 0});
+    // the batched upsampling forward takes UF_T_BATCH tiles
+    const int upf = b->upf_grid ? cdiv(P.geo.lh[1], UF_T_BATCH) * cdiv(P.geo.lw[1], UF_T_BATCH) : 0;
+    for (int i = 0; i < upf; ++i) w_upf.push_back(WorkItem{k, i, upf, 0});
     for (int i = 0; i < b->t0_grid; ++i) w_t0.push_back(WorkItem{k, i, b->t0_grid, 0});
     for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
     for (int i = 0; i < P.head_grid; ++i) w_head.push_back(WorkItem{k, i, P.head_grid, 0});

@@ -48,7 +48,10 @@ struct FoldArgs {
 
 
 // ---------------------------------------------------------------- upsampling
-constexpr int UF_T = 16;  // level-1 tile side of ups_fwd_kernel (one work-group per tile)
+// level-1 tile side of the upsampling forward (one work-group per tile):
+// small tiles fill the device for one image; a batch has work-groups to
+// spare and keeps the halo recompute of larger tiles low
+constexpr int UF_T = 16, UF_T_BATCH = 32;
 struct UpsFwdArgs {
   Geo geo;
   const float* y;

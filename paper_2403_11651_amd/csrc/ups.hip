@@ -14,29 +14,30 @@
 
 namespace cc {
 
-// All steps s = L-2 .. 1 in one launch.  A work-group owns a UF_T x UF_T tile
+// All steps s = L-2 .. 1 in one launch.  A work-group owns a T x T tile
 // of level 1 and works from the coarsest level down: the region of
 // stack_{s+1} that U_s needs for the rows / columns [a, b) of level s is
 // [a/2 - 2, (b-1)/2 + 3) clipped to the grid (every clamped tap index falls in
-// it; at most UF_T/2 + 4 rows / columns for levels >= 2), so each work-group
+// it; at most T/2 + 4 rows / columns for levels >= 2), so each work-group
 // recomputes, in LDS, the small coarse regions its tile depends on.  U_1 is
 // written for the tile; for s >= 2 the work-group writes the part of U_s that
 // lies under its tile, so every output is written exactly once.
-constexpr int UF_R = UF_T / 2 + 4;  // largest region side at levels >= 2
-// every level s <= L-2 keeps at least one row / column of the tile to write
-static_assert((UF_T >> (MAXL - 3)) >= 1 && UF_T % 2 == 0, "ups_fwd tile too small");
 constexpr int UF_CH = MAXL - 1;  // channels of stack_2 at most (L - 2 < 6)
 
+template <int T>
 __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid) {
+  constexpr int UF_R = T / 2 + 4;  // largest region side at levels >= 2
+  // every level s <= L-2 keeps at least one row / column of the tile to write
+  static_assert((T >> (MAXL - 3)) >= 1 && T % 2 == 0, "ups_fwd tile too small");
   __shared__ float s_st[2][UF_CH * UF_R * UF_R];
   constexpr int NQ = (UF_R * UF_R + 255) / 256;  // region values per thread at levels >= 2
   const int L = a.geo.L, tid = threadIdx.x;
   const int h1 = a.geo.lh[1], w1 = a.geo.lw[1];
-  const int ntx = (w1 + UF_T - 1) / UF_T;
-  const int r0 = (bid / ntx) * UF_T, c0 = (bid % ntx) * UF_T;
+  const int ntx = (w1 + T - 1) / T;
+  const int r0 = (bid / ntx) * T, c0 = (bid % ntx) * T;
   // regions [ra, rb) x [ca, cb) per level
   int ra[MAXL], rb[MAXL], ca[MAXL], cb[MAXL];
-  ra[1] = r0; rb[1] = min(r0 + UF_T, h1); ca[1] = c0; cb[1] = min(c0 + UF_T, w1);
+  ra[1] = r0; rb[1] = min(r0 + T, h1); ca[1] = c0; cb[1] = min(c0 + T, w1);
   for (int l = 1; l + 1 < L; ++l) {
     ra[l + 1] = max(0, (ra[l] >> 1) - 2); rb[l + 1] = min(a.geo.lh[l + 1], ((rb[l] - 1) >> 1) + 3);
     ca[l + 1] = max(0, (ca[l] >> 1) - 2); cb[l + 1] = min(a.geo.lw[l + 1], ((cb[l] - 1) >> 1) + 3);
@@ -82,8 +83,8 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
     const int nr = rb[s] - ra[s], nc = cb[s] - ca[s];
     const int hi = a.geo.lh[s + 1], wi = a.geo.lw[s + 1], ws = a.geo.lw[s];
     // the part of level s under this tile (written to global for s >= 2)
-    const int oa = r0 >> (s - 1), ob = min((r0 + UF_T) >> (s - 1), a.geo.lh[s]);
-    const int oc = c0 >> (s - 1), od = min((c0 + UF_T) >> (s - 1), ws);
+    const int oa = r0 >> (s - 1), ob = min((r0 + T) >> (s - 1), a.geo.lh[s]);
+    const int oc = c0 >> (s - 1), od = min((c0 + T) >> (s - 1), ws);
     float* up = a.up_out[s];
     const size_t plane = (size_t)a.geo.lh[s] * ws;
     for (int p = tid; p < nr * nc; p += 256) {
@@ -264,11 +265,11 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
   }
 }
 
-__global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) { ups_fwd_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) { ups_fwd_body<UF_T>(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void ups_fwd_kernel_batch(const UpsFwdArgs* __restrict__ d,
                                                             const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
-  ups_fwd_body(d[it.img], it.bid);
+  ups_fwd_body<UF_T_BATCH>(d[it.img], it.bid);
 }
 __global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
   ups_bwd_body(a, blockIdx.x, gridDim.x, blockIdx.y);
