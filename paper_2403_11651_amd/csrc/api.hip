@@ -17,6 +17,10 @@ namespace {
 constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
 constexpr int MAX_GRID = 1280;
 constexpr int RED_CPB = 16;  // gradient columns per combine work-group (16 row groups each)
+// a batch's side combine starts after the level-0 upsampling adjoint and also
+// folds level 1 (one image: after the head backward, level 0 only)
+constexpr int BATCH_SIDE_LEVELS = 2;
+static_assert(BATCH_SIDE_LEVELS == 1 || BATCH_SIDE_LEVELS == 2, "side combine after the head or step 0");
 // Default ARM grid: the ARM launch runs beside the head backward and the
 // upsampling-adjoint launches, and each of its work-groups holds ~78 KB of
 // LDS; 384 work-groups (1.5 per CU of the 256-CU MI355X) leave part of the
@@ -81,7 +85,7 @@ size_t take(size_t& cur, size_t n) {
   return at;
 }
 
-int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn_grid = 0) {
+int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn_grid = 0, int side_levels = 1) {
   int rc = check_problem(p);
   if (rc) return rc;
   std::memset(P, 0, sizeof(*P));
@@ -119,9 +123,10 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->ups_cpb[s] = P->ups_grid[s] >= 256 ? L - 1 - s : 1;
     P->ups_chunks[s] = cdiv(L - 1 - s, P->ups_cpb[s]);
   }
-  // the ARM context fold: level 0 (final once the head backward has run) and
-  // levels 1.. (final after the upsampling adjoint)
-  P->fold_split = L > 1 ? g.loff[1] : g.n_lat;
+  // the ARM context fold of the side combine takes the first side_levels
+  // levels (level 0 is final once the head backward has run, level 1 after
+  // the level-0 upsampling adjoint); the final combine folds the others
+  P->fold_split = L > side_levels ? g.loff[side_levels] : g.n_lat;
   P->fold_grid0 = cdiv(P->fold_split, 256);
   P->fold_grid1 = cdiv(g.n_lat - P->fold_split, 256);
   // column reductions, one column per block (256 row groups: every column
@@ -382,10 +387,11 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   fa.lambda = p->lambda; fa.inv_hw = 1.0f / HW; fa.inv_3hw = 1.0f / (3.0f * HW);
   fa.have_rate = 1; fa.have_sse = 1; fa.sticky = 1; fa.loss4 = loss4;
   // two combine launches: the side one (after the ARM and the head backward,
-  // beside the upsampling adjoint) sums the ARM and synthesis weight-gradient
-  // partials, folds the ARM context gradients of level 0 into g_y and
-  // evaluates the loss in one more block; the final one sums the upsampling
-  // tap partials and folds the context gradients of the other levels
+  // or for a batch the level-0 upsampling adjoint, beside the rest of the
+  // adjoint) sums the ARM and synthesis weight-gradient partials, folds the
+  // ARM context gradients of the first levels into g_y and evaluates the
+  // loss in one more block; the final one sums the upsampling tap partials
+  // and folds the context gradients of the other levels
   auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
     auto add = [&](const float* src, int rows, int cols, float* dst) {
@@ -490,6 +496,7 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   if ((rc = fork_to(sd, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
+  // level 0 of g_y is final: the side combine may start
   if ((rc = side_waits(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, sd->stream))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
@@ -563,7 +570,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   long long tiles_arm = 0, tiles_syn = 0;
   plans.resize(n);
   for (int k = 0; k < n; ++k) {
-    int rc = make_plan(&probs[k], CC_WS_BACKWARD, &plans[k]);
+    int rc = make_plan(&probs[k], CC_WS_BACKWARD, &plans[k], 0, 0, BATCH_SIDE_LEVELS);
     if (rc) return rc;
     const cc_arch &a = probs[k].arch, &a0 = probs[0].arch;
     if (std::memcmp(&a, &a0, sizeof(cc_arch)) || probs[k].quant != probs[0].quant) return CC_EINVAL;
@@ -576,7 +583,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   for (int k = 0; k < n; ++k) {
     const int ga = share(ta, plans[k].tiles.n_tiles, tiles_arm, 4096);
     const int gs = share(ts, plans[k].syn_tiles, tiles_syn, 4096);
-    make_plan(&probs[k], CC_WS_BACKWARD, &plans[k], ga, gs);
+    make_plan(&probs[k], CC_WS_BACKWARD, &plans[k], ga, gs, BATCH_SIDE_LEVELS);
     img_off[k] = cur;
     cur += (plans[k].total * sizeof(float) + 255) / 256 * 256;
   }
@@ -755,18 +762,23 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
   }
   if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
-  if ((rc = side_waits(sd, st))) return rc;
-  if (B.n_comb_side > 0) {
+  // the side combine, once levels [0, BATCH_SIDE_LEVELS) of every g_y are
+  // final (level 0 after the head backward, level 1 after adjoint step 0)
+  auto side_combine = [&]() -> int {
+    int r = side_waits(sd, st);
+    if (r || B.n_comb_side <= 0) return r;
     void* descs = B.d_comb_side;
     void* work = B.w_comb_side;
     void* argv[] = {&descs, &work};
-    if (hipLaunchKernel((const void*)combine_kernel_batch, dim3(B.n_comb_side), dim3(256), argv, 0, sd->stream) !=
-        hipSuccess)
-      return CC_EHIP;
-  }
-  for (int s = 0; s + 1 < B.L; ++s)
+    return hipLaunchKernel((const void*)combine_kernel_batch, dim3(B.n_comb_side), dim3(256), argv, 0,
+                           sd->stream) == hipSuccess ? CC_OK : CC_EHIP;
+  };
+  if (BATCH_SIDE_LEVELS == 1 && (rc = side_combine())) return rc;
+  for (int s = 0; s + 1 < B.L; ++s) {
     if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
       return rc;
+    if (s == 0 && BATCH_SIDE_LEVELS == 2 && (rc = side_combine())) return rc;
+  }
   if ((rc = join_from(sd, st))) return rc;
   if ((rc = go(CC_STAGE_NONE, (const void*)combine_kernel_batch, B.n_comb_main, 256, B.d_comb_main, B.w_comb_main)))
     return rc;
