@@ -174,3 +174,6 @@ def test_train_step_rejects_invalid_arguments(B):
     assert B.lib.coolchic_train_step(*args(None, 0.9)) == -1     # null theta
     assert B.lib.coolchic_train_step(*args(d, 1.0)) == -1        # beta1 outside [0, 1)
     assert B.lib.coolchic_train_step(None, *args(d, 0.9)[1:]) == -1
+    small = list(args(d, 0.9))
+    small[15] = need - 4                                          # workspace too small
+    assert B.lib.coolchic_train_step(*small) == -3
