@@ -53,7 +53,8 @@ extern "C" {
 
 /* Decoder architecture (Table I notation). */
 typedef struct {
-  int32_t n_levels;   /* L, number of latent grids, 2..7 */
+  int32_t n_levels;   /* L, number of latent grids, 1..7 (1: no upsampling, no
+                         upsampling parameters; ups_w and g_ups may be NULL) */
   int32_t arm_ctx;    /* C, causal neighbours fed to the ARM: 8, 16 or 24 (Table I
                          widths); the C nearest causal positions of a 7x7
                          window, ties in raster order, zero outside the grid */

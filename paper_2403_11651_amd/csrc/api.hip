@@ -50,7 +50,7 @@ struct Plan {
 
 bool arch_ok(const cc_arch* a) {
   if (!a) return false;
-  if (a->n_levels < 2 || a->n_levels > MAXL) return false;
+  if (a->n_levels < 1 || a->n_levels > MAXL) return false;
   if (a->arm_ctx != 8 && a->arm_ctx != 16 && a->arm_ctx != 24) return false;
   if (a->arm_layers < 1 || a->arm_layers > 3) return false;
   if (a->ups_taps != UPS_K) return false;
@@ -297,7 +297,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   Plan P;
   int rc = make_plan(p, CC_WS_FORWARD, &P);
   if (rc) return rc;
-  if (!img || !y || !arm_w || !ups_w || !syn_w || !loss4 || !ws) return CC_EINVAL;
+  if (!img || !y || !arm_w || (!ups_w && P.n_ups) || !syn_w || !loss4 || !ws) return CC_EINVAL;
   if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   const void* armk = arm_kernel_for(P.C, P.NH, false, false);
@@ -417,7 +417,10 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
     if (final_part) {
       ca.fold.q0 = P.fold_split; ca.fold.q1 = P.geo.n_lat;
-      blk += P.fold_grid1;
+      // at least one block: with a single level (no taps, every latent
+      // folded by the side combine) block 0 still stores the fused Adam's
+      // step count, its fold range being empty
+      blk += std::max(P.fold_grid1, blk == 0 ? 1 : 0);
     } else {
       ca.fold.q0 = 0; ca.fold.q1 = P.fold_split;
       blk += P.fold_grid0;
@@ -467,7 +470,8 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   Plan P;
   int rc = make_plan(p, CC_WS_BACKWARD, &P);
   if (rc) return rc;
-  if (!img || !y || !arm_w || !ups_w || !syn_w || !loss4 || !g_y || !g_arm || !g_ups || !g_syn || !ws)
+  if (!img || !y || !arm_w || (!ups_w && P.n_ups) || !syn_w || !loss4 || !g_y || !g_arm || (!g_ups && P.n_ups) ||
+      !g_syn || !ws)
     return CC_EINVAL;
   if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
@@ -642,8 +646,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   if (ws_bytes < total) return CC_EWORKSPACE;
   for (int k = 0; k < n; ++k) {
     const cc_image_io& q = io[k];
-    if (!q.img || !q.y || !q.arm_w || !q.ups_w || !q.syn_w || !q.loss4 || !q.g_y || !q.g_arm || !q.g_ups ||
-        !q.g_syn)
+    if (!q.img || !q.y || !q.arm_w || (!q.ups_w && plans[k].n_ups) || !q.syn_w || !q.loss4 || !q.g_y || !q.g_arm ||
+        (!q.g_ups && plans[k].n_ups) || !q.g_syn)
       return CC_EINVAL;
     if (probs[k].quant == CC_QUANT_NOISE && !q.u) return CC_EINVAL;
   }
@@ -795,7 +799,7 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   Plan P;
   int rc = make_plan(&q, CC_WS_DECODE, &P);
   if (rc) return rc;
-  if (!yq || !ups_w || !syn_w || !xhat || !ws) return CC_EINVAL;
+  if (!yq || (!ups_w && P.n_ups) || !syn_w || !xhat || !ws) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *resk = syn_res_fwd_kernel_for(P.Hs, P.nres, false);
   if (!t0k || !resk) return CC_EUNSUPPORTED;

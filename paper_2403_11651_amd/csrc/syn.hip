@@ -32,11 +32,12 @@ __device__ __forceinline__ void parity_taps(const float (&k8)[UPS_K], int odd, f
   for (int q = 0; q < 4; ++q) t[q] = odd ? k8[2 * q] : k8[2 * q + 1];
 }
 
+// (taps is null for a single latent level, which has no upsampling)
 __device__ __forceinline__ void load_taps(const float* __restrict__ taps, float (&kv)[UPS_K], float (&kh)[UPS_K]) {
 #pragma unroll
   for (int k = 0; k < UPS_K; ++k) {
-    kv[k] = taps[k];
-    kh[k] = taps[UPS_K + k];
+    kv[k] = taps ? taps[k] : 0.0f;
+    kh[k] = taps ? taps[UPS_K + k] : 0.0f;
   }
 }
 

@@ -73,5 +73,8 @@ def small_variants():
         make("L2_8x24", 8, 24, (2, 8, 3, 8, 8, 1), seeds=(28, 29, 30, 31), n_blobs=3),
         make("L7_128x64_c24h3", 128, 64, (7, 24, 3, 8, 48, 1), seeds=(32, 33, 34, 35)),
         make("L4_40x72_c16", 40, 72, (4, 16, 2, 8, 32, 2), seeds=(36, 37, 38, 39), n_blobs=5),
+        # a single latent grid: no upsampling, the synthesis sees y_hat_0 alone
+        make("L1_16x40", 16, 40, (1, 8, 2, 8, 16, 1), seeds=(40, 41, 42, 43), n_blobs=3),
+        make("L1_72x136_c24_noise", 72, 136, (1, 24, 2, 8, 40, 2), seeds=(44, 45, 46, 47), n_blobs=6, noise=True),
     ]
     return out

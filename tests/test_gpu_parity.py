@@ -129,7 +129,7 @@ def test_tiny_noise_mode(B):
     check_backward(B, c)
 
 
-@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("idx", range(len(CS.small_variants())))
 def test_small_variants(B, idx):
     c = CS.small_variants()[idx]
     check_forward(B, c)
@@ -148,8 +148,35 @@ def test_full_768x512(B):
     check_backward(B, c)
 
 
-def test_decode_synth_matches_oracle(B):
-    c = CS.low()
+def test_full_768x512_noise_mode(B):
+    """The full-complexity workload with the additive-noise proxy."""
+    c = CS.make("full768x512_noise", 512, 768, CS.FULL, seeds=(10, 11, 12, 13), n_blobs=200, noise=True)
+    check_forward(B, c)
+    check_backward(B, c)
+
+
+@pytest.mark.parametrize("which", ["low", "full"])
+def test_rate_error_conditioning_768x512(B, which):
+    """Measures, over every latent of the 768x512 workloads, the per-latent
+    rate error against the oracle divided by |dr/dmu| + |dr/ds| (the oracle's
+    derivatives): the size of the FP32 error in (mu, s) that the rate error
+    corresponds to.  It must stay below the 1e-5 the rate bar grants."""
+    c = CS.low() if which == "low" else CS.full()
+    out = gpu_forward(B, c)
+    ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=c.u)
+    _, gmu, gs = O.rate_grads(ref["yq"], ref["mu"], ref["s"])
+    err = np.abs(out["rate"] - ref["rate"])
+    ratio = err / (np.abs(gmu) + np.abs(gs))
+    k = int(np.argmax(ratio))
+    print(f"{which}: max |dr| / (|dr/dmu| + |dr/ds|) = {ratio[k]:.3e} at latent {k} (|dr| {err[k]:.3e} bits, "
+          f"b {np.exp(np.clip(ref['s'][k], O.S_MIN, O.S_MAX)):.4g}); max |dr| {err.max():.3e} bits; "
+          f"latents with b < 0.1: {int(np.sum(np.abs(gmu) >= 15.0))}")
+    assert ratio[k] < 1e-5
+
+
+@pytest.mark.parametrize("which", ["low", "full"])
+def test_decode_synth_matches_oracle(B, which):
+    c = CS.low() if which == "low" else CS.full()
     p = _problem(B, c)
     yq = np.rint(c.y.astype(np.float64)).astype(np.float32)
     xhat = torch.zeros(3 * c.H * c.W, device="cuda")
@@ -225,12 +252,12 @@ def test_stage_timing_events(B):
             assert np.array_equal(out[k], ref[k]), (stage, k)
 
 
-@pytest.mark.parametrize("name", ["tiny", "tiny_noise", "full"])
+@pytest.mark.parametrize("name", ["tiny", "tiny_noise", "full", "single_level"])
 def test_train_step_matches_backward_then_adam(B, name):
     """coolchic_train_step (Adam fused into the gradient reductions) against
     coolchic_backward followed by coolchic_adam_step, over two iterations:
     parameters, moments, gradients, loss and step counter bit for bit."""
-    c = CS.full() if name == "full" else CS.tiny()
+    c = {"full": CS.full, "single_level": lambda: CS.small_variants()[6]}.get(name, CS.tiny)()
     if name == "tiny_noise":
         c.u = np.random.default_rng(11).uniform(-0.5, 0.5, c.y.size).astype(np.float32)
     p = _problem(B, c)

@@ -3,7 +3,8 @@ the FP64 oracle with the same rounding points.
 
 Bars: predicted latents and decoder parameters within 1e-4 relative in the
 2-norm and 1e-3 * max|ref| element by element; loss within 1e-5 relative;
-every gradient block within 1e-3 relative in the 2-norm.  The FP32
+every gradient block within 1e-3 relative in the 2-norm and 1e-3 * max|g|
+element by element.  The FP32
 accumulation differs from the FP64 oracle only by rounding, except where a
 feature value or feature gradient lies within that rounding of a bfloat16
 rounding boundary: such an element rounds the other way (one bfloat16 step,
@@ -62,6 +63,8 @@ def close(name, got, ref, rel=1e-4, elem=1e-3):
     got = np.asarray(got, np.float64)
     assert np.all(np.isfinite(got)), name
     nrm = np.linalg.norm(ref)
+    print(f"{name}: 2-norm rel {np.linalg.norm(got - ref) / nrm:.2e}, max-abs / max|ref| "
+          f"{np.max(np.abs(got - ref)) / np.max(np.abs(ref)):.2e}")
     assert np.linalg.norm(got - ref) <= rel * nrm, (name, np.linalg.norm(got - ref) / nrm)
     assert np.max(np.abs(got - ref)) <= elem * np.max(np.abs(ref)), (name, np.max(np.abs(got - ref)))
 
@@ -103,7 +106,7 @@ def test_warm_backward_matches_oracle(B, H, W, n, seed):
     assert abs(l4[0] - L) <= 1e-5 * abs(L), (l4, L)
     assert abs(l4[1] + l4[2] - l4[0]) <= 1e-6 * abs(l4[0])
     for name, lo, hi in blocks():
-        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-2)
+        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-3)
 
 
 def test_warm_full_size_matches_oracle(B):
@@ -121,7 +124,7 @@ def test_warm_full_size_matches_oracle(B):
                           ths[0].astype(np.float64))
     assert abs(l4[0] - L) <= 1e-5 * abs(L)
     for name, lo, hi in blocks():
-        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-2)
+        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-3)
 
 
 def test_warm_backward_deterministic(B):
@@ -186,4 +189,4 @@ def test_warm_backward_grad_matches_oracle(B, H, W, n, seed):
     gref = sum(WS.backward_from_grads(x.astype(np.float64), net.astype(np.float64), N_THETA,
                                       gy[i].astype(np.float64), gth[i].astype(np.float64)) for i, x in enumerate(xs))
     for name, lo, hi in blocks():
-        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-2)
+        close(name, g[lo:hi], gref[lo:hi], rel=1e-3, elem=1e-3)

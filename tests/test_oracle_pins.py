@@ -67,6 +67,19 @@ def test_context_sets():
     assert d2 == [1, 1, 2, 2, 4, 4, 5, 5]
 
 
+def test_context_set_16_explicit():
+    """C = 16 (Table I's 1079 row): every causal position of the 7x7 window
+    within distance 3 (14 positions: squared distances 1, 2, 4, 5, 8, 9), then
+    two of the four positions at distance sqrt(10), (-3, -1), (-3, 1), (-1, -3)
+    and (-1, 3), taken in raster order: the two of row -3.  Written out by hand
+    in raster order."""
+    assert O.context_offsets(16) == [
+        (-3, -1), (-3, 0), (-3, 1),
+        (-2, -2), (-2, -1), (-2, 0), (-2, 1), (-2, 2),
+        (-1, -2), (-1, -1), (-1, 0), (-1, 1), (-1, 2),
+        (0, -3), (0, -2), (0, -1)]
+
+
 # --------------------------------------------------------------- Laplace rate
 def test_laplace_mass_sums_to_one():
     ks = np.arange(-200, 201, dtype=float)
@@ -500,3 +513,44 @@ def test_adam_first_steps_closed_form():
         th2, m, v = O.adam_step(th, g, m, v, t, lr=0.01)
         assert np.allclose(th2 - th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15)
         th = th2
+
+
+def test_adam_three_steps_by_hand():
+    """A scalar parameter at 0 with the gradients 1, -2, 1/2 and betas (0.9,
+    0.999), worked out by hand: m = 0.1, -0.11, -0.049; v = 0.001, 0.004999,
+    0.005244001; bias corrections 1 - 0.9^t = 0.1, 0.19, 0.271 and
+    1 - 0.999^t = 0.001, 0.001999, 0.002997001.  Swapped or wrong betas, or a
+    missing bias correction, change every step after the first."""
+    m_hand = [0.1, -0.11, -0.049]
+    v_hand = [0.001, 0.004999, 0.005244001]
+    c1 = [0.1, 0.19, 0.271]
+    c2 = [0.001, 0.001999, 0.002997001]
+    th, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    th_hand = 0.0
+    for t, g in enumerate((1.0, -2.0, 0.5), start=1):
+        th, m, v = O.adam_step(th, np.array([g]), m, v, t, lr=0.01)
+        th_hand -= 0.01 * (m_hand[t - 1] / c1[t - 1]) / (math.sqrt(v_hand[t - 1] / c2[t - 1]) + 1e-8)
+        assert abs(m[0] - m_hand[t - 1]) <= 1e-15
+        assert abs(v[0] - v_hand[t - 1]) <= 1e-15
+        assert abs(th[0] - th_hand) <= 1e-14, (t, th[0], th_hand)
+    assert abs(th[0] - (-0.01 + 0.01 * 0.5789473684 / 1.5813761018 + 0.01 * 0.1808118081 / 1.3227809719)) < 1e-9
+
+
+@pytest.mark.parametrize("betas", [(0.9, 0.999), (0.8, 0.95), (0.5, 0.9)])
+def test_adam_matches_torch_optim_varying_gradients(betas):
+    """torch.optim.Adam (a separate implementation of Kingma & Ba) over six
+    steps of gradients that change every step: parameters and both moments."""
+    rng = np.random.default_rng(5)
+    th0 = rng.normal(size=9)
+    p = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=0.01, betas=betas, eps=1e-8)
+    th, m, v = th0.copy(), np.zeros(9), np.zeros(9)
+    for t in range(1, 7):
+        g = rng.normal(size=9) * (1 + t)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        th, m, v = O.adam_step(th, g, m, v, t, lr=0.01, beta1=betas[0], beta2=betas[1])
+        st = opt.state[p]
+        assert np.allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-15), t
+        assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-13, atol=0), t
+        assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=0), t
