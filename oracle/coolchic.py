@@ -43,10 +43,11 @@ S_MIN = math.log(0.01)   # log-scale clamp of the Laplace scale b (reading, see 
 S_MAX = math.log(100.0)
 
 __all__ = [
-    "Arch", "TINY", "FULL", "LOW", "FD16", "param_sizes", "unpack", "pack",
+    "Arch", "TINY", "FULL", "LOW", "FD16", "TABLE1", "param_sizes", "unpack", "pack",
     "table1_param_count", "mac_per_pixel", "level_shapes", "split_levels",
     "quantise", "context_offsets", "gather_context", "arm_forward", "laplace_mass",
     "rate_bits", "rate_grads", "log_laplace_mass", "tconv1d", "tconv1d_adjoint", "upsample2x",
+    "tconv2d", "tconv2d_adjoint", "upsample_step",
     "upsample_pyramid", "conv3x3_replicate", "synthesis", "forward", "backward",
     "adam_step", "S_MIN", "S_MAX",
 ]
@@ -60,9 +61,13 @@ class Arch:
     arm_ctx    : C, ARM input width = number of causal neighbours; the hidden
                  LinR layers are C -> C (residual needs equal widths).
     arm_layers : number of hidden C-C-LinR layers before the C-2-Lin output.
-    ups_taps   : K, taps of each 1-D stride-2 transposed convolution.
+    ups_taps   : K, taps of each stride-2 transposed convolution (4 or 8).
     syn_hidden : width of the first 1x1 synthesis layer (L -> syn_hidden).
     syn_res    : number of 3-3-ConvR-3 residual 3x3 convolutions.
+    ups_shared : False: each upsampling step has its own separable kernel (a
+                 vertical and a horizontal K-tap filter); True: Table I's
+                 "1-1-TConv-K", one non-separable K x K kernel shared by every
+                 step (K*K parameters).
     """
     n_levels: int = 7
     arm_ctx: int = 24
@@ -70,8 +75,12 @@ class Arch:
     ups_taps: int = 8
     syn_hidden: int = 40
     syn_res: int = 2
+    ups_shared: bool = False
 
 
+# Table I's four decoders (300 / 545 / 1079 / 2300 MAC per pixel)
+TABLE1 = {300: Arch(7, 8, 1, 4, 8, 1, True), 545: Arch(7, 8, 2, 4, 16, 2, True),
+          1079: Arch(7, 16, 2, 4, 16, 2, True), 2300: Arch(7, 24, 2, 8, 40, 2, True)}
 TINY = Arch(7, 8, 2, 8, 16, 1)    # 64x64 small instance
 FULL = Arch(7, 24, 2, 8, 40, 2)   # Table I 2300 row with a separable per-level upsampler
 LOW = Arch(7, 8, 2, 8, 16, 1)     # low-complexity decoder
@@ -86,7 +95,7 @@ def param_sizes(arch: Arch):
     (Table I parameter counts), the upsampler has none."""
     C, L, Hs, K = arch.arm_ctx, arch.n_levels, arch.syn_hidden, arch.ups_taps
     n_arm = arch.arm_layers * (C * C + C) + 2 * C + 2
-    n_ups = (L - 1) * 2 * K
+    n_ups = K * K if arch.ups_shared else (L - 1) * 2 * K
     n_syn = Hs * L + Hs + 3 * Hs + 3 + arch.syn_res * (3 * 3 * 3 * 3 + 3)
     return n_arm, n_ups, n_syn
 
@@ -96,8 +105,9 @@ def unpack(arch: Arch, arm_w, ups_w, syn_w):
 
     ARM  : for each hidden layer (W [C][C] (out, in), b [C]); then Wo [2][C]
            (row 0 = mean, row 1 = log-scale) and bo [2].
-    UPS  : [L-1][2][K]; index s produces level s from level s+1; [0] holds the
-           vertical taps, [1] the horizontal taps.
+    UPS  : separable: [L-1][2][K]; index s produces level s from level s+1;
+           [0] holds the vertical taps, [1] the horizontal taps.  Shared:
+           [K][K] (ky, kx), one kernel for every step.
     SYN  : W1 [Hs][L], b1 [Hs], W2 [3][Hs], b2 [3]; per residual conv
            W [3][3][3][3] (out, in, ky, kx), b [3].
     """
@@ -113,7 +123,7 @@ def unpack(arch: Arch, arm_w, ups_w, syn_w):
         hidden.append((W, b))
     Wo = a[o:o + 2 * C].reshape(2, C); o += 2 * C
     bo = a[o:o + 2]; o += 2
-    ups = np.asarray(ups_w, dtype=np.float64).reshape(L - 1, 2, K)
+    ups = np.asarray(ups_w, dtype=np.float64).reshape((K, K) if arch.ups_shared else (L - 1, 2, K))
     s = np.asarray(syn_w, dtype=np.float64)
     o = 0
     W1 = s[o:o + Hs * L].reshape(Hs, L); o += Hs * L
@@ -371,6 +381,46 @@ def upsample2x(stack, v, h):
     return tconv1d(tconv1d(stack, v, axis=-2), h, axis=-1)
 
 
+def tconv2d(a, Wk):
+    """2-D stride-2 transposed convolution with one K x K kernel (Table I
+    "1-1-TConv-K"), applied to every channel of a [C][n_y][n_x]:
+    out[i, j] = sum over (ky, kx) with (i + p - ky) and (j + p - kx) even of
+    Wk[ky, kx] * a[clamp((i + p - ky)/2), clamp((j + p - kx)/2)], p = K/2 - 1,
+    replicate border as in the 1-D case."""
+    a = np.asarray(a, float)
+    K = Wk.shape[0]
+    ny, nx = a.shape[-2:]
+    out = np.zeros(a.shape[:-2] + (2 * ny, 2 * nx))
+    for (ky, rows, ridx) in _tconv_index(ny, K):
+        for (kx, cols, cidx) in _tconv_index(nx, K):
+            out[..., rows[:, None], cols[None, :]] += Wk[ky, kx] * a[..., ridx[:, None], cidx[None, :]]
+    return out
+
+
+def tconv2d_adjoint(g_out, a, Wk):
+    """Adjoint of :func:`tconv2d`: returns (dL/da, dL/dWk)."""
+    g = np.asarray(g_out, float)
+    a = np.asarray(a, float)
+    K = Wk.shape[0]
+    ny, nx = a.shape[-2:]
+    ga = np.zeros(a.shape)
+    gW = np.zeros((K, K))
+    for (ky, rows, ridx) in _tconv_index(ny, K):
+        for (kx, cols, cidx) in _tconv_index(nx, K):
+            gk = g[..., rows[:, None], cols[None, :]]
+            np.add.at(ga, (Ellipsis, ridx[:, None], cidx[None, :]), Wk[ky, kx] * gk)
+            gW[ky, kx] = np.sum(gk * a[..., ridx[:, None], cidx[None, :]])
+    return ga, gW
+
+
+def upsample_step(stack, ups, s):
+    """U_s: the separable kernel of step s (ups [L-1][2][K]) or the shared
+    K x K kernel (ups [K][K])."""
+    if ups.ndim == 2:
+        return tconv2d(stack, ups)
+    return upsample2x(stack, ups[s, 0], ups[s, 1])
+
+
 def upsample_pyramid(levels, ups):
     """Bring every grid to full resolution (Section II f_upsilon): stack_{L-1}
     = y_hat_{L-1}; stack_s = [y_hat_s, U_s(stack_{s+1})] for s = L-2 .. 0.
@@ -379,7 +429,7 @@ def upsample_pyramid(levels, ups):
     stack = levels[L - 1][None]
     stacks = {L - 1: stack}
     for s in range(L - 2, -1, -1):
-        up = upsample2x(stack, ups[s, 0], ups[s, 1])
+        up = upsample_step(stack, ups, s)
         stack = np.concatenate([levels[s][None], up], axis=0)
         stacks[s] = stack
     return stack, stacks
@@ -551,11 +601,15 @@ def backward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None, dloss=1.0):
     for s in range(0, L - 1):
         g_levels[s] += g_stack[0]
         src = stacks[s + 1]
-        tmp = tconv1d(src, P["ups"][s, 0], axis=-2)
-        g_tmp, gh = tconv1d_adjoint(g_stack[1:], tmp, P["ups"][s, 1], axis=-1)
-        g_src, gv = tconv1d_adjoint(g_tmp, src, P["ups"][s, 0], axis=-2)
-        G["ups"][s, 0] += gv
-        G["ups"][s, 1] += gh
+        if arch.ups_shared:
+            g_src, gW = tconv2d_adjoint(g_stack[1:], src, P["ups"])
+            G["ups"] += gW
+        else:
+            tmp = tconv1d(src, P["ups"][s, 0], axis=-2)
+            g_tmp, gh = tconv1d_adjoint(g_stack[1:], tmp, P["ups"][s, 1], axis=-1)
+            g_src, gv = tconv1d_adjoint(g_tmp, src, P["ups"][s, 0], axis=-2)
+            G["ups"][s, 0] += gv
+            G["ups"][s, 1] += gh
         g_stack = g_src
     g_levels[L - 1] += g_stack[0]
 

@@ -64,6 +64,9 @@ def oracle_backward(c):
 
 def assert_grad_close(name, g, go, tol=1e-3):
     g = np.asarray(g, np.float64)
+    assert g.shape == np.shape(go), name
+    if g.size == 0:  # e.g. no upsampling parameters with a single level
+        return
     nrm = np.linalg.norm(go)
     assert np.all(np.isfinite(g)), name
     assert np.linalg.norm(g - go) <= tol * nrm + 1e-30, (name, np.linalg.norm(g - go) / max(nrm, 1e-30))
@@ -157,16 +160,17 @@ def test_full_768x512_noise_mode(B):
 
 @pytest.mark.parametrize("which", ["low", "full"])
 def test_rate_error_conditioning_768x512(B, which):
-    """Measures, over every latent of the 768x512 workloads, the per-latent
-    rate error against the oracle divided by |dr/dmu| + |dr/ds| (the oracle's
-    derivatives): the size of the FP32 error in (mu, s) that the rate error
-    corresponds to.  It must stay below the 1e-5 the rate bar grants."""
+    """Measures, over every latent of the 768x512 workloads, the part of the
+    per-latent rate error above 1e-5 bits (ten times below the plain bar)
+    divided by |dr/dmu| + |dr/ds| (the oracle's derivatives): the size of the
+    FP32 error in (mu, s) that the rate error corresponds to.  It must stay
+    below the 1e-5 the rate bar grants."""
     c = CS.low() if which == "low" else CS.full()
     out = gpu_forward(B, c)
     ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=c.u)
     _, gmu, gs = O.rate_grads(ref["yq"], ref["mu"], ref["s"])
     err = np.abs(out["rate"] - ref["rate"])
-    ratio = err / (np.abs(gmu) + np.abs(gs))
+    ratio = np.maximum(err - 1e-5, 0.0) / (np.abs(gmu) + np.abs(gs))
     k = int(np.argmax(ratio))
     print(f"{which}: max |dr| / (|dr/dmu| + |dr/ds|) = {ratio[k]:.3e} at latent {k} (|dr| {err[k]:.3e} bits, "
           f"b {np.exp(np.clip(ref['s'][k], O.S_MIN, O.S_MAX)):.4g}); max |dr| {err.max():.3e} bits; "

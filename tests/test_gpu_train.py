@@ -60,11 +60,14 @@ def test_adam_step_several_steps_vs_oracle(B, betas, offset):
     step = torch.zeros(2, dtype=torch.int32, device="cuda")
     th_o, m_o, v_o = th0.astype(np.float64), np.zeros(n), np.zeros(n)
     lr, eps = 1e-2, 1e-8
+    # the oracle takes the hyperparameters as the kernel sees them (FP32)
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
     for t in range(1, 5):
         gv = (rng.normal(size=n) * (0.5 + t)).astype(np.float32)
         g.copy_(_dev(gv))
         B.coolchic_adam_step(th, g, m, v, step, lr=lr, beta1=betas[0], beta2=betas[1], eps=eps)
-        th_o, m_o, v_o = O.adam_step(th_o, gv, m_o, v_o, t, lr=lr, beta1=betas[0], beta2=betas[1], eps=eps)
+        th_o, m_o, v_o = O.adam_step(th_o, gv, m_o, v_o, t, lr=f32(lr), beta1=f32(betas[0]), beta2=f32(betas[1]),
+                                     eps=f32(eps))
         torch.cuda.synchronize()
         assert np.allclose(m.cpu().numpy(), m_o, rtol=2e-6, atol=1e-7), t
         assert np.allclose(v.cpu().numpy(), v_o, rtol=2e-6, atol=1e-7), t
@@ -76,13 +79,16 @@ def test_adam_step_several_steps_vs_oracle(B, betas, offset):
 def test_train_step_three_iterations_vs_oracle(B):
     """coolchic_train_step x 3 on the 64x64 workload with the noise proxy and
     betas (0.8, 0.95), eps 0.1: latents and every parameter block, both
-    moments, the loss of each iteration and the step counter."""
+    moments, the loss of each iteration and the step counter.  The moments
+    and the parameter updates are held to the gradient bar; a latent update
+    can be below the FP32 resolution of the latent, so the parameters also
+    get four FP32 spacings of slack."""
     c = CS.make("tiny64_noise", 64, 64, CS.TINY, seeds=(0, 1, 2, 4), noise=True)
     p = _problem(B, c)
     n = CS.n_latents(c.H, c.W, c.arch[0])
     na, nu, ns = CS.sizes(c.arch)
     theta0 = np.concatenate([c.y, c.arm, c.ups, c.syn]).astype(np.float32)
-    lr, b1, b2, eps = 1e-2, 0.8, 0.95, 0.1
+    lr, b1, b2, eps = (float(np.float32(x)) for x in (1e-2, 0.8, 0.95, 0.1))
     th = _dev(theta0)
     g = torch.zeros_like(th)
     m = torch.zeros_like(th)
@@ -104,9 +110,12 @@ def test_train_step_three_iterations_vs_oracle(B):
         got = {k: x.cpu().numpy() for k, x in (("theta", th), ("m", m), ("v", v))}
         for lo, hi, blk in ((0, n, "y"), (n, n + na, "arm"), (n + na, n + na + nu, "ups"),
                             (n + na + nu, theta0.size, "syn")):
-            # the update theta_t - theta_0 and the moments, block by block
-            _rel_close(f"t{t} update {blk}", got["theta"][lo:hi] - theta0[lo:hi].astype(np.float64),
-                       th_new[lo:hi] - theta0[lo:hi].astype(np.float64), 2e-3)
+            # the parameters (against the size of their update), and the
+            # moments, block by block
+            upd = np.max(np.abs(th_new[lo:hi] - theta0[lo:hi]))
+            slack = 4.0 * np.spacing(np.abs(th_new[lo:hi]).astype(np.float32)).astype(np.float64)
+            dth = np.abs(got["theta"][lo:hi] - th_new[lo:hi])
+            assert np.all(dth <= 2e-3 * upd + slack), (t, blk, float(np.max(dth - slack)), upd)
             _rel_close(f"t{t} m {blk}", got["m"][lo:hi], m_o[lo:hi], 2e-3)
             _rel_close(f"t{t} v {blk}", got["v"][lo:hi], v_o[lo:hi], 2e-3)
         th_o = th_new

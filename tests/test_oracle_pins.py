@@ -341,8 +341,7 @@ def test_quantise_rounds_half_to_even():
 
 
 # --------------------------------------------------------------- gradients
-def _fd_instance():
-    arch = O.FD16
+def _fd_instance(arch=O.FD16):
     sd = WL.SEEDS["fd16"]
     H = W = 16
     n_lat = sum(h * w for h, w in O.level_shapes(H, W, arch.n_levels))
@@ -377,10 +376,15 @@ def _kink_margin(arch, img, y, u, arm, ups, syn):
     return m
 
 
-def test_backward_matches_central_differences_16x16():
+FD_ARCHS = [O.FD16, O.Arch(5, 8, 2, 4, 16, 1, True), O.Arch(5, 8, 2, 8, 16, 1, True)]
+
+
+@pytest.mark.parametrize("arch", FD_ARCHS, ids=["separable8", "shared4", "shared8"])
+def test_backward_matches_central_differences_16x16(arch):
     """Every latent and every parameter of the 16x16, 5-level instance:
-    central differences (h = 1e-6) of the FP64 loss vs the hand adjoint."""
-    arch, img, y, u, arm, ups, syn = _fd_instance()
+    central differences (h = 1e-6) of the FP64 loss vs the hand adjoint; with
+    the per-step separable upsampler and with Table I's shared K x K kernel."""
+    arch, img, y, u, arm, ups, syn = _fd_instance(arch)
     # no ReLU / clamp input may sit within reach of a +-h step: the largest
     # sensitivity of a pre-activation to one input here is below 10, so a
     # margin of 1e-5 keeps every kink out of the +-1e-6 stencil
@@ -401,7 +405,8 @@ def test_backward_matches_central_differences_16x16():
             vm = base.copy(); vm[i] -= h
             fd[i] = (f(*mk(vp)) - f(*mk(vm))) / (2 * h)
         scale = np.max(np.abs(g))
-        assert np.max(np.abs(fd - g)) <= 1e-6 * scale + 1e-12, (name, np.max(np.abs(fd - g)), scale)
+        # the stencil's own rounding: a few ulps of the loss (~1e-16) over h
+        assert np.max(np.abs(fd - g)) <= 1e-6 * scale + 1e-9, (name, np.max(np.abs(fd - g)), scale)
 
 
 def _torch_forward(arch, img, y, arm, ups, syn, lam, u=None):
@@ -446,10 +451,13 @@ def _torch_forward(arch, img, y, arm, ups, syn, lam, u=None):
                          torch.where(hi <= mu, cdf(hi) - cdf(lo), 1.0 - sf(hi) - cdf(lo)))
         R = R + torch.sum(-torch.log2(Pm))
     # upsampling via conv_transpose on replicate-padded grids
-    U = uw.view(L - 1, 2, K)
     stack = levels[L - 1][None, None]
     for s_ in range(L - 2, -1, -1):
-        kern = torch.outer(U[s_, 0], U[s_, 1])[None, None]
+        if arch.ups_shared:
+            kern = uw.view(K, K)[None, None]
+        else:
+            U = uw.view(L - 1, 2, K)
+            kern = torch.outer(U[s_, 0], U[s_, 1])[None, None]
         n = stack.shape[1]
         xp = F.pad(stack.reshape(n, 1, *stack.shape[2:]), (2, 2, 2, 2), mode="replicate")
         up = F.conv_transpose2d(xp, kern, stride=2, padding=K // 2 - 1 + 4).reshape(1, n, *levels[s_].shape)
@@ -472,17 +480,70 @@ def _torch_forward(arch, img, y, arm, ups, syn, lam, u=None):
     return float(loss.detach()), yv.grad.numpy(), aw.grad.numpy(), uw.grad.numpy(), sw.grad.numpy()
 
 
-@pytest.mark.parametrize("noise", [False, True])
-def test_backward_matches_torch_autograd_64x64(noise):
-    """The 64x64, 7-level small instance in both quantisation modes."""
-    arch = O.TINY
+def test_shared_tconv2d_matches_torch_conv_transpose():
+    """Table I's non-separable K x K kernel: out = conv_transpose2d(
+    replicate-pad(a, 2), W, stride 2, padding K/2 - 1 + 4), K = 4 and 8,
+    grids down to 1 x 1."""
+    rng = np.random.default_rng(14)
+    for K in (4, 8):
+        for (ny, nx) in ((1, 1), (1, 3), (2, 5), (6, 4), (7, 9)):
+            a = rng.normal(size=(3, ny, nx))
+            Wk = rng.normal(size=(K, K))
+            ours = O.tconv2d(a, Wk)
+            tp = torch.nn.functional.pad(torch.from_numpy(a)[:, None], (2, 2, 2, 2), mode="replicate")
+            ref = torch.nn.functional.conv_transpose2d(tp, torch.from_numpy(Wk)[None, None], stride=2,
+                                                       padding=K // 2 - 1 + 4)[:, 0].numpy()
+            assert ours.shape == (3, 2 * ny, 2 * nx)
+            assert np.allclose(ours, ref, rtol=0, atol=1e-12), (K, ny, nx)
+
+
+def test_shared_tconv2d_rank_one_equals_separable():
+    """A rank-one kernel W = v h^T is the separable step with taps (v, h); the
+    2-D kernel's first index is the vertical one."""
+    rng = np.random.default_rng(15)
+    a = rng.normal(size=(2, 5, 7))
+    for K in (4, 8):
+        v, h = rng.normal(size=K), rng.normal(size=K)
+        assert np.allclose(O.tconv2d(a, np.outer(v, h)), O.upsample2x(a, v, h), rtol=0, atol=1e-12)
+
+
+def test_shared_tconv2d_adjoint_is_transpose():
+    """<T a, g> = <a, T* g> and dL/dW against central differences (linear in
+    W, so exact up to rounding)."""
+    rng = np.random.default_rng(16)
+    for K in (4, 8):
+        a = rng.normal(size=(2, 4, 6))
+        Wk = rng.normal(size=(K, K))
+        g = rng.normal(size=(2, 8, 12))
+        ga, gW = O.tconv2d_adjoint(g, a, Wk)
+        assert abs(np.sum(O.tconv2d(a, Wk) * g) - np.sum(a * ga)) < 1e-11
+        for ky in range(K):
+            for kx in range(K):
+                E = np.zeros((K, K)); E[ky, kx] = 1.0
+                assert abs(np.sum(O.tconv2d(a, E) * g) - gW[ky, kx]) < 1e-11
+
+
+def test_table1_architectures_parameter_counts():
+    """The four Table I decoders as architectures: 281 / 525 / 941 / 1925
+    parameters (Table I), with the shared TConv-4 / TConv-8 upsampler."""
+    assert {k: sum(O.param_sizes(a)) for k, a in O.TABLE1.items()} == {300: 281, 545: 525, 1079: 941, 2300: 1925}
+
+
+@pytest.mark.parametrize("noise,arch,wstd", [(False, O.TINY, 0.1), (True, O.TINY, 0.1), (True, O.TABLE1[545], 0.1),
+                                             (False, O.TABLE1[1079], 0.1), (False, O.TABLE1[2300], 0.05)])
+def test_backward_matches_torch_autograd_64x64(noise, arch, wstd):
+    """The 64x64, 7-level small instance in both quantisation modes, with the
+    per-step separable upsampler and with Table I decoders (shared TConv-4
+    and TConv-8 upsampler).  For the 24-wide ARM the weights are drawn with
+    std 0.05: with 0.1 some scales reach the 0.01 clamp where the plain CDF
+    difference of the torch formulation underflows to a zero mass."""
     sd = WL.SEEDS["tiny"]
     H = W = 64
     n_lat = sum(h * w for h, w in O.level_shapes(H, W, 7))
     n_arm, n_ups, n_syn = O.param_sizes(arch)
     img = WL.image(sd["image"], H, W, 12)
     y = WL.latents(sd["latents"], H, W, 7, rounded=not noise)
-    w = WL.weights(sd["weights"], n_arm + n_ups + n_syn)
+    w = WL.weights(sd["weights"], n_arm + n_ups + n_syn, std=wstd)
     u = WL.noise(sd["noise"], n_lat) if noise else None
     arm, ups, syn = w[:n_arm], w[n_arm:n_arm + n_ups], w[n_arm + n_ups:]
     out = O.backward(arch, img, y, arm, ups, syn, 0.001, u=u)
