@@ -81,7 +81,9 @@ enum {
   CC_EINVAL = -1,       /* null pointer, bad size, H/W not multiples of 2^(L-1) */
   CC_EUNSUPPORTED = -2, /* architecture outside the compiled variants */
   CC_EWORKSPACE = -3,   /* ws_bytes smaller than coolchic_workspace_bytes() */
-  CC_EHIP = -4          /* a kernel launch failed (hipGetLastError) */
+  CC_EHIP = -4,         /* a kernel launch failed (hipGetLastError) */
+  CC_ESCRATCH = -5      /* coolchic_train_step_noalloc: the problem's workspace
+                           exceeds CC_NOALLOC_SCRATCH_BYTES */
 };
 
 enum { CC_WS_FORWARD = 0, CC_WS_BACKWARD = 1, CC_WS_DECODE = 2 };
@@ -133,6 +135,34 @@ int coolchic_backward(const cc_problem* p, const float* img, const float* y, con
 int coolchic_train_step(const cc_problem* p, const float* img, const float* u, float dloss, float* loss4,
                         float* theta, float* grad, float* m, float* v, int32_t* step, float lr, float beta1,
                         float beta2, float eps, void* ws, size_t ws_bytes, void* stream);
+
+/* Size of the library's static device scratch used by
+   coolchic_train_step_noalloc (64 MiB per device, held until the process
+   ends): enough for the backward workspace of a 768x512 image with the
+   largest compiled decoder (about 32 MiB) and of images up to about one
+   megapixel. */
+#define CC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   coolchic_train_step with its workspace taken from a static device array
+   of CC_NOALLOC_SCRATCH_BYTES that the library owns, instead of a caller's
+   ws.  Same arguments (minus ws, ws_bytes), same results, bit for bit.
+   Calls no hipMalloc / hipFree and creates no stream or event: every kernel
+   runs on `stream` in dependency order (so it is slower than
+   coolchic_train_step, which overlaps the ARM on a side stream).  The first
+   call on a device, with that device current, looks up the array's device
+   address (hipGetSymbolAddress), once.
+   Errors: CC_ESCRATCH (nothing enqueued) when coolchic_workspace_bytes(p,
+   CC_WS_BACKWARD) exceeds CC_NOALLOC_SCRATCH_BYTES; otherwise as
+   coolchic_train_step.  Every call on one device shares that device's
+   array, which keeps the last call's contents (the pass overwrites every
+   region it reads, so nothing needs clearing): calls that overlap in time
+   on one device (concurrent streams or threads) race and give wrong
+   results; serialise them. */
+int coolchic_train_step_noalloc(const cc_problem* p, const float* img, const float* u, float dloss, float* loss4,
+                                float* theta, float* grad, float* m, float* v, int32_t* step, float lr, float beta1,
+                                float beta2, float eps, void* stream);
 
 /* Decoder-side parallel work once the latents are known (Section II
    "Decoding", upsampling then synthesis): yq [N_lat] integer-valued latents

@@ -15,7 +15,8 @@ import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoolchic.so")
 
-CC_OK, CC_EINVAL, CC_EUNSUPPORTED, CC_EWORKSPACE, CC_EHIP = 0, -1, -2, -3, -4
+CC_OK, CC_EINVAL, CC_EUNSUPPORTED, CC_EWORKSPACE, CC_EHIP, CC_ESCRATCH = 0, -1, -2, -3, -4, -5
+CC_NOALLOC_SCRATCH_BYTES = 64 << 20
 CC_QUANT_ROUND, CC_QUANT_NOISE = 0, 1
 CC_WS_FORWARD, CC_WS_BACKWARD, CC_WS_DECODE = 0, 1, 2
 
@@ -26,7 +27,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_batch_backward", "coolchic_batch_destroy", "coolchic_warm_param_count",
            "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward",
            "coolchic_uniform_noise", "coolchic_warm_backward_grad", "coolchic_timing_event_create",
-           "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy", "coolchic_train_step")
+           "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy", "coolchic_train_step",
+           "coolchic_train_step_noalloc")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -75,6 +77,7 @@ def _load():
         "coolchic_decode_synth": (I, [pp, P, P, P, P, P, SZ, P]),
         "coolchic_adam_step": (I, [P, P, P, P, I64, P, F, F, F, F, P]),
         "coolchic_train_step": (I, [pp, P, P, F, P, P, P, P, P, P, F, F, F, F, P, SZ, P]),
+        "coolchic_train_step_noalloc": (I, [pp, P, P, F, P, P, P, P, P, P, F, F, F, F, P]),
         "coolchic_set_stage_events": (I, [I, P, P]),
         "coolchic_timing_event_create": (I, [ctypes.POINTER(P)]),
         "coolchic_timing_event_elapsed": (I, [P, P, ctypes.POINTER(F)]),
@@ -251,6 +254,22 @@ def coolchic_train_step(p: Problem, img, u, dloss, loss4, theta, grad, m, v, ste
                                   _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"), _ptr(step, 2, "step"),
                                   lr, beta1, beta2, eps, _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
     _check(rc, "coolchic_train_step")
+
+
+def coolchic_train_step_noalloc(p: Problem, img, u, dloss, loss4, theta, grad, m, v, step, lr=1e-2, beta1=0.9,
+                                beta2=0.999, eps=1e-8, stream=None):
+    """coolchic_train_step with the library's static device scratch as its
+    workspace (no allocation by the library or here)."""
+    n_lat = latent_count(p)
+    na, nu, ns = param_count(p.arch)
+    n = n_lat + na + nu + ns
+    if step.dtype != torch.int32 or step.numel() != 2:
+        raise TypeError("step must be a device int32 tensor of 2 elements: steps taken, completion counter (0)")
+    rc = _lib.coolchic_train_step_noalloc(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"), _ptr(u, n_lat, "u"),
+                                          float(dloss), _ptr(loss4, 4, "loss4"), _ptr(theta, n, "theta"),
+                                          _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
+                                          _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
+    _check(rc, "coolchic_train_step_noalloc")
 
 
 def coolchic_uniform_noise(u, seed: int, step=None, stream_id: int = 0, stream=None):

@@ -464,9 +464,14 @@ void fuse_adam(const FusedAdam& f, CombineArgs& ca, bool last, int32_t* t_slot) 
   ca.fold.th = f.theta + o; ca.fold.m = f.m + o; ca.fold.v = f.v + o;
 }
 
+// one_stream: every kernel on the caller's stream in dependency order (no
+// side stream, so no stream or event is ever created); otherwise the ARM and
+// the side combine run on the device's side stream beside the synthesis
+// adjoint.  Both orders give bit-identical results.
 int backward_impl(const cc_problem* p, const float* img, const float* y, const float* u, const float* arm_w,
                   const float* ups_w, const float* syn_w, float dloss, float* loss4, float* g_y, float* g_arm,
-                  float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream, const FusedAdam* fused) {
+                  float* g_ups, float* g_syn, void* ws, size_t ws_bytes, void* stream, const FusedAdam* fused,
+                  bool one_stream = false) {
   Plan P;
   int rc = make_plan(p, CC_WS_BACKWARD, &P);
   if (rc) return rc;
@@ -490,26 +495,27 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   }
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side* sd = nullptr;
-  if ((rc = side_for_current_device(&sd))) return rc;
+  if (!one_stream && (rc = side_for_current_device(&sd))) return rc;
+  hipStream_t side = one_stream ? st : sd->stream;
   (void)hipGetLastError();
   if (b.upf_grid && (rc = launch((const void*)ups_fwd_kernel, b.upf_grid, 256, &b.upf, st))) return rc;
   if ((rc = launch(t0k, b.t0_grid, 256, &b.syn, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, bwk, P.syn_grid, SYN_THREADS, &b.syn, st))) return rc;
   // the ARM (independent of the synthesis chain) on the side stream, beside
   // the head backward and the latency-bound upsampling adjoint launches
-  if ((rc = fork_to(sd, st))) return rc;
-  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, sd->stream))) return rc;
+  if (!one_stream && (rc = fork_to(sd, st))) return rc;
+  if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, side))) return rc;
   if ((rc = launch(hdk, P.head_grid, 256, &b.syn, st))) return rc;
   // level 0 of g_y is final: the side combine may start
-  if ((rc = side_waits(sd, st))) return rc;
-  if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, sd->stream))) return rc;
+  if (!one_stream && (rc = side_waits(sd, st))) return rc;
+  if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, side))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
     if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0, st) !=
         hipSuccess)
       return CC_EHIP;
   }
-  if ((rc = join_from(sd, st))) return rc;
+  if (!one_stream && (rc = join_from(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_main_grid, 256, &b.comb_main, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
@@ -539,6 +545,70 @@ int coolchic_train_step(const cc_problem* p, const float* img, const float* u, f
   const FusedAdam f{theta, grad, m, v, step, lr, beta1, beta2, eps};
   return backward_impl(p, img, theta, u, theta + ny, theta + ny + na, theta + ny + na + nu, dloss, loss4, grad,
                        grad + ny, grad + ny + na, grad + ny + na + nu, ws, ws_bytes, stream, &f);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free training step
+
+// The workspace of coolchic_train_step_noalloc: one copy per device, resident
+// until the process ends (it is .bss of the code object: nothing is stored in
+// the library file).  In host code `scratch` names a host-side stand-in, not
+// device memory: only the address hipGetSymbolAddress returns for a device is
+// ever handed to a kernel or a HIP call.
+static __device__ __align__(256) unsigned char scratch[CC_NOALLOC_SCRATCH_BYTES];
+
+namespace cc {
+namespace {
+
+void* g_scratch[MAX_DEVICES];  // device address of `scratch` on each device, set once
+std::mutex g_scratch_mu;
+
+// Looks up (once per device, with that device current) the device address of
+// the static scratch array.
+int scratch_for_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return CC_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CC_EHIP;
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return CC_OK;
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+int coolchic_train_step_noalloc(const cc_problem* p, const float* img, const float* u, float dloss, float* loss4,
+                                float* theta, float* grad, float* m, float* v, int32_t* step, float lr, float beta1,
+                                float beta2, float eps, void* stream) {
+  // sizes first: a problem whose workspace does not fit is refused before
+  // anything touches the device
+  const size_t need = coolchic_workspace_bytes(p, CC_WS_BACKWARD);
+  if (need == 0) {
+    const int rc = check_problem(p);
+    return rc ? rc : CC_EINVAL;
+  }
+  if (need > CC_NOALLOC_SCRATCH_BYTES) return CC_ESCRATCH;
+  if (!theta || !grad || !m || !v || !step) return CC_EINVAL;
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return CC_EINVAL;
+  int64_t na = 0, nu = 0, ns = 0;
+  if (coolchic_param_count(&p->arch, &na, &nu, &ns) <= 0) return CC_EUNSUPPORTED;
+  const int64_t ny = coolchic_latent_count(p);
+  if (ny <= 0) return CC_EINVAL;
+  void* ws = nullptr;
+  int rc = scratch_for_current_device(&ws);
+  if (rc) return rc;
+  const FusedAdam f{theta, grad, m, v, step, lr, beta1, beta2, eps};
+  return backward_impl(p, img, theta, u, theta + ny, theta + ny + na, theta + ny + na + nu, dloss, loss4, grad,
+                       grad + ny, grad + ny + na, grad + ny + na + nu, ws, CC_NOALLOC_SCRATCH_BYTES, stream, &f,
+                       /*one_stream=*/true);
 }
 
 }  // extern "C"
@@ -884,6 +954,8 @@ const char* coolchic_strerror(int code) {
     case CC_EUNSUPPORTED: return "architecture not supported by the compiled kernels";
     case CC_EWORKSPACE: return "workspace smaller than coolchic_workspace_bytes()";
     case CC_EHIP: return "HIP kernel launch failed";
+    case CC_ESCRATCH: return "problem needs more workspace than the static scratch of coolchic_train_step_noalloc "
+                             "(CC_NOALLOC_SCRATCH_BYTES)";
   }
   return "unknown error code";
 }

@@ -177,3 +177,28 @@ def test_train_step_rejects_invalid_arguments(B):
     small = list(args(d, 0.9))
     small[15] = need - 4                                          # workspace too small
     assert B.lib.coolchic_train_step(*small) == -3
+
+
+def test_train_step_noalloc_rejects_before_touching_the_device(B):
+    """The allocation-free training step refuses, with the documented codes
+    and before any HIP call, a problem whose backward workspace exceeds the
+    static scratch (CC_ESCRATCH), an invalid problem and bad arguments."""
+    d = ctypes.c_void_p(0x1000)
+
+    def call(p, theta=d, b1=0.9):
+        pc = p.c() if p is not None else None
+        return B.lib.coolchic_train_step_noalloc(None if pc is None else ctypes.byref(pc), d, None,
+                                                 ctypes.c_float(1.0), d, theta, d, d, d, d, ctypes.c_float(0.01),
+                                                 ctypes.c_float(b1), ctypes.c_float(0.999), ctypes.c_float(1e-8), None)
+
+    big = B.Problem(2048, 2048, B.FULL)
+    assert B.workspace_bytes(big, 1) > B.CC_NOALLOC_SCRATCH_BYTES
+    assert call(big) == B.CC_ESCRATCH
+    assert "static scratch" in B.strerror(B.CC_ESCRATCH)
+    assert call(None) == -1
+    assert call(B.Problem(100, 768, B.FULL)) == -1                 # H not a multiple of 2^(L-1)
+    assert call(B.Problem(512, 768, B.Arch(7, 12, 2, 8, 40, 2))) == -2
+    fits = B.Problem(512, 768, B.FULL)
+    assert B.workspace_bytes(fits, 1) <= B.CC_NOALLOC_SCRATCH_BYTES
+    assert call(fits, theta=None) == -1
+    assert call(fits, b1=1.0) == -1
