@@ -332,6 +332,65 @@ int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const 
                                 const float* g_theta, float* loss4, float* g_net, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* ---- Entropy coding of the latents (Section II: the latent grids are sent
+   with a range coder driven by the ARM p_psi; Section III-B: the decoder's
+   ARM runs latent after latent).  The probability of a latent is the
+   Laplace model of the training rate with its parameters quantised for
+   coding: scale index j = rint(8 (clamp(s, ln 0.01, ln 100) - ln 0.01)) (a
+   NaN s taken as ln 100), mean c + f / 16 with c = floor(mu), f =
+   rint(16 (mu - c)) (16 carries into c; mu clamped to +-2^20, NaN taken as
+   0), all in float32 from the ARM outputs (mu, s), which both the encoder
+   and the decoder evaluate with the same fixed-order float32 code.  Table
+   row (j, f) holds the frequencies 1 + floor(P (2^16 - 98)) of d = y_hat - c
+   in [-48, 48] and of an escape symbol for both tails (P the Laplace(f/16,
+   exp(ln 0.01 + j / 8)) masses in float64; the remainder goes to the first
+   most frequent symbol).  An escaped latent sends the bit length of
+   |d| - 48 (5 raw bits), its bits below the leading one (chunks of <= 8,
+   most significant first) and its sign.  Coder: interleaved rANS, 32-bit
+   states in [2^23, 2^31), byte renormalisation, 16-bit frequencies; level 0
+   and levels 1..L-1 form two sets of min(64, rows of the set's first level)
+   states, each with its own byte stream.  Decode order: step t of a grid
+   decodes the latents (i, t - a i) (a = 2, 3, 4 for 8, 16, 24 context
+   neighbours), rows ascending; row i is coded by state i mod n_states; the
+   rows of a step go in groups of n_states consecutive rows, each group a
+   round of primary symbols then rounds of the escape payloads.
+   Bitstream (little-endian): "CCR1", u32 number of sets, u32 byte count of
+   each set, u32 final state of every state (set 0 first), then the bytes of
+   each set.  Supported: every compiled architecture with H <= 2048; the
+   problem's quant and lambda are ignored.  Latents must be integers with
+   |y_hat| <= 2^20. */
+
+/* Device workspace bytes of coolchic_entropy_encode / _decode; 0 if the
+   problem is invalid or unsupported. */
+size_t coolchic_entropy_workspace_bytes(const cc_problem* p);
+
+/* An output capacity that always suffices for coolchic_entropy_encode (12
+   bytes per latent plus the header); -1 if the problem is invalid. */
+int64_t coolchic_entropy_bound(const cc_problem* p);
+
+/* Writes the coder's cumulative frequency tables, uint32 [75][16][99] (scale
+   index j, mean offset f, symbol k = d + 48 with k = 97 the escape; entry 98
+   is 2^16), to the device array cum. */
+int coolchic_entropy_tables(uint32_t* cum, void* stream);
+
+/* Encodes the integer latent pyramid yq [N_lat] (device) with the ARM
+   parameters arm_w into out (device, out_capacity bytes).  *out_nbytes
+   (device int64) receives the bitstream size; 0 if a latent is not an
+   integer of magnitude <= 2^20 (nothing written); -size if out_capacity is
+   too small (nothing written).  ws: coolchic_entropy_workspace_bytes. */
+int coolchic_entropy_encode(const cc_problem* p, const float* yq, const float* arm_w, uint8_t* out,
+                            size_t out_capacity, int64_t* out_nbytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Decodes a bitstream (device, in_bytes bytes) into yq_out [N_lat] (device,
+   float32 integer values), evaluating the ARM arm_w on the decoded context
+   as the wavefront advances.  status (device int32 [2], one per set; the
+   second is written only when L > 1): 0 on success; 1 the header does not
+   match the problem or in_bytes, 2 a stream ended early, 4 the stream or the
+   final states disagree with the problem (a damaged stream or other ARM
+   weights); yq_out is then unspecified. */
+int coolchic_entropy_decode(const cc_problem* p, const uint8_t* in, size_t in_bytes, const float* arm_w,
+                            float* yq_out, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Static description of an error code. */
 const char* coolchic_strerror(int code);
 

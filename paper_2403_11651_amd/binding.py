@@ -28,7 +28,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_warm_workspace_bytes", "coolchic_warm_forward", "coolchic_warm_backward",
            "coolchic_uniform_noise", "coolchic_warm_backward_grad", "coolchic_timing_event_create",
            "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy", "coolchic_train_step",
-           "coolchic_train_step_noalloc")
+           "coolchic_train_step_noalloc", "coolchic_entropy_workspace_bytes", "coolchic_entropy_bound",
+           "coolchic_entropy_tables", "coolchic_entropy_encode", "coolchic_entropy_decode")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -89,6 +90,11 @@ def _load():
         "coolchic_batch_backward": (I, [P, P]),
         "coolchic_batch_destroy": (None, [P]),
         "coolchic_uniform_noise": (I, [P, I64, ctypes.c_uint64, P, ctypes.c_uint32, P]),
+        "coolchic_entropy_workspace_bytes": (SZ, [pp]),
+        "coolchic_entropy_bound": (I64, [pp]),
+        "coolchic_entropy_tables": (I, [P, P]),
+        "coolchic_entropy_encode": (I, [pp, P, P, P, SZ, P, P, SZ, P]),
+        "coolchic_entropy_decode": (I, [pp, P, SZ, P, P, P, P, SZ, P]),
         "coolchic_warm_param_count": (I64, [pa]),
         "coolchic_warm_workspace_bytes": (SZ, [ctypes.POINTER(CCWarmProblem), I]),
         "coolchic_warm_forward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, SZ, P]),
@@ -170,7 +176,7 @@ def _ptr(t, n=None, name="tensor"):
         return None
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a GPU tensor")
-    if t.dtype not in (torch.float32, torch.int32, torch.uint8) or not t.is_contiguous():
+    if t.dtype not in (torch.float32, torch.int32, torch.int64, torch.uint8) or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous float32 tensor")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
@@ -270,6 +276,53 @@ def coolchic_train_step_noalloc(p: Problem, img, u, dloss, loss4, theta, grad, m
                                           _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
                                           _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
     _check(rc, "coolchic_train_step_noalloc")
+
+
+def entropy_workspace(p: Problem, device="cuda") -> torch.Tensor:
+    n = int(_lib.coolchic_entropy_workspace_bytes(ctypes.byref(p.c())))
+    if n == 0:
+        raise CoolChicError(CC_EUNSUPPORTED, "coolchic_entropy_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def entropy_bound(p: Problem) -> int:
+    n = int(_lib.coolchic_entropy_bound(ctypes.byref(p.c())))
+    if n < 0:
+        raise CoolChicError(CC_EINVAL, "coolchic_entropy_bound")
+    return n
+
+
+def coolchic_entropy_tables(cum, stream=None):
+    """cum: device int32 tensor of 75 * 16 * 99 elements (read as uint32)."""
+    _check(_lib.coolchic_entropy_tables(_ptr(cum, 75 * 16 * 99, "cum"), _stream(stream)), "coolchic_entropy_tables")
+
+
+def coolchic_entropy_encode(p: Problem, yq, arm_w, out, out_nbytes, ws=None, stream=None):
+    """Bitstream of the integer latents yq into the device uint8 tensor out;
+    out_nbytes: device int64 tensor of one element (size, 0, or -size)."""
+    n_lat = latent_count(p)
+    na, _, _ = param_count(p.arch)
+    if ws is None:
+        ws = entropy_workspace(p, device=yq.device)
+    rc = _lib.coolchic_entropy_encode(ctypes.byref(p.c()), _ptr(yq, n_lat, "yq"), _ptr(arm_w, na, "arm_w"),
+                                      _ptr(out, None, "out"), out.numel(), _ptr(out_nbytes, 1, "out_nbytes"),
+                                      _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_entropy_encode")
+
+
+def coolchic_entropy_decode(p: Problem, data, nbytes: int, arm_w, yq_out, status, ws=None, stream=None):
+    """Latents from the first nbytes bytes of the device uint8 tensor data;
+    status: device int32 tensor of two elements (one per set of grids)."""
+    n_lat = latent_count(p)
+    na, _, _ = param_count(p.arch)
+    if ws is None:
+        ws = entropy_workspace(p, device=yq_out.device)
+    if nbytes > data.numel():
+        raise ValueError("nbytes exceeds the data tensor")
+    rc = _lib.coolchic_entropy_decode(ctypes.byref(p.c()), _ptr(data, None, "data"), int(nbytes),
+                                      _ptr(arm_w, na, "arm_w"), _ptr(yq_out, n_lat, "yq_out"),
+                                      _ptr(status, 2, "status"), _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_entropy_decode")
 
 
 def coolchic_uniform_noise(u, seed: int, step=None, stream_id: int = 0, stream=None):

@@ -947,6 +947,163 @@ int coolchic_timing_event_destroy(void* ev) {
   return hipEventDestroy((hipEvent_t)ev) == hipSuccess ? CC_OK : CC_EHIP;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- entropy coding
+
+namespace cc {
+namespace {
+
+struct CodecPlan {
+  CodecArgs a;
+  size_t off_cum, off_meta, off_tbl, off_dsym, off_emit[CD_MAX_SETS], total;  // bytes
+  int64_t bound;
+  int threads;
+  size_t lds;
+};
+
+size_t take_bytes(size_t& cur, size_t n) {
+  const size_t at = cur;
+  cur += (n + 255) / 256 * 256;
+  return at;
+}
+
+int codec_plan(const cc_problem* p, CodecPlan* cp) {
+  Plan P;
+  int rc = make_plan(p, CC_WS_FORWARD, &P);
+  if (rc) return rc;
+  if (p->H > CD_MAX_ROWS) return CC_EUNSUPPORTED;
+  std::memset(cp, 0, sizeof(*cp));
+  CodecArgs& a = cp->a;
+  a.geo = P.geo;
+  a.C = P.C;
+  a.NH = P.NH;
+  a.slope = P.C == 8 ? 2 : (P.C == 16 ? 3 : 4);
+  const int L = P.geo.L;
+  a.n_sets = L > 1 ? 2 : 1;
+  a.set[0] = CodecSet{std::min(CD_LANES, P.geo.lh[0]), 0, 1};
+  if (L > 1) a.set[1] = CodecSet{std::min(CD_LANES, P.geo.lh[1]), 1, L};
+  a.rows_max = P.geo.lh[0];
+  size_t cur = 0;
+  cp->off_cum = take_bytes(cur, sizeof(uint32_t) * CD_NSCALE * CD_NMU * CD_ROW);
+  cp->off_meta = take_bytes(cur, sizeof(uint32_t) * CD_META_N);
+  cp->off_tbl = take_bytes(cur, sizeof(uint16_t) * (size_t)P.geo.n_lat);
+  cp->off_dsym = take_bytes(cur, sizeof(int32_t) * (size_t)P.geo.n_lat);
+  int lanes = 0;
+  for (int s = 0; s < a.n_sets; ++s) {
+    const CodecSet& S = a.set[s];
+    const int64_t nl = (int64_t)P.geo.loff[S.lv1] - P.geo.loff[S.lv0];
+    a.emit_cap[s] = nl * CD_BYTES_PER_LATENT;
+    cp->off_emit[s] = take_bytes(cur, (size_t)a.emit_cap[s]);
+    lanes += S.n_lanes;
+  }
+  cp->total = cur;
+  cp->bound = 8 + 4 * (int64_t)a.n_sets + 4 * (int64_t)lanes + (int64_t)CD_BYTES_PER_LATENT * P.geo.n_lat;
+  cp->threads = std::min(1024, std::max(64, (a.rows_max + 63) / 64 * 64));
+  cp->lds = (size_t)a.rows_max * (CD_RING * sizeof(float) + sizeof(int2));
+  return CC_OK;
+}
+
+void codec_bind(CodecPlan* cp, void* ws) {
+  uint8_t* b = (uint8_t*)ws;
+  CodecArgs& a = cp->a;
+  a.cum = (uint32_t*)(b + cp->off_cum);
+  a.meta = (uint32_t*)(b + cp->off_meta);
+  a.tbl = (uint16_t*)(b + cp->off_tbl);
+  a.dsym = (int32_t*)(b + cp->off_dsym);
+  for (int s = 0; s < a.n_sets; ++s) a.emit[s] = b + cp->off_emit[s];
+}
+
+constexpr int CD_TABLE_ROWS = CD_NSCALE * CD_NMU;
+
+int launch_table(uint32_t* cum, uint32_t* meta, hipStream_t st) {
+  void* argv[] = {&cum, &meta};
+  return hipLaunchKernel((const void*)codec_table_kernel, dim3((CD_TABLE_ROWS + 63) / 64), dim3(64), argv, 0, st) ==
+                 hipSuccess
+             ? CC_OK
+             : CC_EHIP;
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+size_t coolchic_entropy_workspace_bytes(const cc_problem* p) {
+  CodecPlan cp;
+  return codec_plan(p, &cp) ? 0 : cp.total;
+}
+
+int64_t coolchic_entropy_bound(const cc_problem* p) {
+  CodecPlan cp;
+  return codec_plan(p, &cp) ? -1 : cp.bound;
+}
+
+int coolchic_entropy_tables(uint32_t* cum, void* stream) {
+  if (!cum) return CC_EINVAL;
+  (void)hipGetLastError();
+  const int rc = launch_table(cum, nullptr, (hipStream_t)stream);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+int coolchic_entropy_encode(const cc_problem* p, const float* yq, const float* arm_w, uint8_t* out,
+                            size_t out_capacity, int64_t* out_nbytes, void* ws, size_t ws_bytes, void* stream) {
+  CodecPlan cp;
+  int rc = codec_plan(p, &cp);
+  if (rc) return rc;
+  if (!yq || !arm_w || !out || !out_nbytes || !ws) return CC_EINVAL;
+  if (ws_bytes < cp.total) return CC_EWORKSPACE;
+  const void* prk = codec_params_kernel_for(cp.a.C);
+  if (!prk) return CC_EUNSUPPORTED;
+  codec_bind(&cp, ws);
+  CodecArgs& a = cp.a;
+  a.yq = yq;
+  a.w = arm_w;
+  a.out = out;
+  a.out_cap = (int64_t)std::min<size_t>(out_capacity, (size_t)INT64_MAX);
+  a.out_nbytes = out_nbytes;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if ((rc = launch_table(a.cum, a.meta, st))) return rc;
+  if ((rc = launch(prk, cdiv(a.geo.n_lat, 256), 256, &a, st))) return rc;
+  {
+    void* argv[] = {&a};
+    if (hipLaunchKernel((const void*)codec_encode_kernel, dim3(a.n_sets), dim3(64), argv, 0, st) != hipSuccess)
+      return CC_EHIP;
+  }
+  const int pack_grid = (int)std::min<int64_t>(2048, (cp.bound + 255) / 256);
+  if ((rc = launch((const void*)codec_pack_kernel, pack_grid, 256, &a, st))) return rc;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+int coolchic_entropy_decode(const cc_problem* p, const uint8_t* in, size_t in_bytes, const float* arm_w,
+                            float* yq_out, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  CodecPlan cp;
+  int rc = codec_plan(p, &cp);
+  if (rc) return rc;
+  if (!in || !arm_w || !yq_out || !status || !ws) return CC_EINVAL;
+  if (ws_bytes < cp.total) return CC_EWORKSPACE;
+  const void* dk = codec_decode_kernel_for(cp.a.C);
+  if (!dk) return CC_EUNSUPPORTED;
+  codec_bind(&cp, ws);
+  CodecArgs& a = cp.a;
+  a.w = arm_w;
+  a.in = in;
+  a.in_bytes = (int64_t)std::min<size_t>(in_bytes, (size_t)INT64_MAX);
+  a.yq_out = yq_out;
+  a.status = status;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  if (cp.lds > 64 * 1024 &&
+      hipFuncSetAttribute(dk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cp.lds) != hipSuccess)
+    return CC_EHIP;
+  if ((rc = launch_table(a.cum, nullptr, st))) return rc;
+  void* argv[] = {&a};
+  if (hipLaunchKernel(dk, dim3(a.n_sets), dim3(cp.threads), argv, cp.lds, st) != hipSuccess) return CC_EHIP;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
 const char* coolchic_strerror(int code) {
   switch (code) {
     case CC_OK: return "ok";

@@ -28,26 +28,6 @@
 
 namespace cc {
 
-// Causal neighbour sets (dy, dx), raster order: the C positions of the 7x7
-// window that precede the latent, nearest first (ties in raster order).
-// (compile-time tables: with the loops over k unrolled, every offset is an
-// immediate)
-template <int C>
-__device__ __forceinline__ constexpr int ctx_dy(int k) {
-  constexpr signed char t8[8] = {-2, -2, -2, -1, -1, -1, 0, 0};
-  constexpr signed char t16[16] = {-3, -3, -3, -2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0, 0};
-  constexpr signed char t24[24] = {-3, -3, -3, -3, -3, -3, -3, -2, -2, -2, -2, -2,
-                                   -2, -2, -1, -1, -1, -1, -1, -1, -1, 0,  0,  0};
-  return C == 8 ? t8[k] : (C == 16 ? t16[k] : t24[k]);
-}
-template <int C>
-__device__ __forceinline__ constexpr int ctx_dx(int k) {
-  constexpr signed char t8[8] = {-1, 0, 1, -1, 0, 1, -2, -1};
-  constexpr signed char t16[16] = {-1, 0, 1, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -3, -2, -1};
-  constexpr signed char t24[24] = {-3, -2, -1, 0, 1, 2, 3, -3, -2, -1, 0, 1, 2, 3, -3, -2, -1, 0, 1, 2, 3, -3, -2, -1};
-  return C == 8 ? t8[k] : (C == 16 ? t16[k] : t24[k]);
-}
-
 constexpr int STG = 36;  // row stride of the per-wave staging matrices
 
 template <int C, int NH, bool BWD>

@@ -184,6 +184,64 @@ template <bool VEC>
 __global__ void adam_kernel(AdamArgs a);
 __global__ void noise_kernel(float* u, int64_t n, uint32_t k0, uint32_t k1, const int32_t* step, uint32_t stream_id);
 
+// ---------------------------------------------------------------- entropy coding
+// Interleaved rANS over the latents with the ARM's Laplace probabilities
+// (quantised per latent to a table row) and the wavefront decode order.
+constexpr int CD_PREC = 16;                      // frequency total 2^16
+constexpr uint32_t CD_TOTAL = 1u << CD_PREC;
+constexpr uint32_t CD_RANS_L = 1u << 23;         // coder state in [2^23, 2^31)
+constexpr int CD_A = 48;                         // |d| <= 48 has a symbol of its own
+constexpr int CD_NSYM = 2 * CD_A + 2;            // 97 symbols and the escape
+constexpr int CD_ESC = CD_NSYM - 1;
+constexpr int CD_ROW = CD_NSYM + 1;              // cumulative frequencies per table row
+constexpr int CD_NMU = 16;                       // mean offsets per integer
+constexpr int CD_SCALE_PER_LN = 8;               // scale indices per unit of ln b
+constexpr int CD_NSCALE = 75;                    // scale indices 0..74 (b = 0.01 .. 100)
+constexpr float CD_LOG_BMIN = -0x1.26bb1cp+2f;   // ln 0.01 rounded to float32
+constexpr float CD_LOG_BMAX = 0x1.26bb1cp+2f;    // ln 100
+constexpr float CD_MU_LIM = 1048576.0f;          // |mu| clamp, 2^20
+constexpr int CD_YQ_LIM = 1 << 20;               // |y_hat| limit of the coder
+constexpr int CD_LANES = 64;                     // coder states per set (one wave)
+constexpr int CD_RING = 16;                      // decoded columns kept per row
+constexpr int CD_MAX_SETS = 2;
+constexpr int CD_MAX_ROWS = 2048;                // rows of a set's first level
+constexpr int CD_BYTES_PER_LATENT = 12;          // worst case: 6 symbols of 2 bytes
+constexpr uint32_t CD_MAGIC = 0x31524343u;       // "CCR1"
+
+struct CodecSet {
+  int n_lanes;   // coder states of the set (min(64, rows of its first level))
+  int lv0, lv1;  // levels [lv0, lv1)
+};
+
+struct CodecArgs {
+  Geo geo;
+  int C, NH, slope, n_sets, rows_max;
+  CodecSet set[CD_MAX_SETS];
+  const float* w;                  // packed ARM parameters
+  uint32_t* cum;                   // [CD_NSCALE * CD_NMU][CD_ROW]
+  // encoder
+  const float* yq;                 // [N_lat] integer-valued latents
+  uint16_t* tbl;                   // [N_lat] table row of each latent
+  int32_t* dsym;                   // [N_lat] y_hat - c
+  uint8_t* emit[CD_MAX_SETS];      // bytes in emission order, per set
+  int64_t emit_cap[CD_MAX_SETS];
+  uint32_t* meta;                  // [set] emitted bytes, [2 + 64 set + lane] final states, [130] bad latent, [131] overflow
+  uint8_t* out;
+  int64_t out_cap;
+  int64_t* out_nbytes;
+  // decoder
+  const uint8_t* in;
+  int64_t in_bytes;
+  float* yq_out;
+  int32_t* status;                 // [n_sets]
+};
+constexpr int CD_META_BAD = 2 + CD_MAX_SETS * CD_LANES, CD_META_OVF = CD_META_BAD + 1, CD_META_N = CD_META_OVF + 1;
+__global__ void codec_table_kernel(uint32_t* cum, uint32_t* meta);
+__global__ void codec_encode_kernel(CodecArgs a);
+__global__ void codec_pack_kernel(CodecArgs a);
+const void* codec_params_kernel_for(int C);
+const void* codec_decode_kernel_for(int C);
+
 // ---------------------------------------------------------------- warm start
 constexpr int WS_CH = 32;          // trunk width
 constexpr int WS_MAX_THETA = 4096; // decoder parameters the head can predict
