@@ -356,7 +356,7 @@ int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const 
    round of primary symbols then rounds of the escape payloads.
    Bitstream (little-endian): "CCR1", u32 number of sets, u32 byte count of
    each set, u32 final state of every state (set 0 first), then the bytes of
-   each set.  Supported: every compiled architecture with H <= 2048; the
+   each set.  Supported: every compiled architecture with H <= 1024; the
    problem's quant and lambda are ignored.  Latents must be integers with
    |y_hat| <= 2^20. */
 
@@ -381,7 +381,7 @@ int coolchic_entropy_tables(uint32_t* cum, void* stream);
 int coolchic_entropy_encode(const cc_problem* p, const float* yq, const float* arm_w, uint8_t* out,
                             size_t out_capacity, int64_t* out_nbytes, void* ws, size_t ws_bytes, void* stream);
 
-/* Decodes a bitstream (device, in_bytes bytes) into yq_out [N_lat] (device,
+/* Decodes a bitstream (device, in_bytes bytes, 4-byte aligned) into yq_out [N_lat] (device,
    float32 integer values), evaluating the ARM arm_w on the decoded context
    as the wavefront advances.  status (device int32 [2], one per set; the
    second is written only when L > 1): 0 on success; 1 the header does not

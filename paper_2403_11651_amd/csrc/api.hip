@@ -956,7 +956,7 @@ namespace {
 
 struct CodecPlan {
   CodecArgs a;
-  size_t off_cum, off_meta, off_tbl, off_dsym, off_emit[CD_MAX_SETS], total;  // bytes
+  size_t off_cum, off_cum16, off_meta, off_tbl, off_dsym, off_emit[CD_MAX_SETS], total;  // bytes
   int64_t bound;
   int threads;
   size_t lds;
@@ -986,6 +986,7 @@ int codec_plan(const cc_problem* p, CodecPlan* cp) {
   a.rows_max = P.geo.lh[0];
   size_t cur = 0;
   cp->off_cum = take_bytes(cur, sizeof(uint32_t) * CD_NSCALE * CD_NMU * CD_ROW);
+  cp->off_cum16 = take_bytes(cur, sizeof(uint16_t) * CD_NSCALE * CD_NMU * CD_ROW16);
   cp->off_meta = take_bytes(cur, sizeof(uint32_t) * CD_META_N);
   cp->off_tbl = take_bytes(cur, sizeof(uint16_t) * (size_t)P.geo.n_lat);
   cp->off_dsym = take_bytes(cur, sizeof(int32_t) * (size_t)P.geo.n_lat);
@@ -999,8 +1000,8 @@ int codec_plan(const cc_problem* p, CodecPlan* cp) {
   }
   cp->total = cur;
   cp->bound = 8 + 4 * (int64_t)a.n_sets + 4 * (int64_t)lanes + (int64_t)CD_BYTES_PER_LATENT * P.geo.n_lat;
-  cp->threads = std::min(1024, std::max(64, (a.rows_max + 63) / 64 * 64));
-  cp->lds = (size_t)a.rows_max * (CD_RING * sizeof(float) + sizeof(int2));
+  cp->threads = 512;  // 8 waves: one 32-row slice each per chunk of CD_SLOTS rows
+  cp->lds = codec_decode_lds_bytes(a.rows_max, (int)P.n_arm);
   return CC_OK;
 }
 
@@ -1008,6 +1009,7 @@ void codec_bind(CodecPlan* cp, void* ws) {
   uint8_t* b = (uint8_t*)ws;
   CodecArgs& a = cp->a;
   a.cum = (uint32_t*)(b + cp->off_cum);
+  a.cum16 = (uint16_t*)(b + cp->off_cum16);
   a.meta = (uint32_t*)(b + cp->off_meta);
   a.tbl = (uint16_t*)(b + cp->off_tbl);
   a.dsym = (int32_t*)(b + cp->off_dsym);
@@ -1016,8 +1018,8 @@ void codec_bind(CodecPlan* cp, void* ws) {
 
 constexpr int CD_TABLE_ROWS = CD_NSCALE * CD_NMU;
 
-int launch_table(uint32_t* cum, uint32_t* meta, hipStream_t st) {
-  void* argv[] = {&cum, &meta};
+int launch_table(uint32_t* cum, uint16_t* cum16, uint32_t* meta, hipStream_t st) {
+  void* argv[] = {&cum, &cum16, &meta};
   return hipLaunchKernel((const void*)codec_table_kernel, dim3((CD_TABLE_ROWS + 63) / 64), dim3(64), argv, 0, st) ==
                  hipSuccess
              ? CC_OK
@@ -1042,7 +1044,7 @@ int64_t coolchic_entropy_bound(const cc_problem* p) {
 int coolchic_entropy_tables(uint32_t* cum, void* stream) {
   if (!cum) return CC_EINVAL;
   (void)hipGetLastError();
-  const int rc = launch_table(cum, nullptr, (hipStream_t)stream);
+  const int rc = launch_table(cum, nullptr, nullptr, (hipStream_t)stream);
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
@@ -1065,8 +1067,8 @@ int coolchic_entropy_encode(const cc_problem* p, const float* yq, const float* a
   a.out_nbytes = out_nbytes;
   hipStream_t st = (hipStream_t)stream;
   (void)hipGetLastError();
-  if ((rc = launch_table(a.cum, a.meta, st))) return rc;
-  if ((rc = launch(prk, cdiv(a.geo.n_lat, 256), 256, &a, st))) return rc;
+  if ((rc = launch_table(a.cum, nullptr, a.meta, st))) return rc;
+  if ((rc = launch(prk, cdiv(a.geo.n_lat, 128), 256, &a, st))) return rc;  // 32 latents per wave
   {
     void* argv[] = {&a};
     if (hipLaunchKernel((const void*)codec_encode_kernel, dim3(a.n_sets), dim3(64), argv, 0, st) != hipSuccess)
@@ -1082,7 +1084,7 @@ int coolchic_entropy_decode(const cc_problem* p, const uint8_t* in, size_t in_by
   CodecPlan cp;
   int rc = codec_plan(p, &cp);
   if (rc) return rc;
-  if (!in || !arm_w || !yq_out || !status || !ws) return CC_EINVAL;
+  if (!in || !arm_w || !yq_out || !status || !ws || ((uintptr_t)in & 3u)) return CC_EINVAL;
   if (ws_bytes < cp.total) return CC_EWORKSPACE;
   const void* dk = codec_decode_kernel_for(cp.a.C);
   if (!dk) return CC_EUNSUPPORTED;
@@ -1098,7 +1100,7 @@ int coolchic_entropy_decode(const cc_problem* p, const uint8_t* in, size_t in_by
   if (cp.lds > 64 * 1024 &&
       hipFuncSetAttribute(dk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cp.lds) != hipSuccess)
     return CC_EHIP;
-  if ((rc = launch_table(a.cum, nullptr, st))) return rc;
+  if ((rc = launch_table(a.cum, a.cum16, nullptr, st))) return rc;
   void* argv[] = {&a};
   if (hipLaunchKernel(dk, dim3(a.n_sets), dim3(cp.threads), argv, cp.lds, st) != hipSuccess) return CC_EHIP;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;

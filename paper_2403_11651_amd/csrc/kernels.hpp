@@ -204,9 +204,11 @@ constexpr int CD_YQ_LIM = 1 << 20;               // |y_hat| limit of the coder
 constexpr int CD_LANES = 64;                     // coder states per set (one wave)
 constexpr int CD_RING = 16;                      // decoded columns kept per row
 constexpr int CD_MAX_SETS = 2;
-constexpr int CD_MAX_ROWS = 2048;                // rows of a set's first level
+constexpr int CD_MAX_ROWS = 1024;                // rows of a set's first level (LDS of the decoder)
 constexpr int CD_BYTES_PER_LATENT = 12;          // worst case: 6 symbols of 2 bytes
 constexpr uint32_t CD_MAGIC = 0x31524343u;       // "CCR1"
+constexpr int CD_ROW16 = 104;                    // uint16 copy of a row: cum[0..97], padding (16-byte rows)
+constexpr int CD_SLOTS = 256;                    // table rows the decoder holds in LDS per chunk of a step
 
 struct CodecSet {
   int n_lanes;   // coder states of the set (min(64, rows of its first level))
@@ -219,6 +221,7 @@ struct CodecArgs {
   CodecSet set[CD_MAX_SETS];
   const float* w;                  // packed ARM parameters
   uint32_t* cum;                   // [CD_NSCALE * CD_NMU][CD_ROW]
+  uint16_t* cum16;                 // [CD_NSCALE * CD_NMU][CD_ROW16]: cum[0..97] (cum[98] = 2^16 implied)
   // encoder
   const float* yq;                 // [N_lat] integer-valued latents
   uint16_t* tbl;                   // [N_lat] table row of each latent
@@ -236,11 +239,12 @@ struct CodecArgs {
   int32_t* status;                 // [n_sets]
 };
 constexpr int CD_META_BAD = 2 + CD_MAX_SETS * CD_LANES, CD_META_OVF = CD_META_BAD + 1, CD_META_N = CD_META_OVF + 1;
-__global__ void codec_table_kernel(uint32_t* cum, uint32_t* meta);
+__global__ void codec_table_kernel(uint32_t* cum, uint16_t* cum16, uint32_t* meta);
 __global__ void codec_encode_kernel(CodecArgs a);
 __global__ void codec_pack_kernel(CodecArgs a);
 const void* codec_params_kernel_for(int C);
 const void* codec_decode_kernel_for(int C);
+size_t codec_decode_lds_bytes(int rows_max, int n_arm);  // dynamic LDS of the decoder
 
 // ---------------------------------------------------------------- warm start
 constexpr int WS_CH = 32;          // trunk width
