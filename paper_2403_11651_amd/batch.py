@@ -203,12 +203,25 @@ def cache_path():
                           os.path.join(os.path.expanduser("~"), ".cache", "coolchic", "autotune.json"))
 
 
+_LIB_DIGEST = None
+
+
+def _library_digest():
+    """Hash of the built library: a tuned choice is only reused with the
+    kernels it was timed on."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        with open(B.LIB_PATH, "rb") as f:
+            _LIB_DIGEST = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _LIB_DIGEST
+
+
 def tuning_key(enc: BatchEncoder):
     a = enc.problems[0].arch
     sizes = ",".join(f"{p.H}x{p.W}" for p in enc.problems)
     dev = torch.cuda.get_device_name(enc.device)
-    return f"{dev}|{a.n_levels},{a.arm_ctx},{a.arm_layers},{a.ups_taps},{a.syn_hidden},{a.syn_res}|" \
-           f"{hashlib.sha256(sizes.encode()).hexdigest()[:16]}"
+    return f"{dev}|{_library_digest()}|{a.n_levels},{a.arm_ctx},{a.arm_layers},{a.ups_taps},{a.syn_hidden}," \
+           f"{a.syn_res}|{hashlib.sha256(sizes.encode()).hexdigest()[:16]}"
 
 
 def _load_cache(path):
