@@ -36,8 +36,11 @@
  *    sum_{m < l} (H >> m) * (W >> m).
  *  - ARM parameters psi: for each hidden residual layer j: W_j [C][C] (out, in)
  *    then b_j [C]; then W_o [2][C] (row 0 = mean, row 1 = log-scale), b_o [2].
- *  - upsampling parameters upsilon: [L-1][2][K]; index s produces level s from
- *    level s+1; [s][0] are the vertical taps, [s][1] the horizontal taps.
+ *  - upsampling parameters upsilon: separable, [L-1][2][K]; index s produces
+ *    level s from level s+1; [s][0] are the vertical taps, [s][1] the
+ *    horizontal taps.  Shared: [K][K] (ky, kx), used by every step.  Output
+ *    row i of a step takes tap ky from input row (i + K/2 - 1 - ky) / 2 when
+ *    that is an integer, the input index clamped to the grid.
  *  - synthesis parameters theta: W1 [Hs][L], b1 [Hs], W2 [3][Hs], b2 [3]; then
  *    for each residual 3x3 conv r: W_r [3][3][3][3] (out, in, ky, kx), b_r [3].
  */
@@ -59,9 +62,14 @@ typedef struct {
                          widths); the C nearest causal positions of a 7x7
                          window, ties in raster order, zero outside the grid */
   int32_t arm_layers; /* hidden C-C-LinR layers before the C-2-Lin output, 1..3 */
-  int32_t ups_taps;   /* K of each 1-D stride-2 transposed conv; only 8 */
+  int32_t ups_taps;   /* K of the stride-2 transposed convs: 4 or 8 (the batched
+                         entry points: 8 only) */
   int32_t syn_hidden; /* width of the first 1x1 synthesis layer, 8..48, multiple of 8 */
   int32_t syn_res;    /* number of residual 3x3 convs 3->3 (ConvR-3), 1..2 */
+  int32_t ups_shared; /* 0: each upsampling step has its own separable kernel
+                         (vertical and horizontal K-tap filters); 1: one
+                         non-separable K x K kernel shared by every step
+                         (Table I "1-1-TConv-K") */
 } cc_arch;
 
 /* Quantisation proxy Q (Section II "Encoding"): rounding to nearest (ties to

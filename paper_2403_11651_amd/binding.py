@@ -35,7 +35,8 @@ CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 class CCArch(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("arm_ctx", ctypes.c_int32), ("arm_layers", ctypes.c_int32),
-                ("ups_taps", ctypes.c_int32), ("syn_hidden", ctypes.c_int32), ("syn_res", ctypes.c_int32)]
+                ("ups_taps", ctypes.c_int32), ("syn_hidden", ctypes.c_int32), ("syn_res", ctypes.c_int32),
+                ("ups_shared", ctypes.c_int32)]
 
 
 class CCProblem(ctypes.Structure):
@@ -123,9 +124,11 @@ class Arch:
     ups_taps: int = 8
     syn_hidden: int = 40
     syn_res: int = 2
+    ups_shared: int = 0
 
     def c(self) -> CCArch:
-        return CCArch(self.n_levels, self.arm_ctx, self.arm_layers, self.ups_taps, self.syn_hidden, self.syn_res)
+        return CCArch(self.n_levels, self.arm_ctx, self.arm_layers, self.ups_taps, self.syn_hidden, self.syn_res,
+                      int(self.ups_shared))
 
 
 FULL = Arch(7, 24, 2, 8, 40, 2)

@@ -36,6 +36,7 @@ struct Plan {
   ArmTiles tiles;
   int C, NH, K, Hs, nres;
   int64_t n_arm, n_ups, n_syn;
+  int shared;             // upsampler: one shared K x K kernel (Table I) instead of separable ones; K = 4 or 8
   int arm_grid, syn_grid, syn_tiles_x, syn_tiles, fold_split, fold_grid0, fold_grid1, red_grid;
   int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
@@ -43,7 +44,8 @@ struct Plan {
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
-  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], tslot, total;
+  size_t t0, gz, gpt, gext, wpart_arm, wpart_syn, hpart, rpart, spart, upart[MAXL], tslot, tapx, total;
+  int up_rows[MAXL];      // tap-gradient partial rows of each upsampling step
   int head_grid;  // tiles of the 1x1-layer backward
   int n_head;     // 1x1-layer parameters (W1, b1, W2, b2)
 };
@@ -53,7 +55,8 @@ bool arch_ok(const cc_arch* a) {
   if (a->n_levels < 1 || a->n_levels > MAXL) return false;
   if (a->arm_ctx != 8 && a->arm_ctx != 16 && a->arm_ctx != 24) return false;
   if (a->arm_layers < 1 || a->arm_layers > 3) return false;
-  if (a->ups_taps != UPS_K) return false;
+  if (a->ups_taps != 4 && a->ups_taps != 8) return false;
+  if (a->ups_shared != 0 && a->ups_shared != 1) return false;
   if (a->syn_hidden < 8 || a->syn_hidden > 48 || a->syn_hidden % 8) return false;
   if (a->syn_res < 1 || a->syn_res > SYN_MAXRES) return false;
   return true;
@@ -62,7 +65,7 @@ bool arch_ok(const cc_arch* a) {
 void counts(const cc_arch* a, int64_t* n_arm, int64_t* n_ups, int64_t* n_syn) {
   const int64_t C = a->arm_ctx, L = a->n_levels, Hs = a->syn_hidden;
   *n_arm = a->arm_layers * (C * C + C) + 2 * C + 2;
-  *n_ups = (L - 1) * 2 * a->ups_taps;
+  *n_ups = L < 2 ? 0 : (a->ups_shared ? (int64_t)a->ups_taps * a->ups_taps : (L - 1) * 2 * a->ups_taps);
   *n_syn = Hs * L + Hs + 3 * Hs + 3 + a->syn_res * 84;
 }
 
@@ -93,6 +96,7 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   const int L = a->n_levels;
   P->C = a->arm_ctx; P->NH = a->arm_layers; P->K = a->ups_taps; P->Hs = a->syn_hidden; P->nres = a->syn_res;
   counts(a, &P->n_arm, &P->n_ups, &P->n_syn);
+  P->shared = a->ups_shared;
   Geo& g = P->geo;
   g.H = p->H; g.W = p->W; g.L = L;
   int off = 0;
@@ -136,8 +140,10 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   P->head_grid = cdiv(p->H, SYN_HD) * cdiv(p->W, SYN_HD);
   P->red_blocks_syn = cdiv(P->nres * 84, RED_CPB) + cdiv(P->n_head, RED_CPB);
   P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
+  // tap-gradient reduction blocks (segments as build_backward lays them out)
   for (int s = 0; s + 1 < L; ++s) {
-    P->red_blocks_ups[s] = cdiv(2 * UPS_K, RED_CPB);
+    if (P->shared) P->red_blocks_ups[s] = s == 0 ? (P->K == 8 ? cdiv(UPS_SHARED_TAPS, RED_CPB) : 4) : 0;
+    else P->red_blocks_ups[s] = P->K == 8 ? cdiv(2 * UPS_K, RED_CPB) : 2;
     P->red_grid += P->red_blocks_ups[s];
   }
 
@@ -154,11 +160,46 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     P->gpt = take(cur, (size_t)3 * p->H * p->W);
     P->wpart_syn = take(cur, (size_t)P->syn_grid * P->nres * 84);
     P->hpart = take(cur, (size_t)P->head_grid * P->n_head);
-    for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->ups_grid[s] * P->ups_chunks[s] * 2 * UPS_K);
+    for (int s = 0; s + 1 < L; ++s) P->up_rows[s] = P->ups_grid[s] * P->ups_chunks[s];
+    if (P->shared) {
+      // one matrix of [all steps' rows][64]: the shared kernel's gradient is
+      // the column sums over every step
+      size_t rows = 0;
+      for (int s = 0; s + 1 < L; ++s) rows += P->up_rows[s];
+      const size_t base = take(cur, rows * UPS_SHARED_TAPS);
+      size_t r = 0;
+      for (int s = 0; s + 1 < L; ++s) {
+        P->upart[s] = base + r * UPS_SHARED_TAPS;
+        r += P->up_rows[s];
+      }
+    } else {
+      for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->up_rows[s] * 2 * UPS_K);
+    }
     P->tslot = take(cur, 1);  // the fused Adam's step number, passed from the side combine to the final one
   }
+  // 4-tap kernels run as 8-tap ones with zero taps on each side
+  P->tapx = take(cur, P->K == 4 && L > 1 ? (P->shared ? UPS_SHARED_TAPS : (size_t)(L - 1) * 2 * UPS_K) : 0);
   P->total = cur;
   return CC_OK;
+}
+
+// The 8-tap form of the upsampling parameters the kernels use: ups_w itself
+// for K = 8, else its zero-padded copy in the workspace (written by
+// launch_expand).
+const float* taps8(const Plan& P, float* ws, const float* ups_w) {
+  return P.K == 8 || P.geo.L < 2 ? ups_w : ws + P.tapx;
+}
+
+int launch_expand(const Plan& P, float* ws, const float* ups_w, hipStream_t st) {
+  if (P.K == 8 || P.geo.L < 2) return CC_OK;
+  const float* src = ups_w;
+  float* dst = ws + P.tapx;
+  int steps = P.geo.L - 1, shared = P.shared;
+  void* argv[] = {&src, &dst, &steps, &shared};
+  const int n = shared ? UPS_SHARED_TAPS : steps * 2 * UPS_K;
+  return hipLaunchKernel((const void*)ups_expand_kernel, dim3(cdiv(n, 64)), dim3(64), argv, 0, st) == hipSuccess
+             ? CC_OK
+             : CC_EHIP;
 }
 
 int launch(const void* fn, int grid, int block, void* args, hipStream_t st) {
@@ -231,7 +272,7 @@ UpsFwdArgs ups_fwd_args(const Plan& P, float* ws, const float* y, const float* u
   const int L = P.geo.L;
   UpsFwdArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.geo = P.geo; a.y = y; a.u = u; a.quant = quant; a.ups_w = ups_w;
+  a.geo = P.geo; a.y = y; a.u = u; a.quant = quant; a.ups_w = taps8(P, ws, ups_w); a.shared = P.shared;
   for (int s = 1; s + 1 < L; ++s) a.up_out[s] = ws + P.up[s];
   *grid = L < 3 ? 0 : cdiv(P.geo.lh[1], UF_T) * cdiv(P.geo.lw[1], UF_T);
   return a;
@@ -242,7 +283,7 @@ int launch_ups_fwd(const Plan& P, float* ws, const float* y, const float* u, int
   int grid = 0;
   UpsFwdArgs a = ups_fwd_args(P, ws, y, u, quant, ups_w, &grid);
   if (!grid) return CC_OK;
-  return launch((const void*)ups_fwd_kernel, grid, 256, &a, st);
+  return launch(ups_fwd_kernel_for(P.shared, false), grid, 256, &a, st);
 }
 
 SynArgs syn_args(const Plan& P, float* ws, const float* y, const float* u, int quant, const float* ups_w,
@@ -250,7 +291,8 @@ SynArgs syn_args(const Plan& P, float* ws, const float* y, const float* u, int q
   SynArgs a;
   std::memset(&a, 0, sizeof(a));
   a.geo = P.geo; a.y = y; a.u = u; a.quant = quant;
-  a.ups0 = ups_w;
+  a.ups0 = taps8(P, ws, ups_w);
+  a.ups_shared = P.shared;
   a.up1 = P.geo.L > 2 ? ws + P.up[1] : nullptr;
   a.w = syn_w;
   a.n_res = P.nres;
@@ -315,6 +357,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   aa.rate_map = rate_map; aa.yq_out = yq_out; aa.rpart = W + P.rpart;
   if ((rc = fork_to(sd, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
+  if ((rc = launch_expand(P, W, ups_w, st))) return rc;
   if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
   sa.img = img;
@@ -369,7 +412,8 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   for (int s = 0; s + 1 < L; ++s) {
     UpsBwdArgs& ua = b->upb[s];
     ua.geo = P.geo; ua.s = s; ua.y = y; ua.u = u; ua.quant = p->quant;
-    ua.taps = ups_w + (size_t)s * 2 * UPS_K;
+    ua.shared = P.shared;
+    ua.taps = P.shared ? taps8(P, W, ups_w) : taps8(P, W, ups_w) + (size_t)s * 2 * UPS_K;
     ua.up_in = (s + 1 <= L - 2) ? W + P.up[s + 1] : nullptr;
     ua.g_in = s == 0 ? W + P.gz : W + P.gb[s];
     ua.g_y = g_y + P.geo.loff[s + 1];
@@ -394,9 +438,9 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   // and folds the context gradients of the other levels
   auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
-    auto add = [&](const float* src, int rows, int cols, float* dst) {
+    auto add = [&](const float* src, int rows, int cols, float* dst, int ld = 0) {
       const int cpb = RED_CPB;
-      ca.seg[ns] = RedSeg{src, rows, cols, cols, cpb, dst};
+      ca.seg[ns] = RedSeg{src, rows, cols, ld ? ld : cols, cpb, dst};
       ca.block_start[ns] = blk;
       blk += cdiv(cols, cpb);
       ++ns;
@@ -406,8 +450,25 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
       add(W + P.hpart, P.head_grid, P.n_head, g_syn);                                 // W1, b1, W2, b2
       add(W + P.wpart_syn, P.syn_grid, P.nres * 84, g_syn + (P.n_syn - P.nres * 84));  // residual convs
     } else {
-      for (int s = 0; s + 1 < L; ++s)
-        add(W + P.upart[s], P.ups_grid[s] * P.ups_chunks[s], 2 * UPS_K, g_ups + (size_t)s * 2 * UPS_K);
+      if (P.shared && L > 1) {
+        // every step's rows of the shared kernel's partials, summed at once
+        int rows = 0;
+        for (int s = 0; s + 1 < L; ++s) rows += P.up_rows[s];
+        if (P.K == 8) {
+          add(W + P.upart[0], rows, UPS_SHARED_TAPS, g_ups);
+        } else {  // the inner 4 x 4 taps of the 8 x 8 gradient
+          for (int r = 0; r < 4; ++r) add(W + P.upart[0] + (r + 2) * UPS_K + 2, rows, 4, g_ups + 4 * r, UPS_SHARED_TAPS);
+        }
+      } else {
+        for (int s = 0; s + 1 < L; ++s) {
+          if (P.K == 8) {
+            add(W + P.upart[s], P.up_rows[s], 2 * UPS_K, g_ups + (size_t)s * 2 * UPS_K);
+          } else {  // the inner 4 taps of each direction
+            add(W + P.upart[s] + 2, P.up_rows[s], 4, g_ups + (size_t)s * 8, 2 * UPS_K);
+            add(W + P.upart[s] + UPS_K + 2, P.up_rows[s], 4, g_ups + (size_t)s * 8 + 4, 2 * UPS_K);
+          }
+        }
+      }
     }
     ca.nseg = ns;
     ca.block_start[ns] = blk;
@@ -498,7 +559,8 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   if (!one_stream && (rc = side_for_current_device(&sd))) return rc;
   hipStream_t side = one_stream ? st : sd->stream;
   (void)hipGetLastError();
-  if (b.upf_grid && (rc = launch((const void*)ups_fwd_kernel, b.upf_grid, 256, &b.upf, st))) return rc;
+  if ((rc = launch_expand(P, (float*)ws, ups_w, st))) return rc;
+  if (b.upf_grid && (rc = launch(ups_fwd_kernel_for(P.shared, false), b.upf_grid, 256, &b.upf, st))) return rc;
   if ((rc = launch(t0k, b.t0_grid, 256, &b.syn, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_SYNTHESIS, bwk, P.syn_grid, SYN_THREADS, &b.syn, st))) return rc;
   // the ARM (independent of the synthesis chain) on the side stream, beside
@@ -511,7 +573,8 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, side))) return rc;
   for (int s = 0; s + 1 < L; ++s) {
     void* argv[] = {&b.upb[s]};
-    if (hipLaunchKernel((const void*)ups_bwd_kernel, dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0, st) !=
+    if (hipLaunchKernel(ups_bwd_kernel_for(P.shared, false), dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0,
+                        st) !=
         hipSuccess)
       return CC_EHIP;
   }
@@ -618,7 +681,7 @@ namespace {
 
 // Host-side plan of a batch.
 struct BatchPlan {
-  int n = 0, L = 0, device = 0;
+  int n = 0, L = 0, device = 0, shared = 0;
   const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr, *hdk = nullptr;
   // device arrays inside the workspace
   ArmArgs* d_arm = nullptr;
@@ -648,6 +711,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     if (rc) return rc;
     const cc_arch &a = probs[k].arch, &a0 = probs[0].arch;
     if (std::memcmp(&a, &a0, sizeof(cc_arch)) || probs[k].quant != probs[0].quant) return CC_EINVAL;
+    if (plans[k].K != 8) return CC_EUNSUPPORTED;  // the batch runs 8-tap upsamplers only
     tiles_arm += plans[k].tiles.n_tiles;
     tiles_syn += plans[k].syn_tiles;
   }
@@ -726,6 +790,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   BatchPlan B;
   B.n = n;
   B.L = L;
+  B.shared = plans[0].shared;
   B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
   B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
   B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
@@ -821,7 +886,7 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   Side* sd = nullptr;
   if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
-  if ((rc = go(CC_STAGE_NONE, (const void*)ups_fwd_kernel_batch, B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
+  if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
   if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
   if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
   if ((rc = fork_to(sd, st))) return rc;
@@ -849,7 +914,7 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   };
   if (BATCH_SIDE_LEVELS == 1 && (rc = side_combine())) return rc;
   for (int s = 0; s + 1 < B.L; ++s) {
-    if ((rc = go(CC_STAGE_NONE, (const void*)ups_bwd_kernel_batch, B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
+    if ((rc = go(CC_STAGE_NONE, ups_bwd_kernel_for(B.shared, true), B.n_upb[s], 256, B.d_upb[s], B.w_upb[s])))
       return rc;
     if (s == 0 && BATCH_SIDE_LEVELS == 2 && (rc = side_combine())) return rc;
   }
@@ -876,6 +941,7 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
   (void)hipGetLastError();
+  if ((rc = launch_expand(P, W, ups_w, st))) return rc;
   if ((rc = launch_ups_fwd(P, W, yq, nullptr, 2, ups_w, st))) return rc;
   SynArgs sa = syn_args(P, W, yq, nullptr, 2, ups_w, syn_w);
   sa.xhat = xhat;

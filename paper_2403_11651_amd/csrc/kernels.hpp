@@ -52,16 +52,22 @@ struct FoldArgs {
 // small tiles fill the device for one image; a batch has work-groups to
 // spare and keeps the halo recompute of larger tiles low
 constexpr int UF_T = 16, UF_T_BATCH = 32;
+// Upsampler kernels: separable, [L-1][2][8] (vertical, horizontal taps per
+// step), or shared (Table I "1-1-TConv-K"): one non-separable [8][8] kernel
+// for every step.  A 4-tap kernel runs as the 8-tap one with two zero taps
+// on each side (same operator: p = 1 for K = 4 against p = 3 for K = 8).
 struct UpsFwdArgs {
   Geo geo;
   const float* y;
   const float* u;
   int quant;
-  const float* ups_w;          // [L-1][2][K] all taps
+  int shared;                  // 0: separable taps, 1: one shared [8][8] kernel
+  const float* ups_w;          // [L-1][2][8] all taps, or [8][8]
   float* up_out[MAXL];         // U_s output [(L-1-s)][h_s][w_s] for s = 1..L-2
 };
-__global__ void ups_fwd_kernel(UpsFwdArgs a);
-__global__ void ups_fwd_kernel_batch(const UpsFwdArgs* d, const WorkItem* w);
+// kernel handles (host stub addresses); batch: the variant taking
+// (const UpsFwdArgs* descs, const WorkItem* work)
+const void* ups_fwd_kernel_for(bool shared, bool batch);
 
 struct UpsBwdArgs {
   Geo geo;
@@ -69,16 +75,20 @@ struct UpsBwdArgs {
   const float* y;
   const float* u;
   int quant;
-  const float* taps;   // [2][K]
+  int shared;          // 0: taps [2][8] of step s; 1: the shared [8][8] kernel
+  const float* taps;   // [2][8] or [8][8]
   const float* up_in;  // forward U_{s+1} output (channels 1.. of stack_{s+1}); null when s = L-2
   const float* g_in;   // [(L-1-s)][h_s][w_s]: gradient of U_s's output
   float* g_y;          // level s+1 of the packed latent gradient (channel 0 of g_stack_{s+1})
   float* g_out;        // [(L-2-s)][h_{s+1}][w_{s+1}]: channels 1.. of g_stack_{s+1}; null when s = L-2
-  float* part;         // [chunks][tiles][2K] tap-gradient partials
+  float* part;         // [chunks][tiles][2K] (separable) or [chunks][tiles][64] (shared) tap-gradient partials
   int cpb;             // channels of stack_{s+1} per block: block (tile, chunk) takes [chunk cpb, chunk cpb + cpb)
 };
-__global__ void ups_bwd_kernel(UpsBwdArgs a);
-__global__ void ups_bwd_kernel_batch(const UpsBwdArgs* d, const WorkItem* w);
+const void* ups_bwd_kernel_for(bool shared, bool batch);
+// 4-tap parameters (separable [L-1][2][4] or shared [4][4]) as 8-tap ones
+// with two zero taps on each side; one thread per output tap
+__global__ void ups_expand_kernel(const float* src, float* dst, int n_steps, int shared);
+constexpr int UPS_SHARED_TAPS = UPS_K * UPS_K;
 
 
 // ---------------------------------------------------------------- synthesis
@@ -98,7 +108,8 @@ struct SynArgs {
   const float* y;
   const float* u;
   int quant;
-  const float* ups0;   // [2][K] taps of step 0
+  int ups_shared;      // 0: ups0 = [2][8] taps of step 0; 1: ups0 = the shared [8][8] kernel
+  const float* ups0;   // taps of step 0
   const float* up1;    // U_1 output (channels 1.. of stack_1); null when L = 2
   const float* w;      // packed synthesis parameters
   int n_res;

@@ -20,10 +20,10 @@
 
 namespace cc {
 
-// The L channels of z at pixel (i, j): y_hat_0 and U_0 of every channel of
-// stack_1 = [y_hat_1, U_1 output].  U_0 runs vertically first (four taps per
-// column, explicit FMAs), then horizontally, in the same order as the tiled
-// computation of syn_t0_body, so both give bit-identical z.
+// The L channels of z at pixel (i, j) are y_hat_0 and U_0 of every channel of
+// stack_1 = [y_hat_1, U_1 output].  A separable U_0 runs vertically first
+// (four taps per column, explicit FMAs), then horizontally; the shared 8 x 8
+// kernel (Table I) takes its 4 x 4 taps of the pixel's parity at once.
 // The four taps of one direction that reach an output of parity `odd`
 // (tap 2q + 1 - odd for the q-th input), selected from the eight taps held
 // in registers (uniform loads, no per-lane indexing).
@@ -41,40 +41,24 @@ __device__ __forceinline__ void load_taps(const float* __restrict__ taps, float 
   }
 }
 
-__device__ __forceinline__ void compute_z(const SynArgs& a, int i, int j, float z[MAXL]) {
-  const int L = a.geo.L, W = a.geo.W, h1 = a.geo.lh[1], w1 = a.geo.lw[1];
-  z[0] = quantise(a.y, a.u, i * W + j, a.quant);
-  int ro[4], co[4];
-  float vt[4], ht[4], kv[UPS_K], kh[UPS_K];
-  load_taps(a.ups0, kv, kh);
-  parity_taps(kv, i & 1, vt);
-  parity_taps(kh, j & 1, ht);
+// Channel c >= 1 of z at pixel (pi, pj) with the shared kernel w2 (LDS,
+// [8][8]) from the stack_1 region st (frame origin (r0, c0), row stride RS1,
+// already clamped to the grid): sum over the 4 x 4 taps of the pixel's parity.
+template <int RS1>
+__device__ __forceinline__ float shared_u0(const float* __restrict__ w2, const float* __restrict__ st, int pi, int pj,
+                                           int r0, int c0) {
+  const int ky0 = 1 - (pi & 1), kx0 = 1 - (pj & 1);
+  float acc = 0.0f;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ky = 2 * q + 1 - (i & 1), kx = 2 * q + 1 - (j & 1);
-    ro[q] = clampi((i + UPS_P - ky) >> 1, 0, h1 - 1);
-    co[q] = clampi((j + UPS_P - kx) >> 1, 0, w1 - 1);
-  }
-  const int lo1 = a.geo.loff[1];
+  for (int q1 = 0; q1 < 4; ++q1) {
+    const int rr = ((pi + UPS_P - (2 * q1 + ky0)) >> 1) - r0;
 #pragma unroll
-  for (int c = 1; c < MAXL; ++c) {
-    z[c] = 0.0f;
-    if (c < L) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int q2 = 0; q2 < 4; ++q2) {
-        float v = 0.0f;
-#pragma unroll
-        for (int q1 = 0; q1 < 4; ++q1) {
-          const int p = ro[q1] * w1 + co[q2];
-          const float val = c == 1 ? quantise(a.y, a.u, lo1 + p, a.quant) : a.up1[(size_t)(c - 2) * h1 * w1 + p];
-          v = __builtin_fmaf(vt[q1], val, v);
-        }
-        acc = __builtin_fmaf(ht[q2], v, acc);
-      }
-      z[c] = acc;
+    for (int q2 = 0; q2 < 4; ++q2) {
+      const int cc = ((pj + UPS_P - (2 * q2 + kx0)) >> 1) - c0;
+      acc = __builtin_fmaf(w2[(2 * q1 + ky0) * UPS_K + 2 * q2 + kx0], st[rr * RS1 + cc], acc);
     }
   }
+  return acc;
 }
 
 // Synthesis weights staged in LDS once per work-group, laid out for 128-bit
@@ -151,7 +135,10 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   __shared__ SynW<HS, NRES> sw;
   __shared__ float s_s[MAXL - 1][RH][RW + 1];
   __shared__ float s_v[MAXL - 1][SYN_T0_H][RW + 1];
+  __shared__ float s_w2[UPS_SHARED_TAPS];
   const int H = a.geo.H, W = a.geo.W, L = a.geo.L, tid = threadIdx.x;
+  const bool shared = a.ups_shared != 0;
+  if (shared && tid < UPS_SHARED_TAPS) s_w2[tid] = a.ups0[tid];
   const int h1 = a.geo.lh[1], w1 = a.geo.lw[1], lo1 = a.geo.loff[1];
   const int ntx = (W + SYN_T0_W - 1) / SYN_T0_W;
   const int i0 = (bid / ntx) * SYN_T0_H, j0 = (bid % ntx) * SYN_T0_W;
@@ -159,7 +146,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   const int nch = L - 1;
   if (bid == 0 && tid == 0 && a.flag_clear) *a.flag_clear = 0.0f;
   float kv[UPS_K], kh[UPS_K];
-  load_taps(a.ups0, kv, kh);
+  load_taps(shared ? nullptr : a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
   batched_stage_stack<((MAXL - 1) * RH * RW + 255) / 256, 256>(
       tid, nch * RH * RW, a.y, a.u, a.quant, a.up1,
@@ -174,7 +161,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
         s_s[c][rem / RW][rem % RW] = v;
       });
   __syncthreads();
-  for (int p = tid; p < nch * SYN_T0_H * RW; p += 256) {
+  for (int p = tid; !shared && p < nch * SYN_T0_H * RW; p += 256) {
     const int c = p / (SYN_T0_H * RW), rem = p % (SYN_T0_H * RW), ti = rem / RW, cc = rem % RW;
     const int i = i0 + ti;
     float vt[4];
@@ -212,8 +199,12 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
     for (int c = 1; c < 7; ++c) {
       float acc = 0.0f;
       if (c < L) {
+        if (shared) {
+          acc = shared_u0<RW + 1>(s_w2, &s_s[c - 1][0][0], pi[n], pj[n], r0, c0);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+          for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+        }
       }
       zz[n][c] = acc;
     }
@@ -688,8 +679,11 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
   const int i0 = (bid / ntx) * T, j0 = (bid % ntx) * T;
   const int r0 = i0 / 2 - 2, c0 = j0 / 2 - 2;
   const int nch = L - 1;
+  const bool shared = a.ups_shared != 0;
+  __shared__ float s_w2[UPS_SHARED_TAPS];
+  if (shared && tid < UPS_SHARED_TAPS) s_w2[tid] = a.ups0[tid];
   float kv[UPS_K], kh[UPS_K];
-  load_taps(a.ups0, kv, kh);
+  load_taps(shared ? nullptr : a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
   // ---- z (the computation of syn_t0_body on this tile)
   batched_stage_stack<((MAXL - 1) * RS * RS + 255) / 256, 256>(
@@ -705,7 +699,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
         s_s[c][rem / RS][rem % RS] = v;
       });
   __syncthreads();
-  for (int p = tid; p < nch * T * RS; p += 256) {
+  for (int p = tid; !shared && p < nch * T * RS; p += 256) {
     const int c = p / (T * RS), rem = p % (T * RS), ti = rem / RS, cc = rem % RS;
     const int i = i0 + ti;
     float vt[4];
@@ -737,8 +731,12 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
     for (int c = 1; c < 7; ++c) {
       float acc = 0.0f;
       if (c < L) {
+        if (shared) {
+          acc = shared_u0<RS + 1>(s_w2, &s_s[c - 1][0][0], pi, pj, r0, c0);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+          for (int q = 0; q < 4; ++q) acc = __builtin_fmaf(ht[q], s_v[c - 1][ti][col[q]], acc);
+        }
       }
       zz[c] = own ? acc : 0.0f;
     }

@@ -2,11 +2,12 @@
 // "TConv", stride 2).
 //
 // stack_{L-1} = y_hat_{L-1}; stack_s = [y_hat_s, U_s(stack_{s+1})].  U_s is a
-// stride-2 transposed convolution with 8 taps per axis, applied as the outer
-// product of a vertical and a horizontal kernel, with input indices clamped
-// to the grid (replicate border):
-//     out[i][j] = sum_{ky, kx} v[ky] h[kx] in[clamp((i+3-ky)/2)][clamp((j+3-kx)/2)]
-// over the taps with (i+3-ky) and (j+3-kx) even (4 x 4 taps per output).
+// stride-2 transposed convolution with 8 taps per axis and input indices
+// clamped to the grid (replicate border):
+//     out[i][j] = sum_{ky, kx} w[ky][kx] in[clamp((i+3-ky)/2)][clamp((j+3-kx)/2)]
+// over the taps with (i+3-ky) and (j+3-kx) even (4 x 4 taps per output), with
+// w[ky][kx] = v[ky] h[kx] for the separable per-step kernels (applied as the
+// outer product) or one non-separable kernel shared by every step (Table I).
 // The step s = 0 is fused into the synthesis kernels; these kernels produce
 // the steps s >= 1 and the adjoint of every step.
 #include "common.hpp"
@@ -24,14 +25,17 @@ namespace cc {
 // lies under its tile, so every output is written exactly once.
 constexpr int UF_CH = MAXL - 1;  // channels of stack_2 at most (L - 2 < 6)
 
-template <int T>
+template <int T, bool SH>
 __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid) {
   constexpr int UF_R = T / 2 + 4;  // largest region side at levels >= 2
   // every level s <= L-2 keeps at least one row / column of the tile to write
   static_assert((T >> (MAXL - 3)) >= 1 && T % 2 == 0, "ups_fwd tile too small");
   __shared__ float s_st[2][UF_CH * UF_R * UF_R];
+  __shared__ float s_w2[SH ? UPS_SHARED_TAPS : 1];
   constexpr int NQ = (UF_R * UF_R + 255) / 256;  // region values per thread at levels >= 2
   const int L = a.geo.L, tid = threadIdx.x;
+  constexpr bool shared = SH;
+  if (shared && tid < UPS_SHARED_TAPS) s_w2[tid] = a.ups_w[tid];
   const int h1 = a.geo.lh[1], w1 = a.geo.lw[1];
   const int ntx = (w1 + T - 1) / T;
   const int r0 = (bid / ntx) * T, c0 = (bid % ntx) * T;
@@ -77,7 +81,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
     if (s > L - 2) continue;
     const float* src = s_st[(s + 1) & 1];
     float* dst = s_st[s & 1];
-    const float* taps = a.ups_w + (size_t)s * 2 * UPS_K;
+    const float* taps = shared ? a.ups_w : a.ups_w + (size_t)s * 2 * UPS_K;
     const int nci = L - 1 - s;  // channels of stack_{s+1}
     const int sr = rb[s + 1] - ra[s + 1], sc = cb[s + 1] - ca[s + 1];
     const int nr = rb[s] - ra[s], nc = cb[s] - ca[s];
@@ -96,19 +100,28 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
         const int ky = 2 * q + 1 - (i & 1), kx = 2 * q + 1 - (j & 1);
         ro[q] = clampi((i + UPS_P - ky) >> 1, 0, hi - 1) - ra[s + 1];
         co[q] = clampi((j + UPS_P - kx) >> 1, 0, wi - 1) - ca[s + 1];
-        vt[q] = taps[ky];
-        ht[q] = taps[UPS_K + kx];
+        vt[q] = shared ? 0.0f : taps[ky];
+        ht[q] = shared ? 0.0f : taps[UPS_K + kx];
       }
       const bool owned = s == 1 || (i >= oa && i < ob && j >= oc && j < od);
+      const int ky0 = 1 - (i & 1), kx0 = 1 - (j & 1);
       for (int c = 0; c < nci; ++c) {
         const float* in = src + c * sr * sc;
         float acc = 0.0f;
+        if constexpr (SH) {
 #pragma unroll
-        for (int q1 = 0; q1 < 4; ++q1) {
-          float rr = 0.0f;
+          for (int q1 = 0; q1 < 4; ++q1)
 #pragma unroll
-          for (int q2 = 0; q2 < 4; ++q2) rr += ht[q2] * in[ro[q1] * sc + co[q2]];
-          acc += vt[q1] * rr;
+            for (int q2 = 0; q2 < 4; ++q2)
+              acc = __builtin_fmaf(s_w2[(2 * q1 + ky0) * UPS_K + 2 * q2 + kx0], in[ro[q1] * sc + co[q2]], acc);
+        } else {
+#pragma unroll
+          for (int q1 = 0; q1 < 4; ++q1) {
+            float rr = 0.0f;
+#pragma unroll
+            for (int q2 = 0; q2 < 4; ++q2) rr += ht[q2] * in[ro[q1] * sc + co[q2]];
+            acc += vt[q1] * rr;
+          }
         }
         if (s > 1) dst[(c + 1) * nr * nc + p] = acc;
         if (owned) up[c * plane + i * ws + j] = acc;
@@ -145,6 +158,7 @@ constexpr int UR_N = 2 * UT + 14;      // output rows / columns read: [2m0-7, 2m
 // fetched into registers while the current one is processed); the tap
 // gradients of all its channels go to one partial row.
 // (explicit FMAs: every kernel built from this body rounds identically)
+template <bool SH>
 __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid, const int ntiles, const int chunk) {
   __shared__ float s_g[UR_N * UR_N];
   __shared__ float s_T[UR_N * UP_N];   // [output row][padded column]
@@ -156,14 +170,21 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
   const int ntx = (wi + UT - 1) / UT;
   const int r0 = (bid / ntx) * UT, c0 = (bid % ntx) * UT;
   const int c_lo = chunk * a.cpb, c_hi = min(L - 1 - s, c_lo + a.cpb);
+  constexpr bool shared = SH;
   float v[UPS_K], hh[UPS_K], gv[UPS_K], gh[UPS_K];
 #pragma unroll
   for (int k = 0; k < UPS_K; ++k) {
-    v[k] = a.taps[k];
-    hh[k] = a.taps[UPS_K + k];
+    v[k] = shared ? 0.0f : a.taps[k];
+    hh[k] = shared ? 0.0f : a.taps[UPS_K + k];
     gv[k] = 0.0f;
     gh[k] = 0.0f;
   }
+  // shared kernel: its taps and their gradients (one accumulator per tap)
+  __shared__ float s_w2[SH ? UPS_SHARED_TAPS : 1];
+  float gw[SH ? UPS_SHARED_TAPS : 1];
+#pragma unroll
+  for (int k = 0; k < (SH ? UPS_SHARED_TAPS : 1); ++k) gw[k] = 0.0f;
+  if (shared && tid < UPS_SHARED_TAPS) s_w2[tid] = a.taps[tid];
   const int jr0 = 2 * r0 - 7, jc0 = 2 * c0 - 7;
   const int lo = a.geo.loff[s + 1];
   float pf[NPF];
@@ -204,7 +225,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     float inval = 0.0f;
     if (in_tile)
       inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant) : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
-    for (int p = t; p < UR_N * UP_N; p += 256) {
+    for (int p = t; !shared && p < UR_N * UP_N; p += 256) {
       {  // T[row][pc] = sum_kx h[kx] g[row][2 pc + kx]
         const int row = p / UP_N, pc = p % UP_N;
         float acc = 0.0f;
@@ -224,8 +245,16 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     for (int p = t; p < UP_N * UP_N; p += 256) {
       const int pr = p / UP_N, pc = p % UP_N;
       float acc = 0.0f;
+      if constexpr (SH) {  // g_pad[pr][pc] = sum_{ky, kx} w[ky][kx] g[2 pr + ky][2 pc + kx]
 #pragma unroll
-      for (int k = 0; k < UPS_K; ++k) acc = __builtin_fmaf(v[k], s_T[(2 * pr + k) * UP_N + pc], acc);
+        for (int ky = 0; ky < UPS_K; ++ky)
+#pragma unroll
+          for (int kx = 0; kx < UPS_K; ++kx)
+            acc = __builtin_fmaf(s_w2[ky * UPS_K + kx], s_g[(2 * pr + ky) * UR_N + 2 * pc + kx], acc);
+      } else {
+#pragma unroll
+        for (int k = 0; k < UPS_K; ++k) acc = __builtin_fmaf(v[k], s_T[(2 * pr + k) * UP_N + pc], acc);
+      }
       s_P[p] = acc;
     }
     __syncthreads();
@@ -238,10 +267,19 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
         for (int j = 0; j < 5; ++j) {
           if (cb[j] < 0) continue;
           gsum += s_P[ca[i] * UP_N + cb[j]];
+          if constexpr (SH) {
 #pragma unroll
-          for (int k = 0; k < UPS_K; ++k) {
-            gv[k] = __builtin_fmaf(inval, s_T[(2 * ca[i] + k) * UP_N + cb[j]], gv[k]);
-            gh[k] = __builtin_fmaf(inval, s_T2[ca[i] * UR_N + 2 * cb[j] + k], gh[k]);
+            for (int ky = 0; ky < UPS_K; ++ky)
+#pragma unroll
+              for (int kx = 0; kx < UPS_K; ++kx)
+                gw[ky * UPS_K + kx] =
+                    __builtin_fmaf(inval, s_g[(2 * ca[i] + ky) * UR_N + 2 * cb[j] + kx], gw[ky * UPS_K + kx]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < UPS_K; ++k) {
+              gv[k] = __builtin_fmaf(inval, s_T[(2 * ca[i] + k) * UP_N + cb[j]], gv[k]);
+              gh[k] = __builtin_fmaf(inval, s_T2[ca[i] * UR_N + 2 * cb[j] + k], gh[k]);
+            }
           }
         }
       }
@@ -250,34 +288,69 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     }
     __syncthreads();
   }
-  __shared__ float s_red[4][2 * UPS_K];
+  constexpr int ncol = SH ? UPS_SHARED_TAPS : 2 * UPS_K;
+  __shared__ float s_red[4][ncol];
   const int lane = tid & 63, wave = tid >> 6;
+  if constexpr (SH) {
 #pragma unroll
-  for (int k = 0; k < UPS_K; ++k) {
-    const float a0 = wave_sum(gv[k]), a1 = wave_sum(gh[k]);
-    if (lane == 0) { s_red[wave][k] = a0; s_red[wave][UPS_K + k] = a1; }
+    for (int k = 0; k < UPS_SHARED_TAPS; ++k) {
+      const float a0 = wave_sum(gw[k]);
+      if (lane == 0) s_red[wave][k] = a0;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < UPS_K; ++k) {
+      const float a0 = wave_sum(gv[k]), a1 = wave_sum(gh[k]);
+      if (lane == 0) { s_red[wave][k] = a0; s_red[wave][UPS_K + k] = a1; }
+    }
   }
   __syncthreads();
-  if (tid < 2 * UPS_K) {
+  if (tid < ncol) {
     float acc = 0.0f;
     for (int wv = 0; wv < 4; ++wv) acc += s_red[wv][tid];
-    a.part[((size_t)chunk * ntiles + bid) * 2 * UPS_K + tid] = acc;
+    a.part[((size_t)chunk * ntiles + bid) * ncol + tid] = acc;
   }
 }
 
-__global__ __launch_bounds__(256) void ups_fwd_kernel(UpsFwdArgs a) { ups_fwd_body<UF_T>(a, blockIdx.x); }
-__global__ __launch_bounds__(256) void ups_fwd_kernel_batch(const UpsFwdArgs* __restrict__ d,
-                                                            const WorkItem* __restrict__ w) {
-  const WorkItem it = w[blockIdx.x];
-  ups_fwd_body<UF_T_BATCH>(d[it.img], it.bid);
+__global__ void ups_expand_kernel(const float* __restrict__ src, float* __restrict__ dst, int n_steps, int shared) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (shared) {
+    if (t >= UPS_SHARED_TAPS) return;
+    const int ky = t / UPS_K - 2, kx = t % UPS_K - 2;
+    dst[t] = (ky >= 0 && ky < 4 && kx >= 0 && kx < 4) ? src[ky * 4 + kx] : 0.0f;
+  } else {
+    if (t >= n_steps * 2 * UPS_K) return;
+    const int row = t / UPS_K, k = t % UPS_K - 2;
+    dst[t] = (k >= 0 && k < 4) ? src[row * 4 + k] : 0.0f;
+  }
 }
-__global__ __launch_bounds__(256) void ups_bwd_kernel(UpsBwdArgs a) {
-  ups_bwd_body(a, blockIdx.x, gridDim.x, blockIdx.y);
-}
-__global__ __launch_bounds__(256) void ups_bwd_kernel_batch(const UpsBwdArgs* __restrict__ d,
-                                                            const WorkItem* __restrict__ w) {
+
+template <bool SH>
+__global__ __launch_bounds__(256) void ups_fwd_kernel_t(UpsFwdArgs a) { ups_fwd_body<UF_T, SH>(a, blockIdx.x); }
+template <bool SH>
+__global__ __launch_bounds__(256) void ups_fwd_kernel_batch_t(const UpsFwdArgs* __restrict__ d,
+                                                              const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
-  ups_bwd_body(d[it.img], it.bid, it.nblk, it.aux);
+  ups_fwd_body<UF_T_BATCH, SH>(d[it.img], it.bid);
+}
+template <bool SH>
+__global__ __launch_bounds__(256) void ups_bwd_kernel_t(UpsBwdArgs a) {
+  ups_bwd_body<SH>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+template <bool SH>
+__global__ __launch_bounds__(256) void ups_bwd_kernel_batch_t(const UpsBwdArgs* __restrict__ d,
+                                                              const WorkItem* __restrict__ w) {
+  const WorkItem it = w[blockIdx.x];
+  ups_bwd_body<SH>(d[it.img], it.bid, it.nblk, it.aux);
+}
+
+const void* ups_fwd_kernel_for(bool shared, bool batch) {
+  if (batch) return shared ? (const void*)ups_fwd_kernel_batch_t<true> : (const void*)ups_fwd_kernel_batch_t<false>;
+  return shared ? (const void*)ups_fwd_kernel_t<true> : (const void*)ups_fwd_kernel_t<false>;
+}
+const void* ups_bwd_kernel_for(bool shared, bool batch) {
+  if (batch) return shared ? (const void*)ups_bwd_kernel_batch_t<true> : (const void*)ups_bwd_kernel_batch_t<false>;
+  return shared ? (const void*)ups_bwd_kernel_t<true> : (const void*)ups_bwd_kernel_t<false>;
 }
 
 }  // namespace cc

@@ -24,8 +24,12 @@ class Case:
 
 
 def sizes(arch):
-    L, C, NH, K, Hs, R = arch
-    return NH * (C * C + C) + 2 * C + 2, (L - 1) * 2 * K, Hs * L + Hs + 3 * Hs + 3 + R * 84
+    """(n_arm, n_ups, n_syn) of an architecture tuple (n_levels, arm_ctx,
+    arm_layers, ups_taps, syn_hidden, syn_res[, ups_shared])."""
+    L, C, NH, K, Hs, R = arch[:6]
+    shared = len(arch) > 6 and arch[6]
+    n_ups = 0 if L < 2 else (K * K if shared else (L - 1) * 2 * K)
+    return NH * (C * C + C) + 2 * C + 2, n_ups, Hs * L + Hs + 3 * Hs + 3 + R * 84
 
 
 def n_latents(H, W, L):

@@ -31,6 +31,20 @@ def test_param_counts_match_oracle(B):
         assert B.param_count(B.Arch(*arch)) == O.param_sizes(O.Arch(*arch))
 
 
+def test_table1_param_counts_through_the_c_abi(B):
+    """Table I's four decoders (shared K x K upsampler): 281 / 525 / 941 /
+    1925 parameters, as the oracle counts them from the paper's layers."""
+    rows = {300: (7, 8, 1, 4, 8, 1, 1), 545: (7, 8, 2, 4, 16, 2, 1), 1079: (7, 16, 2, 4, 16, 2, 1),
+            2300: (7, 24, 2, 8, 40, 2, 1)}
+    expect = {300: 281, 545: 525, 1079: 941, 2300: 1925}
+    for k, arch in rows.items():
+        assert sum(B.param_count(B.Arch(*arch))) == expect[k], k
+        o = O.TABLE1[k]
+        assert B.param_count(B.Arch(*arch)) == O.param_sizes(o)
+    # separable 4-tap upsampler: [L-1][2][4]
+    assert B.param_count(B.Arch(7, 8, 2, 4, 16, 1))[1] == 6 * 2 * 4
+
+
 def test_latent_count_and_workspace(B):
     p = B.Problem(512, 768)
     assert B.latent_count(p) == 524256
@@ -45,7 +59,7 @@ def test_latent_count_and_workspace(B):
     (0, 768, (7, 24, 2, 8, 40, 2), 0, -1),
     (512, 768, (7, 24, 2, 8, 40, 2), 5, -1),   # unknown quantiser
     (512, 768, (7, 12, 2, 8, 40, 2), 0, -2),   # context width not compiled
-    (512, 768, (7, 24, 2, 4, 40, 2), 0, -2),   # 4-tap upsampler not compiled
+    (512, 768, (7, 24, 2, 6, 40, 2), 0, -2),   # 6-tap upsampler not compiled
     (512, 768, (7, 24, 2, 8, 44, 2), 0, -2),   # hidden width not a multiple of 8
     (512, 768, (7, 24, 2, 8, 40, 3), 0, -2),   # three residual convs
     (1024, 1024, (9, 24, 2, 8, 40, 2), 0, -2),  # more than 7 levels
@@ -202,3 +216,12 @@ def test_train_step_noalloc_rejects_before_touching_the_device(B):
     assert B.workspace_bytes(fits, 1) <= B.CC_NOALLOC_SCRATCH_BYTES
     assert call(fits, theta=None) == -1
     assert call(fits, b1=1.0) == -1
+
+
+def test_batch_refuses_four_tap_upsamplers(B):
+    """The batched entry points run 8-tap upsamplers only: a 4-tap
+    architecture gets no workspace size and no plan."""
+    p = B.Problem(64, 64, B.Arch(7, 8, 1, 4, 8, 1, 1))
+    assert B.batch_workspace_bytes([p]) == 0
+    q = B.Problem(64, 64, B.Arch(7, 24, 2, 8, 40, 2, 1))
+    assert B.batch_workspace_bytes([q]) > 0

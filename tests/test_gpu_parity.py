@@ -27,9 +27,7 @@ def _dev(a):
 
 
 def _problem(B, c):
-    L, C, NH, K, Hs, R = c.arch
-    return B.Problem(c.H, c.W, B.Arch(L, C, NH, K, Hs, R), B.CC_QUANT_NOISE if c.u is not None else B.CC_QUANT_ROUND,
-                     c.lam)
+    return B.Problem(c.H, c.W, B.Arch(*c.arch), B.CC_QUANT_NOISE if c.u is not None else B.CC_QUANT_ROUND, c.lam)
 
 
 def gpu_forward(B, c):
