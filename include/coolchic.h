@@ -340,6 +340,20 @@ int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const 
                                 const float* g_theta, float* loss4, float* g_net, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* Quantisation of the decoder parameters (Section II: after the encoding the
+   network parameters are quantised and entropy coded with an ad-hoc
+   probability model).  Each module m (0 ARM, 1 upsampling, 2 synthesis) on a
+   grid of step 2^-k, k = step_log2[m] (host array, 0..24): q = rint(theta
+   2^k) (ties to even), theta_hat = q 2^-k, both exact in float32; written to
+   arm_q / ups_q / syn_q (device, laid out like the inputs; they may alias
+   them).  bits (device float [3]): the rate of each module, the sum over its
+   parameters of -log2 of the Laplace(0, b) mass over [q - 1/2, q + 1/2] with
+   b = max(mean |q|, 0.01).  ups_w / ups_q may be NULL when the architecture
+   has no upsampling parameters. */
+int coolchic_param_quantize(const cc_arch* arch, const float* arm_w, const float* ups_w, const float* syn_w,
+                            const int32_t* step_log2, float* arm_q, float* ups_q, float* syn_q, float* bits,
+                            void* stream);
+
 /* ---- Entropy coding of the latents (Section II: the latent grids are sent
    with a range coder driven by the ARM p_psi; Section III-B: the decoder's
    ARM runs latent after latent).  The probability of a latent is the

@@ -49,7 +49,7 @@ __all__ = [
     "rate_bits", "rate_grads", "log_laplace_mass", "tconv1d", "tconv1d_adjoint", "upsample2x",
     "tconv2d", "tconv2d_adjoint", "upsample_step",
     "upsample_pyramid", "conv3x3_replicate", "synthesis", "forward", "backward",
-    "adam_step", "S_MIN", "S_MAX",
+    "adam_step", "S_MIN", "S_MAX", "param_rate_bits", "quantize_params", "PARAM_B_MIN",
 ]
 
 
@@ -632,3 +632,36 @@ def adam_step(theta, g, m, v, t, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ----------------------------------------------------------------------------
+# quantisation of the decoder parameters (Section II: after the encoding the
+# network parameters are quantised and entropy coded with an ad-hoc
+# probability model)
+# ----------------------------------------------------------------------------
+PARAM_B_MIN = 0.01   # smallest Laplace scale of the parameter model (reading)
+
+
+def param_rate_bits(q):
+    """Bits of the integer vector q under the Laplace(0, b) model with b the
+    mean |q| (its maximum-likelihood scale), at least PARAM_B_MIN: the sum of
+    -log2 of the mass over [q - 1/2, q + 1/2]."""
+    q = np.asarray(q, np.float64)
+    if q.size == 0:
+        return 0.0
+    b = max(float(np.mean(np.abs(q))), PARAM_B_MIN)
+    return float(np.sum(-log_laplace_mass(q, np.zeros_like(q), np.full_like(q, b)) / LN2))
+
+
+def quantize_params(arm_w, ups_w, syn_w, step_log2):
+    """Each module (ARM, upsampling, synthesis) on its own grid of step
+    2^-k, k = step_log2[m]: q = rint(theta 2^k), theta_hat = q 2^-k.
+    Returns (arm_hat, ups_hat, syn_hat, bits [3], q blocks)."""
+    outs, bits, qs = [], [], []
+    for w, k in zip((arm_w, ups_w, syn_w), step_log2):
+        w = np.asarray(w, np.float64)
+        q = np.rint(w * 2.0 ** k)
+        outs.append(q * 2.0 ** -k)
+        bits.append(param_rate_bits(q))
+        qs.append(q)
+    return outs[0], outs[1], outs[2], np.array(bits), qs

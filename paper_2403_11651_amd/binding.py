@@ -29,7 +29,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_uniform_noise", "coolchic_warm_backward_grad", "coolchic_timing_event_create",
            "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy", "coolchic_train_step",
            "coolchic_train_step_noalloc", "coolchic_entropy_workspace_bytes", "coolchic_entropy_bound",
-           "coolchic_entropy_tables", "coolchic_entropy_encode", "coolchic_entropy_decode")
+           "coolchic_entropy_tables", "coolchic_entropy_encode", "coolchic_entropy_decode",
+           "coolchic_param_quantize")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -91,6 +92,7 @@ def _load():
         "coolchic_batch_backward": (I, [P, P]),
         "coolchic_batch_destroy": (None, [P]),
         "coolchic_uniform_noise": (I, [P, I64, ctypes.c_uint64, P, ctypes.c_uint32, P]),
+        "coolchic_param_quantize": (I, [pa, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P, P, P, P]),
         "coolchic_entropy_workspace_bytes": (SZ, [pp]),
         "coolchic_entropy_bound": (I64, [pp]),
         "coolchic_entropy_tables": (I, [P, P]),
@@ -279,6 +281,19 @@ def coolchic_train_step_noalloc(p: Problem, img, u, dloss, loss4, theta, grad, m
                                           _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
                                           _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
     _check(rc, "coolchic_train_step_noalloc")
+
+
+def coolchic_param_quantize(arch: Arch, arm_w, ups_w, syn_w, step_log2, arm_q, ups_q, syn_q, bits, stream=None):
+    """Each module on a grid of step 2^-k (k from step_log2, three ints);
+    quantised values into *_q, the modules' rates (bits) into the device
+    float tensor bits [3]."""
+    na, nu, ns = param_count(arch)
+    ks = (ctypes.c_int32 * 3)(*[int(k) for k in step_log2])
+    rc = _lib.coolchic_param_quantize(ctypes.byref(arch.c()), _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"),
+                                      _ptr(syn_w, ns, "syn_w"), ks, _ptr(arm_q, na, "arm_q"),
+                                      _ptr(ups_q, nu, "ups_q"), _ptr(syn_q, ns, "syn_q"), _ptr(bits, 3, "bits"),
+                                      _stream(stream))
+    _check(rc, "coolchic_param_quantize")
 
 
 def entropy_workspace(p: Problem, device="cuda") -> torch.Tensor:

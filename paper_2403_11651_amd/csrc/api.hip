@@ -1015,6 +1015,37 @@ int coolchic_timing_event_destroy(void* ev) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- parameter quantisation
+
+extern "C" int coolchic_param_quantize(const cc_arch* arch, const float* arm_w, const float* ups_w,
+                                       const float* syn_w, const int32_t* step_log2, float* arm_q, float* ups_q,
+                                       float* syn_q, float* bits, void* stream) {
+  if (!arch || !step_log2 || !bits) return CC_EINVAL;
+  if (!arch_ok(arch)) return CC_EUNSUPPORTED;
+  int64_t na = 0, nu = 0, ns = 0;
+  counts(arch, &na, &nu, &ns);
+  if (!arm_w || !arm_q || !syn_w || !syn_q || (nu && (!ups_w || !ups_q))) return CC_EINVAL;
+  ParamQArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const float* src[3] = {arm_w, ups_w, syn_w};
+  float* dst[3] = {arm_q, ups_q, syn_q};
+  const int64_t n[3] = {na, nu, ns};
+  for (int m = 0; m < 3; ++m) {
+    if (step_log2[m] < 0 || step_log2[m] > 24) return CC_EINVAL;
+    a.src[m] = src[m];
+    a.dst[m] = dst[m];
+    a.n[m] = (int)n[m];
+    a.k[m] = step_log2[m];
+  }
+  a.bits = bits;
+  (void)hipGetLastError();
+  void* argv[] = {&a};
+  if (hipLaunchKernel((const void*)param_quant_kernel, dim3(3), dim3(256), argv, 0, (hipStream_t)stream) !=
+      hipSuccess)
+    return CC_EHIP;
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
 // ---------------------------------------------------------------- entropy coding
 
 namespace cc {

@@ -195,6 +195,17 @@ template <bool VEC>
 __global__ void adam_kernel(AdamArgs a);
 __global__ void noise_kernel(float* u, int64_t n, uint32_t k0, uint32_t k1, const int32_t* step, uint32_t stream_id);
 
+// ---------------------------------------------------------------- parameter quantisation
+constexpr float PARAM_B_MIN = 0.01f;  // smallest Laplace scale of the parameter model
+struct ParamQArgs {
+  const float* src[3];   // ARM, upsampling, synthesis parameters
+  float* dst[3];         // their quantised values (may alias src)
+  int n[3];
+  int k[3];              // step 2^-k per module
+  float* bits;           // [3] rate of each module, bits
+};
+__global__ void param_quant_kernel(ParamQArgs a);
+
 // ---------------------------------------------------------------- entropy coding
 // Interleaved rANS over the latents with the ARM's Laplace probabilities
 // (quantised per latent to a table row) and the wavefront decode order.

@@ -615,3 +615,24 @@ def test_adam_matches_torch_optim_varying_gradients(betas):
         assert np.allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-15), t
         assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-13, atol=0), t
         assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=0), t
+
+
+# ---------------------------------------------------------------- parameter quantisation
+def test_param_quantisation_hand_values():
+    # step 2^-3 = 0.125: 0.3 -> rint(2.4) = 2 -> 0.25; -0.0625 -> rint(-0.5) = -0 (ties to even)
+    a, u, s, bits, qs = O.quantize_params([0.3, -0.0625, 0.1875], [1.0], [-2.6], [3, 0, 1])
+    assert list(a) == [0.25, -0.0, 0.25] and list(qs[0]) == [2.0, -0.0, 2.0]
+    assert list(u) == [1.0] and list(s) == [-2.5]
+
+
+def test_param_rate_against_scipy_laplace():
+    """The parameter rate is -log2 of the Laplace(0, mean|q|) mass, from
+    scipy's CDF; an all-zero block costs n (-log2 (1 - e^(-1/(2 b_min))))."""
+    import scipy.stats
+    q = np.array([0.0, 1.0, -3.0, 7.0, 0.0, 2.0, -1.0])
+    b = np.mean(np.abs(q))
+    ref = -np.log2(scipy.stats.laplace.cdf(q + 0.5, 0.0, b) - scipy.stats.laplace.cdf(q - 0.5, 0.0, b)).sum()
+    assert abs(O.param_rate_bits(q) - ref) <= 1e-9 * ref
+    z = np.zeros(11)
+    assert abs(O.param_rate_bits(z) - 11 * -math.log2(1.0 - math.exp(-0.5 / O.PARAM_B_MIN))) <= 1e-12
+    assert O.param_rate_bits(np.zeros(0)) == 0.0
