@@ -172,13 +172,21 @@ def codec_record(B, enc, log=None):
     and the decode time (entropy decoding with the ARM, then upsampling and
     synthesis) per image."""
     import torch
+    from paper_2403_11651_amd.paramq import quantize_decoder
     dev = enc.device
-    tot_bits = tot_info = tot_R = tot_px = 0.0
-    ratios, enc_ms, dec_ms, syn_ms = [], [], [], []
+    tot_bits = tot_info = tot_R = tot_px = tot_pbits = tot_R_unq = 0.0
+    ratios, enc_ms, dec_ms, syn_ms, psnr_q, psnr_unq, steps = [], [], [], [], [], [], []
     stream = torch.cuda.current_stream()
     for k, p in enumerate(enc.problems):
-        y, arm, ups, syn = enc._views(enc.theta, k)
+        y, arm0, ups0, syn0 = enc._views(enc.theta, k)
         n_lat = y.numel()
+        # the decoder's parameters quantised first: a decoder only knows those
+        qd = quantize_decoder(p, enc.images[k], y, arm0, ups0, syn0)
+        arm, ups, syn = qd["arm"], qd["ups"], qd["syn"]
+        tot_pbits += sum(qd["bits"])
+        steps.append(qd["steps"])
+        psnr_unq.append(-10.0 * np.log10(float(enc.loss[k, 1].item())))
+        tot_R_unq += float(enc.loss[k, 2].item())
         yq = torch.empty(n_lat, device=dev)
         loss4 = torch.zeros(4, device=dev)
         B.coolchic_forward(p, enc.images[k], y, None, arm, ups, syn, loss4, yq_out=yq)
@@ -214,6 +222,7 @@ def codec_record(B, enc, log=None):
         x = data[8 + 4 * n_sets:head].view(np.uint32).astype(np.float64)
         info = 8.0 * (n - head) + float(np.log2(x / 2.0 ** 23).sum())
         R = float(loss4[2].item())
+        psnr_q.append(-10.0 * np.log10(float(loss4[1].item())))
         tot_bits += 8.0 * n
         tot_info += info
         tot_R += R
@@ -222,12 +231,20 @@ def codec_record(B, enc, log=None):
         dec_ms.append(e[1].elapsed_time(e[2]))
         syn_ms.append(e[2].elapsed_time(e[3]))
     if log:
-        log(f"codec: {tot_bits / tot_px:.4f} bpp coded, proxy {tot_R / tot_px:.4f} bpp")
-    return {"workload": "the 32 batch-trained images: latents rounded by coolchic_forward, coded with each image's "
-                        "trained ARM (coolchic_entropy_encode), decoded (coolchic_entropy_decode) and synthesised "
-                        "(coolchic_decode_synth) one image at a time",
+        log(f"codec: {tot_bits / tot_px:.4f} bpp latents coded + {tot_pbits / tot_px:.4f} bpp parameters, "
+            f"latent proxy {tot_R / tot_px:.4f} bpp")
+    return {"workload": "the 32 batch-trained images: decoder parameters quantised (coolchic_param_quantize, steps "
+                        "chosen per module on the rate-distortion cost), latents rounded by coolchic_forward and "
+                        "coded with the quantised ARM (coolchic_entropy_encode), decoded (coolchic_entropy_decode) "
+                        "and synthesised with the quantised decoder (coolchic_decode_synth), one image at a time",
             "bpp_bitstream": round(tot_bits / tot_px, 5), "bpp_payload_information": round(tot_info / tot_px, 5),
             "bpp_rate_proxy": round(tot_R / tot_px, 5),
+            "bpp_parameters": round(tot_pbits / tot_px, 5),
+            "bpp_total": round((tot_bits + tot_pbits) / tot_px, 5),
+            "bpp_rate_proxy_unquantised_decoder": round(tot_R_unq / tot_px, 5),
+            "psnr_db_mean_quantised_decoder": round(float(np.mean(psnr_q)), 4),
+            "psnr_db_mean_unquantised_decoder": round(float(np.mean(psnr_unq)), 4),
+            "parameter_steps_log2_first_images": [list(s) for s in steps[:4]],
             "bitstream_over_proxy": round(tot_bits / tot_R, 5), "payload_over_proxy": round(tot_info / tot_R, 5),
             "per_image_ratio_range": [round(min(ratios), 4), round(max(ratios), 4)],
             "round_trip": "exact for every image",
