@@ -45,7 +45,7 @@ S_MAX = math.log(100.0)
 __all__ = [
     "Arch", "TINY", "FULL", "LOW", "FD16", "TABLE1", "param_sizes", "unpack", "pack",
     "table1_param_count", "mac_per_pixel", "level_shapes", "split_levels",
-    "quantise", "context_offsets", "gather_context", "arm_forward", "laplace_mass",
+    "quantise", "quantise_grad", "soft_round", "soft_round_grad", "context_offsets", "gather_context", "arm_forward", "laplace_mass",
     "rate_bits", "rate_grads", "log_laplace_mass", "tconv1d", "tconv1d_adjoint", "upsample2x",
     "tconv2d", "tconv2d_adjoint", "upsample_step",
     "upsample_pyramid", "conv3x3_replicate", "synthesis", "forward", "backward",
@@ -205,15 +205,45 @@ def split_levels(vec, H, W, L):
     return out
 
 
-def quantise(y, u=None):
+def soft_round(x, alpha):
+    """Soft rounding (Agustsson & Theis, "Universally quantized neural
+    compression", 2020): floor(x) + 1/2 + tanh(alpha r) / (2 tanh(alpha / 2))
+    with r = x - floor(x) - 1/2; it passes through every integer and half
+    integer, tends to rounding as alpha grows and to the identity as alpha
+    goes to 0."""
+    x = np.asarray(x, dtype=np.float64)
+    fl = np.floor(x)
+    return fl + 0.5 + np.tanh(alpha * (x - fl - 0.5)) / (2.0 * np.tanh(alpha / 2.0))
+
+
+def soft_round_grad(x, alpha):
+    """d soft_round / dx = alpha (1 - tanh^2(alpha r)) / (2 tanh(alpha / 2))."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.tanh(alpha * (x - np.floor(x) - 0.5))
+    return alpha * (1.0 - t * t) / (2.0 * np.tanh(alpha / 2.0))
+
+
+def quantise(y, u=None, alpha=None):
     """y_hat = Q(y) (Section II "Encoding").  Without noise: round to the
     nearest integer, ties to even; its gradient is taken as the identity
     (straight-through).  With noise u in [-1/2, 1/2): y_hat = y + u, the
-    additive-noise proxy, whose gradient is the identity too."""
+    additive-noise proxy, whose gradient is the identity too.  With alpha
+    (the proxy C3 uses, cited in Section II): y_hat = s(s(y) + u) with s the
+    soft rounding of sharpness alpha; its gradient is s'(s(y) + u) s'(y)."""
     y = np.asarray(y, dtype=np.float64)
+    if alpha is not None:
+        return soft_round(soft_round(y, alpha) + np.asarray(u, dtype=np.float64), alpha)
     if u is None:
         return np.rint(y)
     return y + np.asarray(u, dtype=np.float64)
+
+
+def quantise_grad(y, u, alpha):
+    """dy_hat/dy of the soft proxy (1 for the other two)."""
+    y = np.asarray(y, dtype=np.float64)
+    if alpha is None:
+        return np.ones_like(y)
+    return soft_round_grad(soft_round(y, alpha) + np.asarray(u, dtype=np.float64), alpha) * soft_round_grad(y, alpha)
 
 
 # ----------------------------------------------------------------------------
@@ -475,15 +505,16 @@ def _as64(*arrs):
     return [None if a is None else np.asarray(a, dtype=np.float64) for a in arrs]
 
 
-def forward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None):
+def forward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None, soft_alpha=None):
     """Eq. (1): loss = D + lambda * R / (H W), D = mean over 3HW of
     (x_hat - x)^2, R = sum of the per-latent rates in bits.  Returns a dict
-    with loss, D, R, the per-latent rate map, y_hat, x_hat, mu and s."""
+    with loss, D, R, the per-latent rate map, y_hat, x_hat, mu and s.
+    soft_alpha: the soft-rounding proxy of :func:`quantise` (u required)."""
     img, y, u = _as64(img, y, u)
     _, H, W = img.shape
     L = arch.n_levels
     P = unpack(arch, arm_w, ups_w, syn_w)
-    yq = quantise(y, u)
+    yq = quantise(y, u, soft_alpha)
     levels = split_levels(yq, H, W, L)
     offs = context_offsets(arch.arm_ctx)
     mus, ss = [], []
@@ -521,17 +552,18 @@ def _conv3x3_adjoint(g, t, W):
     return gp[:, 1:H + 1, 1:Wd + 1], gW
 
 
-def backward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None, dloss=1.0):
+def backward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None, dloss=1.0, soft_alpha=None):
     """Hand-written reverse mode of :func:`forward` (Section IV-A: each layer
     returns the gradient w.r.t. its weights and w.r.t. its input).  The
     quantiser passes the gradient through unchanged (straight-through for
-    rounding, exact for additive noise).  ReLU'(0) = 0.  Returns the forward
-    dict plus g_y, g_arm, g_ups, g_syn (flat, laid out like the inputs)."""
+    rounding, exact for additive noise); the soft proxy multiplies it by its
+    derivative.  ReLU'(0) = 0.  Returns the forward dict plus g_y, g_arm,
+    g_ups, g_syn (flat, laid out like the inputs)."""
     img, y, u = _as64(img, y, u)
     _, H, W = img.shape
     L = arch.n_levels
     P = unpack(arch, arm_w, ups_w, syn_w)
-    yq = quantise(y, u)
+    yq = quantise(y, u, soft_alpha)
     levels = split_levels(yq, H, W, L)
     offs = context_offsets(arch.arm_ctx)
     shapes = level_shapes(H, W, L)
@@ -613,7 +645,7 @@ def backward(arch: Arch, img, y, arm_w, ups_w, syn_w, lam, u=None, dloss=1.0):
         g_stack = g_src
     g_levels[L - 1] += g_stack[0]
 
-    g_y = np.concatenate([g.ravel() for g in g_levels])
+    g_y = np.concatenate([g.ravel() for g in g_levels]) * quantise_grad(y, u, soft_alpha)
     g_arm, g_ups, g_syn = pack(arch, G)
     rate = np.concatenate(rates)
     loss = D + lam * R / (H * W)

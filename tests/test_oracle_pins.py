@@ -353,10 +353,10 @@ def _fd_instance(arch=O.FD16):
     return arch, img, y, u, w[:n_arm], w[n_arm:n_arm + n_ups], w[n_arm + n_ups:]
 
 
-def _kink_margin(arch, img, y, u, arm, ups, syn):
+def _kink_margin(arch, img, y, u, arm, ups, syn, alpha=None):
     """Smallest distance of any ReLU / clamp input to its kink."""
     P = O.unpack(arch, arm, ups, syn)
-    yq = O.quantise(y, u)
+    yq = O.quantise(y, u, alpha)
     H, W = img.shape[1:]
     levels = O.split_levels(yq, H, W, arch.n_levels)
     offs = O.context_offsets(arch.arm_ctx)
@@ -636,3 +636,53 @@ def test_param_rate_against_scipy_laplace():
     z = np.zeros(11)
     assert abs(O.param_rate_bits(z) - 11 * -math.log2(1.0 - math.exp(-0.5 / O.PARAM_B_MIN))) <= 1e-12
     assert O.param_rate_bits(np.zeros(0)) == 0.0
+
+
+# ---------------------------------------------------------------- soft rounding (C3's proxy)
+def test_soft_round_closed_forms_and_limits():
+    """s passes through every integer and half integer (r = -1/2, 0), is odd,
+    tends to rounding (alpha -> inf) and to the identity (alpha -> 0)."""
+    for a in (0.5, 3.0, 10.0):
+        x = np.array([-3.0, -2.5, -1.0, -0.5, 0.0, 0.5, 1.0, 4.5, 7.0])
+        assert np.allclose(O.soft_round(x, a), x, rtol=0, atol=1e-12)
+        z = np.linspace(-3.2, 3.2, 97)
+        assert np.allclose(O.soft_round(-z, a), -O.soft_round(z, a), rtol=0, atol=1e-12)
+        assert np.all(np.diff(O.soft_round(np.linspace(-2, 2, 401), a)) > 0)
+    z = np.array([0.3, 0.7, 1.2, -1.8, 2.05])
+    assert np.allclose(O.soft_round(z, 400.0), np.rint(z), rtol=0, atol=1e-12)
+    assert np.allclose(O.soft_round(z, 1e-4), z, rtol=0, atol=1e-8)
+
+
+def test_soft_round_gradient_and_proxy_against_differences():
+    h = 1e-6
+    x = np.linspace(-2.3, 2.3, 41) + 0.013
+    u = np.random.default_rng(3).uniform(-0.5, 0.5, x.size)
+    for a in (1.0, 4.0):
+        fd = (O.soft_round(x + h, a) - O.soft_round(x - h, a)) / (2 * h)
+        assert np.allclose(O.soft_round_grad(x, a), fd, rtol=1e-6, atol=1e-8)
+        fq = (O.quantise(x + h, u, a) - O.quantise(x - h, u, a)) / (2 * h)
+        assert np.allclose(O.quantise_grad(x, u, a), fq, rtol=1e-6, atol=1e-8)
+
+
+def test_backward_matches_central_differences_soft_16x16():
+    """The whole loss with the soft-rounding proxy (alpha = 3): the hand
+    adjoint against central differences, every latent and parameter."""
+    arch, img, y, u, arm, ups, syn = _fd_instance(O.FD16)
+    a = 3.0
+    assert _kink_margin(arch, img, y, u, arm, ups, syn, a) > 1e-5
+    lam = 0.001
+    out = O.backward(arch, img, y, arm, ups, syn, lam, u=u, soft_alpha=a)
+    f = lambda yy, aa, p, s: O.forward(arch, img, yy, aa, p, s, lam, u=u, soft_alpha=a)["loss"]  # noqa: E731
+    h = 1e-6
+    checks = [("g_y", y, lambda v: (v, arm, ups, syn)),
+              ("g_arm", arm, lambda v: (y, v, ups, syn)),
+              ("g_syn", syn, lambda v: (y, arm, ups, v))]
+    for name, base, mk in checks:
+        g = out[name]
+        fd = np.empty_like(base)
+        for i in range(base.size):
+            vp = base.copy(); vp[i] += h
+            vm = base.copy(); vm[i] -= h
+            fd[i] = (f(*mk(vp)) - f(*mk(vm))) / (2 * h)
+        scale = np.max(np.abs(g))
+        assert np.max(np.abs(fd - g)) <= 1e-6 * scale + 1e-9, (name, np.max(np.abs(fd - g)), scale)
