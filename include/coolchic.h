@@ -73,14 +73,20 @@ typedef struct {
 } cc_arch;
 
 /* Quantisation proxy Q (Section II "Encoding"): rounding to nearest (ties to
-   even) with a straight-through gradient, or additive noise y + u with
-   u in [-1/2, 1/2) supplied by the caller. */
-enum { CC_QUANT_ROUND = 0, CC_QUANT_NOISE = 1 };
+   even) with a straight-through gradient; additive noise y + u with u in
+   [-1/2, 1/2) supplied by the caller (identity gradient); or the proxy of C3
+   that Section II cites, y_hat = s(s(y) + u) with s the soft rounding
+   s(x) = floor(x) + 1/2 + tanh(a r) / (2 tanh(a/2)), r = x - floor(x) - 1/2
+   (Agustsson & Theis 2020), gradient s'(s(y) + u) s'(y).  For
+   CC_QUANT_SOFT the noise buffer u holds N_lat + 1 floats: the noise, then
+   the sharpness a > 0 (read on the device, so a captured graph can anneal
+   it). */
+enum { CC_QUANT_ROUND = 0, CC_QUANT_NOISE = 1, CC_QUANT_SOFT = 2 };
 
 typedef struct {
   int32_t H, W;     /* image rows and columns; both multiples of 2^(L-1) */
   cc_arch arch;
-  int32_t quant;    /* CC_QUANT_ROUND or CC_QUANT_NOISE */
+  int32_t quant;    /* CC_QUANT_ROUND, CC_QUANT_NOISE or CC_QUANT_SOFT */
   float lambda;     /* rate weight of Eq. (1) */
 } cc_problem;
 

@@ -39,6 +39,9 @@ class BatchEncoder:
     the Philox generator keyed by `noise_seed` and the step counter."""
 
     def __init__(self, problems, images, y0, params0, lr=1e-2, tune=(0, 0), noise_seed=0, device="cuda"):
+        """The noise buffer holds, per image, its latents' noise followed by one
+        float: the soft proxy's sharpness (CC_QUANT_SOFT reads it there), copied
+        from the device scalar self.alpha after every draw."""
         n = len(problems)
         if not (n and len(images) == n and len(y0) == n and len(params0) == n):
             raise ValueError("problems, images, y0 and params0 must be equally long and non-empty")
@@ -57,7 +60,7 @@ class BatchEncoder:
             n_lat = B.latent_count(p)
             self.seg.append((off, n_lat, uoff))
             off += n_lat + na + nu + ns
-            uoff += n_lat
+            uoff += n_lat + 1
         self.n_params = off
         flat = np.empty(off, np.float32)
         for (o, n_lat, _), y, (a, u, s) in zip(self.seg, y0, params0):
@@ -71,6 +74,8 @@ class BatchEncoder:
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
         self.u = torch.zeros(uoff, device=dev)
+        self.alpha = torch.ones(1, device=dev)
+        self._alpha_idx = torch.tensor([uo + n for _, n, uo in self.seg], dtype=torch.int64, device=dev)
         self.step_ctr = torch.zeros(2, dtype=torch.int32, device=dev)
         self.loss = torch.zeros(n, 4, device=dev)
         self.images = [torch.from_numpy(np.ascontiguousarray(x, np.float32).reshape(-1)).to(dev) for x in images]
@@ -100,7 +105,8 @@ class BatchEncoder:
                 y, a, u, s = self._views(self.theta, k)
                 gy, ga, gu, gs = self._views(self.grad, k)
                 _, n_lat, uo = self.seg[k]
-                io.append(dict(img=self.images[k], y=y, u=self.u[uo:uo + n_lat] if mode == B.CC_QUANT_NOISE else None,
+                noise = {B.CC_QUANT_NOISE: n_lat, B.CC_QUANT_SOFT: n_lat + 1}.get(mode)
+                io.append(dict(img=self.images[k], y=y, u=self.u[uo:uo + noise] if noise else None,
                                arm_w=a, ups_w=u, syn_w=s, loss4=self.loss[k], g_y=gy, g_arm=ga, g_ups=gu, g_syn=gs))
             probs = [dataclasses.replace(p, quant=mode) for p in self.problems]
             self.plans[mode] = B.BatchPlan(probs, io, tune=self.tune, device=self.device)
@@ -116,19 +122,24 @@ class BatchEncoder:
         self.plan = self._plan(self.mode)
 
     def set_mode(self, mode):
-        """CC_QUANT_ROUND or CC_QUANT_NOISE for the following iterations."""
-        if mode not in (B.CC_QUANT_ROUND, B.CC_QUANT_NOISE):
+        """CC_QUANT_ROUND, CC_QUANT_NOISE or CC_QUANT_SOFT for the following
+        iterations."""
+        if mode not in (B.CC_QUANT_ROUND, B.CC_QUANT_NOISE, B.CC_QUANT_SOFT):
             raise ValueError("unknown quantisation mode")
         self.mode = mode
         self.plan = self._plan(mode)
 
     def _draw(self, stream=None):
         B.coolchic_uniform_noise(self.u, self.noise_seed, step=self.step_ctr, stream=stream)
+        if self.mode == B.CC_QUANT_SOFT:
+            # the sharpness after each image's noise (a device copy: a graph
+            # replay reads the current self.alpha)
+            self.u.index_copy_(0, self._alpha_idx, self.alpha.expand(len(self.seg)))
 
     def backward(self, stream=None):
         """Loss and gradients of every image (written to self.loss, self.grad)
         at the current parameters, in the current mode."""
-        if self.mode == B.CC_QUANT_NOISE:
+        if self.mode in (B.CC_QUANT_NOISE, B.CC_QUANT_SOFT):
             self._draw(stream)
         self.plan.backward(stream)
 
@@ -174,12 +185,32 @@ class BatchEncoder:
         for _ in range(rem):
             self.step()
 
-    def fit(self, iters, noise_frac=0.8, graph_steps=50):
-        """The two-phase schedule: noise proxy for the first noise_frac of the
-        iterations, then rounding with the straight-through gradient."""
+    def fit(self, iters, noise_frac=0.8, graph_steps=50, proxy="noise", t_start=0.3, t_end=0.1):
+        """The two-phase schedule: a differentiable proxy for the first
+        noise_frac of the iterations, then rounding with the straight-through
+        gradient.  proxy "noise": y + u; "soft": C3's soft rounding s(s(y) +
+        u) with the temperature 1 / alpha annealed linearly from t_start to
+        t_end over the first phase (stepped once per graph of graph_steps
+        iterations)."""
         n_noise = int(round(iters * noise_frac))
-        self.set_mode(B.CC_QUANT_NOISE)
-        self.run(n_noise, graph_steps)
+        if proxy == "soft":
+            self.set_mode(B.CC_QUANT_SOFT)
+            g = self.capture(graph_steps) if n_noise >= graph_steps > 0 else None
+            done = 0
+            while done < n_noise:
+                k = graph_steps if g is not None and n_noise - done >= graph_steps else 1
+                frac = (done + 0.5 * k) / max(n_noise, 1)
+                self.alpha.fill_(1.0 / (t_start + (t_end - t_start) * frac))
+                if k == graph_steps and g is not None:
+                    g.replay()
+                else:
+                    self.step()
+                done += k
+        elif proxy == "noise":
+            self.set_mode(B.CC_QUANT_NOISE)
+            self.run(n_noise, graph_steps)
+        else:
+            raise ValueError("proxy is 'noise' or 'soft'")
         self.set_mode(B.CC_QUANT_ROUND)
         self.run(iters - n_noise, graph_steps)
 

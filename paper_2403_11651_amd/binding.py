@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoolchic
 
 CC_OK, CC_EINVAL, CC_EUNSUPPORTED, CC_EWORKSPACE, CC_EHIP, CC_ESCRATCH = 0, -1, -2, -3, -4, -5
 CC_NOALLOC_SCRATCH_BYTES = 64 << 20
-CC_QUANT_ROUND, CC_QUANT_NOISE = 0, 1
+CC_QUANT_ROUND, CC_QUANT_NOISE, CC_QUANT_SOFT = 0, 1, 2
 CC_WS_FORWARD, CC_WS_BACKWARD, CC_WS_DECODE = 0, 1, 2
 
 # every symbol the header declares
@@ -199,6 +199,12 @@ def _check(rc, where):
         raise CoolChicError(rc, where)
 
 
+def _n_noise(p: Problem, n_lat: int) -> int:
+    """Floats of the noise buffer: the soft proxy stores its sharpness after
+    the noise."""
+    return n_lat + 1 if p.quant == CC_QUANT_SOFT else n_lat
+
+
 def coolchic_forward(p: Problem, img, y, u, arm_w, ups_w, syn_w, loss4, rate_map=None, yq_out=None, xhat_out=None,
                      ws=None, stream=None):
     n_lat = latent_count(p)
@@ -206,7 +212,8 @@ def coolchic_forward(p: Problem, img, y, u, arm_w, ups_w, syn_w, loss4, rate_map
     hw3 = 3 * p.H * p.W
     if ws is None:
         ws = workspace(p, CC_WS_FORWARD, device=y.device)
-    rc = _lib.coolchic_forward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"), _ptr(u, n_lat, "u"),
+    rc = _lib.coolchic_forward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"),
+                               _ptr(u, _n_noise(p, n_lat), "u"),
                                _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
                                _ptr(loss4, 4, "loss4"), _ptr(rate_map, n_lat, "rate_map"),
                                _ptr(yq_out, n_lat, "yq_out"), _ptr(xhat_out, hw3, "xhat_out"),
@@ -221,7 +228,8 @@ def coolchic_backward(p: Problem, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, 
     hw3 = 3 * p.H * p.W
     if ws is None:
         ws = workspace(p, CC_WS_BACKWARD, device=y.device)
-    rc = _lib.coolchic_backward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"), _ptr(u, n_lat, "u"),
+    rc = _lib.coolchic_backward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"),
+                                _ptr(u, _n_noise(p, n_lat), "u"),
                                 _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
                                 float(dloss), _ptr(loss4, 4, "loss4"), _ptr(g_y, n_lat, "g_y"),
                                 _ptr(g_arm, na, "g_arm"), _ptr(g_ups, nu, "g_ups"), _ptr(g_syn, ns, "g_syn"),
@@ -260,7 +268,7 @@ def coolchic_train_step(p: Problem, img, u, dloss, loss4, theta, grad, m, v, ste
         raise TypeError("step must be a device int32 tensor of 2 elements: steps taken, completion counter (0)")
     if ws is None:
         ws = workspace(p, CC_WS_BACKWARD, device=theta.device)
-    rc = _lib.coolchic_train_step(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"), _ptr(u, n_lat, "u"),
+    rc = _lib.coolchic_train_step(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"), _ptr(u, _n_noise(p, n_lat), "u"),
                                   float(dloss), _ptr(loss4, 4, "loss4"), _ptr(theta, n, "theta"),
                                   _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"), _ptr(step, 2, "step"),
                                   lr, beta1, beta2, eps, _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
@@ -276,7 +284,8 @@ def coolchic_train_step_noalloc(p: Problem, img, u, dloss, loss4, theta, grad, m
     n = n_lat + na + nu + ns
     if step.dtype != torch.int32 or step.numel() != 2:
         raise TypeError("step must be a device int32 tensor of 2 elements: steps taken, completion counter (0)")
-    rc = _lib.coolchic_train_step_noalloc(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"), _ptr(u, n_lat, "u"),
+    rc = _lib.coolchic_train_step_noalloc(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"),
+                                          _ptr(u, _n_noise(p, n_lat), "u"),
                                           float(dloss), _ptr(loss4, 4, "loss4"), _ptr(theta, n, "theta"),
                                           _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"),
                                           _ptr(step, 2, "step"), lr, beta1, beta2, eps, _stream(stream))
@@ -402,7 +411,7 @@ class BatchPlan:
         for k, (p, d) in enumerate(zip(probs, io)):
             n_lat = latent_count(p)
             na, nu, ns = param_count(p.arch)
-            sizes = {"img": 3 * p.H * p.W, "y": n_lat, "u": n_lat, "arm_w": na, "ups_w": nu, "syn_w": ns,
+            sizes = {"img": 3 * p.H * p.W, "y": n_lat, "u": _n_noise(p, n_lat), "arm_w": na, "ups_w": nu, "syn_w": ns,
                      "loss4": 4, "g_y": n_lat, "g_arm": na, "g_ups": nu, "g_syn": ns}
             for name, size in sizes.items():
                 setattr(ios[k], name, _ptr(d.get(name), size, f"io[{k}].{name}"))

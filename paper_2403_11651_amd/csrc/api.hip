@@ -29,6 +29,10 @@ static_assert(BATCH_SIDE_LEVELS == 1 || BATCH_SIDE_LEVELS == 2, "side combine af
 constexpr int ARM_DEFAULT_GRID = 384;
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+// quantiser mode of the kernels: the public modes, with the soft proxy as 3
+// (2 is the kernels' "latents used as given" of the decode path)
+inline int kmode(int quant) { return quant == CC_QUANT_SOFT ? QMODE_SOFT : quant; }
+inline bool needs_noise(int quant) { return quant == CC_QUANT_NOISE || quant == CC_QUANT_SOFT; }
 inline int t0_tiles(int H, int W) { return cdiv(H, SYN_T0_H) * cdiv(W, SYN_T0_W); }
 
 struct Plan {
@@ -77,7 +81,7 @@ int check_problem(const cc_problem* p) {
   if (p->H <= 0 || p->W <= 0 || p->H > 16384 || p->W > 16384) return CC_EINVAL;
   const int m = 1 << (a->n_levels - 1);
   if (p->H % m || p->W % m) return CC_EINVAL;
-  if (p->quant != CC_QUANT_ROUND && p->quant != CC_QUANT_NOISE) return CC_EINVAL;
+  if (p->quant != CC_QUANT_ROUND && p->quant != CC_QUANT_NOISE && p->quant != CC_QUANT_SOFT) return CC_EINVAL;
   if (!arch_ok(a)) return CC_EUNSUPPORTED;
   return CC_OK;
 }
@@ -340,7 +344,7 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   int rc = make_plan(p, CC_WS_FORWARD, &P);
   if (rc) return rc;
   if (!img || !y || !arm_w || (!ups_w && P.n_ups) || !syn_w || !loss4 || !ws) return CC_EINVAL;
-  if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
+  if (needs_noise(p->quant) && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   const void* armk = arm_kernel_for(P.C, P.NH, false, false);
   const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *resk = syn_res_fwd_kernel_for(P.Hs, P.nres, false);
@@ -353,13 +357,13 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   (void)hipGetLastError();
   ArmArgs aa;
   std::memset(&aa, 0, sizeof(aa));
-  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
+  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = kmode(p->quant); aa.w = arm_w;
   aa.rate_map = rate_map; aa.yq_out = yq_out; aa.rpart = W + P.rpart;
   if ((rc = fork_to(sd, st))) return rc;
   if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &aa, sd->stream))) return rc;
   if ((rc = launch_expand(P, W, ups_w, st))) return rc;
-  if ((rc = launch_ups_fwd(P, W, y, u, p->quant, ups_w, st))) return rc;
-  SynArgs sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
+  if ((rc = launch_ups_fwd(P, W, y, u, kmode(p->quant), ups_w, st))) return rc;
+  SynArgs sa = syn_args(P, W, y, u, kmode(p->quant), ups_w, syn_w);
   sa.img = img;
   sa.xhat = xhat_out;
   sa.spart = W + P.spart;
@@ -393,12 +397,12 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   const int L = P.geo.L;
   const float HW = (float)p->H * p->W;
   ArmArgs& aa = b->arm;
-  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = p->quant; aa.w = arm_w;
+  aa.geo = P.geo; aa.tiles = P.tiles; aa.y = y; aa.u = u; aa.quant = kmode(p->quant); aa.w = arm_w;
   aa.scale = dloss * p->lambda / HW;
   aa.gext = W + P.gext; aa.wpart = W + P.wpart_arm; aa.rpart = W + P.rpart;
-  b->upf = ups_fwd_args(P, W, y, u, p->quant, ups_w, &b->upf_grid);
+  b->upf = ups_fwd_args(P, W, y, u, kmode(p->quant), ups_w, &b->upf_grid);
   SynArgs& sa = b->syn;
-  sa = syn_args(P, W, y, u, p->quant, ups_w, syn_w);
+  sa = syn_args(P, W, y, u, kmode(p->quant), ups_w, syn_w);
   sa.img = img;
   sa.dscale = dloss * 2.0f / (3.0f * HW);
   sa.g_y = g_y;
@@ -411,7 +415,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   b->t0_grid = t0_tiles(p->H, p->W);
   for (int s = 0; s + 1 < L; ++s) {
     UpsBwdArgs& ua = b->upb[s];
-    ua.geo = P.geo; ua.s = s; ua.y = y; ua.u = u; ua.quant = p->quant;
+    ua.geo = P.geo; ua.s = s; ua.y = y; ua.u = u; ua.quant = kmode(p->quant);
     ua.shared = P.shared;
     ua.taps = P.shared ? taps8(P, W, ups_w) : taps8(P, W, ups_w) + (size_t)s * 2 * UPS_K;
     ua.up_in = (s + 1 <= L - 2) ? W + P.up[s + 1] : nullptr;
@@ -476,6 +480,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ca.bad = loss4 + 3;
     ca.loss_block = -1;
     ca.fold.geo = P.geo; ca.fold.tiles = P.tiles; ca.fold.gext = W + P.gext; ca.fold.g_y = g_y;
+    ca.fold.y = y; ca.fold.u = u; ca.fold.quant = kmode(p->quant);
     if (final_part) {
       ca.fold.q0 = P.fold_split; ca.fold.q1 = P.geo.n_lat;
       // at least one block: with a single level (no taps, every latent
@@ -539,7 +544,7 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   if (!img || !y || !arm_w || (!ups_w && P.n_ups) || !syn_w || !loss4 || !g_y || !g_arm || (!g_ups && P.n_ups) ||
       !g_syn || !ws)
     return CC_EINVAL;
-  if (p->quant == CC_QUANT_NOISE && !u) return CC_EINVAL;
+  if (needs_noise(p->quant) && !u) return CC_EINVAL;
   if (ws_bytes < P.total * sizeof(float)) return CC_EWORKSPACE;
   const void* armk = arm_kernel_for(P.C, P.NH, true, false);
   const void *t0k = syn_t0_kernel_for(P.Hs, P.nres, false), *bwk = syn_bwd_kernel_for(P.Hs, P.nres, false);
@@ -783,7 +788,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     if (!q.img || !q.y || !q.arm_w || (!q.ups_w && plans[k].n_ups) || !q.syn_w || !q.loss4 || !q.g_y || !q.g_arm ||
         (!q.g_ups && plans[k].n_ups) || !q.g_syn)
       return CC_EINVAL;
-    if (probs[k].quant == CC_QUANT_NOISE && !q.u) return CC_EINVAL;
+    if (needs_noise(probs[k].quant) && !q.u) return CC_EINVAL;
   }
   const Plan& P0 = plans[0];
   const int L = P0.geo.L;

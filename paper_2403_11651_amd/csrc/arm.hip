@@ -106,6 +106,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
   // thread; the next tile's are fetched while the current one is processed
   constexpr int NPF = (ARM_EXT + ARM_THREADS - 1) / ARM_THREADS;
   float pf[NPF], pu[NPF];  // raw latents (and noise), quantised when staged
+  const float alpha = proxy_alpha(a.u, a.quant, a.geo.n_lat);
   auto fetch = [&](int tile) {
     int l = 0;
     while (l + 1 < a.geo.L && tile >= a.tiles.base[l + 1]) ++l;
@@ -120,7 +121,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
       pu[q] = 0.0f;
       if (idx < ARM_EXT && ii >= 0 && ii < h && jj >= 0 && jj < wl) {
         pf[q] = a.y[base + ii * wl + jj];
-        if (a.quant == 1) pu[q] = a.u[base + ii * wl + jj];
+        if (uses_noise(a.quant)) pu[q] = a.u[base + ii * wl + jj];
       }
     }
   };
@@ -136,7 +137,7 @@ __device__ __forceinline__ void arm_body(const ArmArgs& a, const int bid, const 
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       const int idx = tid + ARM_THREADS * q;
-      if (idx < ARM_EXT) s_yq[idx] = quantise_raw(pf[q], pu[q], a.quant);
+      if (idx < ARM_EXT) s_yq[idx] = quantise_raw(pf[q], pu[q], a.quant, alpha);
     }
     __syncthreads();
     if (tile + nblk < a.tiles.n_tiles) fetch(tile + nblk);

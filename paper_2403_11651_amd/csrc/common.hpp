@@ -21,22 +21,45 @@ struct Geo {
   int lh[MAXL + 1], lw[MAXL + 1], loff[MAXL + 1];
 };
 
-// Quantisation proxy: 0 = round half to even (straight-through gradient),
-// 1 = additive noise y + u, 2 = values used as given (already quantised).
-__device__ __forceinline__ float quantise(const float* __restrict__ y, const float* __restrict__ u, int q,
-                                          int mode) {
-  float v = y[q];
-  if (mode == 0) return __builtin_rintf(v);
-  if (mode == 1) return v + u[q];
-  return v;
+// Soft rounding (Agustsson & Theis 2020) of sharpness a: floor(x) + 1/2 +
+// tanh(a r) / (2 tanh(a/2)), r = x - floor(x) - 1/2, and its derivative.
+__device__ __forceinline__ float soft_round(float x, float a) {
+  const float fl = floorf(x);
+  return fl + 0.5f + tanhf(a * (x - fl - 0.5f)) / (2.0f * tanhf(0.5f * a));
+}
+__device__ __forceinline__ float soft_round_grad(float x, float a) {
+  const float t = tanhf(a * (x - floorf(x) - 0.5f));
+  return a * (1.0f - t * t) / (2.0f * tanhf(0.5f * a));
 }
 
-// The same from values already read (uv is read only for mode 1), so that a
-// thread can issue all its reads before it uses any.
-__device__ __forceinline__ float quantise_raw(float yv, float uv, int mode) {
+// Quantisation proxy: 0 = round half to even (straight-through gradient),
+// 1 = additive noise y + u, 2 = values used as given (already quantised),
+// 3 = C3's proxy s(s(y) + u), s the soft rounding of sharpness alpha (read
+// by each kernel from u[N_lat]).
+constexpr int QMODE_SOFT = 3;
+__device__ __forceinline__ bool uses_noise(int mode) { return mode == 1 || mode == QMODE_SOFT; }
+
+__device__ __forceinline__ float quantise_raw(float yv, float uv, int mode, float alpha = 0.0f) {
   if (mode == 0) return __builtin_rintf(yv);
   if (mode == 1) return yv + uv;
+  if (mode == QMODE_SOFT) return soft_round(soft_round(yv, alpha) + uv, alpha);
   return yv;
+}
+
+__device__ __forceinline__ float quantise(const float* __restrict__ y, const float* __restrict__ u, int q, int mode,
+                                          float alpha = 0.0f) {
+  return quantise_raw(y[q], uses_noise(mode) ? u[q] : 0.0f, mode, alpha);
+}
+
+// dy_hat / dy of the proxy (1 except for the soft one).
+__device__ __forceinline__ float quantise_grad(float yv, float uv, int mode, float alpha) {
+  if (mode != QMODE_SOFT) return 1.0f;
+  return soft_round_grad(soft_round(yv, alpha) + uv, alpha) * soft_round_grad(yv, alpha);
+}
+
+// The soft proxy's sharpness, stored after the noise of the N_lat latents.
+__device__ __forceinline__ float proxy_alpha(const float* __restrict__ u, int mode, int n_lat) {
+  return mode == QMODE_SOFT ? u[n_lat] : 0.0f;
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -98,7 +121,7 @@ __device__ __forceinline__ void batched_stage(int tid, int n, Load load, Store s
 // planes[idx] (already a stack channel).  All reads first, then the writes.
 template <int NQ, int NT, typename Src, typename Store>
 __device__ __forceinline__ void batched_stage_stack(int tid, int n, const float* __restrict__ y,
-                                                    const float* __restrict__ u, int mode,
+                                                    const float* __restrict__ u, int mode, float alpha,
                                                     const float* __restrict__ planes, Src src, Store store) {
   float ry[NQ], ru[NQ];
   bool lat[NQ];
@@ -115,7 +138,7 @@ __device__ __forceinline__ void batched_stage_stack(int tid, int n, const float*
       lat[q] = is_lat;
       if (is_lat) {
         ry[q] = y[idx];
-        if (mode == 1) ru[q] = u[idx];
+        if (uses_noise(mode)) ru[q] = u[idx];
       } else {
         ry[q] = planes[idx];
       }
@@ -124,7 +147,7 @@ __device__ __forceinline__ void batched_stage_stack(int tid, int n, const float*
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int p = tid + NT * q;
-    if (p < n) store(p, lat[q] ? quantise_raw(ry[q], ru[q], mode) : ry[q]);
+    if (p < n) store(p, lat[q] ? quantise_raw(ry[q], ru[q], mode, alpha) : ry[q]);
   }
 }
 

@@ -44,6 +44,10 @@ struct FoldArgs {
   float* g_y;
   int q0, q1;          // the latents [q0, q1) of the packed pyramid
   float *th, *m, *v;   // fused Adam: the latents and their moments (indexed like g_y)
+  // the soft proxy (quant 3): its derivative multiplies the folded gradient
+  const float* y;
+  const float* u;
+  int quant;
 };
 
 

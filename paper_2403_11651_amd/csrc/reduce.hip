@@ -51,7 +51,9 @@ __device__ bool arm_fold_one(const FoldArgs& a, int q, const AD& ad, float k1, f
   float G = 0.0f;
 #pragma unroll
   for (int k = 0; k < 6; ++k) G += f[k];
-  const float v = gy + G;
+  float v = gy + G;
+  // the gradient so far is w.r.t. y_hat; the soft proxy's derivative takes it to y
+  if (a.quant == QMODE_SOFT) v *= quantise_grad(a.y[q], a.u[q], a.quant, a.u[a.geo.n_lat]);
   a.g_y[q] = v;
   if (ad.on) {
     adam_apply(ad.lr, ad.beta1, ad.beta2, ad.eps, k1, k2, th, v, m, vv);

@@ -149,7 +149,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   load_taps(shared ? nullptr : a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
   batched_stage_stack<((MAXL - 1) * RH * RW + 255) / 256, 256>(
-      tid, nch * RH * RW, a.y, a.u, a.quant, a.up1,
+      tid, nch * RH * RW, a.y, a.u, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat), a.up1,
       [&](int p, int& idx, bool& is_lat) {
         const int c = p / (RH * RW), rem = p % (RH * RW), rr = rem / RW, cc = rem % RW;
         const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
@@ -186,7 +186,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
     pi[n] = i0 + ti;
     pj[n] = j0 + tj;
     const int i = min(pi[n], H - 1), j = min(pj[n], W - 1);  // ragged tiles: computed, not stored
-    zz[n][0] = quantise(a.y, a.u, i * W + j, a.quant);
+    zz[n][0] = quantise(a.y, a.u, i * W + j, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat));
     int col[4];
     float ht[4];
     parity_taps(kh, pj[n] & 1, ht);
@@ -687,7 +687,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
   stage_weights(sw, a.w, L, tid);
   // ---- z (the computation of syn_t0_body on this tile)
   batched_stage_stack<((MAXL - 1) * RS * RS + 255) / 256, 256>(
-      tid, nch * RS * RS, a.y, a.u, a.quant, a.up1,
+      tid, nch * RS * RS, a.y, a.u, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat), a.up1,
       [&](int p, int& idx, bool& is_lat) {
         const int c = p / (RS * RS), rem = p % (RS * RS), rr = rem / RS, cc = rem % RS;
         const int q = clampi(r0 + rr, 0, h1 - 1) * w1 + clampi(c0 + cc, 0, w1 - 1);
@@ -717,7 +717,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
   const bool own = pi < H && pj < W;
   const int i = min(pi, H - 1), j = min(pj, W - 1);
   float zz[8], gpt[3], gz[7];
-  zz[0] = own ? quantise(a.y, a.u, i * W + j, a.quant) : 0.0f;
+  zz[0] = own ? quantise(a.y, a.u, i * W + j, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat)) : 0.0f;
   {
     int col[4];
     float ht[4];

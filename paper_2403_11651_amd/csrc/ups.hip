@@ -48,6 +48,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
   }
   // the latents of every level's region (channel 0 of its stack), all read up
   // front; quantised where they are used
+  const float alpha = proxy_alpha(a.u, a.quant, a.geo.n_lat);
   float py[MAXL][NQ], pu[MAXL][NQ];
 #pragma unroll
   for (int l = 2; l < MAXL; ++l)
@@ -60,7 +61,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
         const int nc = cb[l] - ca[l];
         const int idx = a.geo.loff[l] + (ra[l] + p / nc) * a.geo.lw[l] + ca[l] + p % nc;
         py[l][q] = a.y[idx];
-        if (a.quant == 1) pu[l][q] = a.u[idx];
+        if (uses_noise(a.quant)) pu[l][q] = a.u[idx];
       }
     }
   // stack_{L-1} = y_hat_{L-1} on its region
@@ -72,7 +73,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int p = tid + 256 * q;
-        if (p < n) dst[p] = quantise_raw(py[l][q], pu[l][q], a.quant);
+        if (p < n) dst[p] = quantise_raw(py[l][q], pu[l][q], a.quant, alpha);
       }
     }
   __syncthreads();
@@ -131,7 +132,7 @@ __device__ __forceinline__ void ups_fwd_body(const UpsFwdArgs& a, const int bid)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int p = tid + 256 * q;
-        if (p < nr * nc) dst[p] = quantise_raw(py[s][q], pu[s][q], a.quant);
+        if (p < nr * nc) dst[p] = quantise_raw(py[s][q], pu[s][q], a.quant, alpha);
       }
     }
     __syncthreads();
@@ -224,7 +225,8 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     const int idx = r * wi + c;
     float inval = 0.0f;
     if (in_tile)
-      inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant) : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
+      inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat))
+                      : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
     for (int p = t; !shared && p < UR_N * UP_N; p += 256) {
       {  // T[row][pc] = sum_kx h[kx] g[row][2 pc + kx]
         const int row = p / UP_N, pc = p % UP_N;

@@ -139,12 +139,14 @@ def test_batch_noise_mode_vs_oracle(B, BT):
     enc.set_mode(B.CC_QUANT_NOISE)
     enc.backward()
     torch.cuda.synchronize()
-    u_all = NZ.uniform_noise(sum(c.y.size for c in cs), 77, it=0)
+    # the encoder's noise buffer: each image's noise, then one float (the
+    # soft proxy's sharpness slot)
+    u_all = NZ.uniform_noise(sum(c.y.size + 1 for c in cs), 77, it=0)
     L = enc.loss.cpu().numpy()
     o = 0
     for k, c in enumerate(cs):
         u = u_all[o:o + c.y.size]
-        o += c.y.size
+        o += c.y.size + 1
         ref = O.backward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=u)
         assert abs(L[k, 0] - ref["loss"]) <= 1e-5 * abs(ref["loss"])
         for name, g in zip(("g_y", "g_arm", "g_ups", "g_syn"), enc.grads(k)):
@@ -233,3 +235,42 @@ def test_bench_batch_sampled(B, BT):
             assert_grad_close(f"{k}.{name}", ga, gb.astype(np.float64), tol=1e-4)
         if k == k_small:
             check_vs_oracle(c, L[k], enc.grads(k))
+
+
+def test_batch_soft_mode_vs_oracle(B, BT):
+    """C3's soft proxy in the batch: the device noise, the sharpness from
+    the encoder's device scalar, against the oracle with the same noise."""
+    from oracle import noise as NZ
+    cs = batch_cases(CS.LOW, SMALL_SIZES[:3], seed0=820)
+    enc = make_encoder(B, BT, cs)
+    enc.noise_seed = 78
+    enc.set_mode(B.CC_QUANT_SOFT)
+    enc.alpha.fill_(4.0)
+    enc.backward()
+    torch.cuda.synchronize()
+    u_all = NZ.uniform_noise(sum(c.y.size + 1 for c in cs), 78, it=0)
+    L = enc.loss.cpu().numpy()
+    o = 0
+    for k, c in enumerate(cs):
+        u = u_all[o:o + c.y.size]
+        o += c.y.size + 1
+        ref = O.backward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=u, soft_alpha=4.0)
+        assert abs(L[k, 0] - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+        for name, g in zip(("g_y", "g_arm", "g_ups", "g_syn"), enc.grads(k)):
+            assert_grad_close(f"{k}.{name}", g, ref[name])
+
+
+def test_fit_soft_schedule_runs_and_lowers_the_loss(B, BT):
+    """The soft-proxy schedule (annealed sharpness in graph replays, then
+    rounding) trains: the rounding-mode loss falls, and stays finite."""
+    cs = batch_cases(CS.LOW, SMALL_SIZES[:3], seed0=840)
+    enc = make_encoder(B, BT, cs)
+    enc.probe()
+    torch.cuda.synchronize()
+    l0 = enc.loss.cpu().numpy()[:, 0].copy()
+    enc.fit(100, noise_frac=0.6, graph_steps=20, proxy="soft")
+    enc.probe()
+    torch.cuda.synchronize()
+    l1 = enc.loss.cpu().numpy()
+    assert np.all(np.isfinite(l1[:, 0])) and np.all(l1[:, 3] == 0.0)
+    assert np.all(l1[:, 0] < l0)
