@@ -305,6 +305,38 @@ def decode_latency_record(B):
     return out
 
 
+def proxy_record(B, n_images=8, iters=1000, log=None):
+    """The plain encoder with C3's soft-rounding proxy against the uniform
+    noise proxy at an equal number of iterations (Section II cites C3 for the
+    proxy): the first n_images of the batched workload, the same
+    initialisation, the proxy for 80 % of the iterations (temperature 1 ->
+    0.1 for the soft one), then rounding with the straight-through gradient;
+    the rate-distortion cost of Eq. (1) of the result, rounding mode."""
+    import torch
+    from paper_2403_11651_amd import batch as BT
+    probs, images, y0, params0 = batch_inputs(B)
+    probs, images, y0, params0 = probs[:n_images], images[:n_images], y0[:n_images], params0[:n_images]
+    out = {}
+    for proxy in ("noise", "soft"):
+        enc = BT.BatchEncoder(probs, images, [np.zeros_like(y) for y in y0], params0)
+        t0 = time.perf_counter()
+        enc.fit(iters, noise_frac=0.8, graph_steps=50, proxy=proxy)
+        enc.probe()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        l4 = enc.loss.cpu().numpy()
+        px = np.array([p.H * p.W for p in probs], np.float64)
+        out[proxy] = {"loss_mean": float(l4[:, 0].mean()), "psnr_db_mean": float(np.mean(-10 * np.log10(l4[:, 1]))),
+                      "bpp_mean": float(np.mean(l4[:, 2] / px)), "seconds": round(secs, 3)}
+        if log:
+            log(f"proxy {proxy}: loss {out[proxy]['loss_mean']:.6f}, {out[proxy]['psnr_db_mean']:.3f} dB, "
+                f"{out[proxy]['bpp_mean']:.4f} bpp")
+    out["workload"] = (f"the first {n_images} images of the batched workload, latents from 0, {iters} iterations: "
+                       "the proxy for 80 % (noise: y + u; soft: s(s(y) + u), temperature 1 -> 0.1), then rounding")
+    out["loss_ratio_soft_over_noise"] = round(out["soft"]["loss_mean"] / out["noise"]["loss_mean"], 5)
+    return out
+
+
 WARM_TRAIN, WARM_HELD, WARM_ITERS = 256, 32, 500
 
 
@@ -669,6 +701,8 @@ def main():
             f"{out['decode_768x512']['full']['decode_ms']} ms (full)")
     if args.batch_iters > 0:
         out["batched"] = run_batched(B, args.batch_iters, log=log)
+        if not args.no_extra:
+            out["quantisation_proxy"] = proxy_record(B, log=log)
     if not args.no_warm_start:
         out["warm_start"] = run_warm_start(warm_images, log=log)
     if not args.no_cpu_baseline:

@@ -185,7 +185,7 @@ class BatchEncoder:
         for _ in range(rem):
             self.step()
 
-    def fit(self, iters, noise_frac=0.8, graph_steps=50, proxy="noise", t_start=0.3, t_end=0.1):
+    def fit(self, iters, noise_frac=0.8, graph_steps=50, proxy="noise", t_start=1.0, t_end=0.1):
         """The two-phase schedule: a differentiable proxy for the first
         noise_frac of the iterations, then rounding with the straight-through
         gradient.  proxy "noise": y + u; "soft": C3's soft rounding s(s(y) +

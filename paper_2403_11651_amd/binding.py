@@ -430,7 +430,8 @@ class BatchPlan:
         _check(_lib.coolchic_batch_backward(self._h, _stream(stream)), "coolchic_batch_backward")
 
     def close(self):
-        if getattr(self, "_h", None):
+        # (at interpreter exit the module globals may already be gone)
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.coolchic_batch_destroy(self._h)
             self._h = None
 
