@@ -259,11 +259,15 @@ typedef struct {
 
 /* Launch shape of the persistent kernels (tuned by the caller): total
    work-groups of the ARM launch and of the synthesis-backward launch, split
-   over the images in proportion to their tiles.  0 selects, per image, the
-   grid coolchic_backward uses (then the results are bit-identical to it). */
+   over the images in proportion to their tiles (0 selects, per image, the
+   grid coolchic_backward uses; then the results are bit-identical to it);
+   arm_first = 1 forks the ARM launch onto the side stream before the
+   upsampling and synthesis launches instead of after the residual-conv
+   backward (the order changes no result). */
 typedef struct {
   int32_t arm_blocks;
   int32_t syn_blocks;
+  int32_t arm_first;
 } cc_batch_tuning;
 
 typedef struct cc_batch cc_batch; /* opaque host-side plan */

@@ -82,7 +82,7 @@ class BatchEncoder:
         self._na, self._nu, self._ns = na, nu, ns
         self.plans = {}
         self.mode = B.CC_QUANT_ROUND
-        self.tune = tuple(int(t) for t in tune)
+        self.tune = tuple(int(t) for t in tune) + (0,) * (3 - len(tune))
         self.plan = self._plan(self.mode)
 
     # -- views of image k's parameters and gradients
@@ -113,7 +113,7 @@ class BatchEncoder:
         return self.plans[mode]
 
     def set_tuning(self, tune):
-        tune = tuple(int(t) for t in tune)
+        tune = tuple(int(t) for t in tune) + (0,) * (3 - len(tune))
         if tune != self.tune:
             for p in self.plans.values():
                 p.close()
@@ -225,6 +225,7 @@ class BatchEncoder:
 # ---- autotuner -----------------------------------------------------------
 
 ARM_CANDIDATES = (0, 512, 1024, 2048, 4096)
+ARM_FIRST_CANDIDATES = (0, 1)
 SYN_CANDIDATES = (0, 512, 1024, 2048, 4096)
 _cache_lock = threading.Lock()
 
@@ -296,11 +297,11 @@ def time_iteration(enc: BatchEncoder, iters=10, reps=3):
 
 
 def autotune(enc: BatchEncoder, use_cache=True, iters=10, reps=3, log=None):
-    """Chooses (arm_blocks, syn_blocks) for enc by coordinate search over the
-    candidate lists (ARM first, with the default synthesis shape, then the
-    synthesis shape), timing whole training iterations.  The encoder's state
-    is restored afterwards; the choice is applied and returned, with the
-    timings, and cached."""
+    """Chooses (arm_blocks, syn_blocks, arm_first) for enc by coordinate
+    search over the candidate lists (the ARM's launch position, then its
+    grid with the default synthesis shape, then the synthesis shape), timing
+    whole training iterations.  The encoder's state is restored afterwards;
+    the choice is applied and returned, with the timings, and cached."""
     path = cache_path()
     key = tuning_key(enc)
     if use_cache:
@@ -319,11 +320,12 @@ def autotune(enc: BatchEncoder, use_cache=True, iters=10, reps=3, log=None):
                 log(f"autotune {t}: {timings[t]:.4f} ms/iter")
         return timings[t]
 
-    best_a = min(ARM_CANDIDATES, key=lambda a: measure((a, 0)))
-    best = min(((best_a, s) for s in SYN_CANDIDATES), key=measure)
+    best_f = min(ARM_FIRST_CANDIDATES, key=lambda f: measure((0, 0, f)))
+    best_a = min(ARM_CANDIDATES, key=lambda a: measure((a, 0, best_f)))
+    best = min(((best_a, s, best_f) for s in SYN_CANDIDATES), key=measure)
     enc.load(state)
     enc.set_tuning(best)
     result = dict(tune=list(best), ms_per_iter=timings[best],
-                  timings={f"{a},{s}": v for (a, s), v in timings.items()})
+                  timings={",".join(str(x) for x in t): v for t, v in timings.items()})
     _store_cache(path, key, result)
     return dict(result, cached=False)

@@ -686,7 +686,7 @@ namespace {
 
 // Host-side plan of a batch.
 struct BatchPlan {
-  int n = 0, L = 0, device = 0, shared = 0;
+  int n = 0, L = 0, device = 0, shared = 0, arm_first = 0;
   const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr, *hdk = nullptr;
   // device arrays inside the workspace
   ArmArgs* d_arm = nullptr;
@@ -796,6 +796,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.n = n;
   B.L = L;
   B.shared = plans[0].shared;
+  B.arm_first = tune ? (tune->arm_first != 0) : 0;
   B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
   B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
   B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
@@ -891,12 +892,11 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   Side* sd = nullptr;
   if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
-  if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
-  if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
-  if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
-  if ((rc = fork_to(sd, st))) return rc;
-  {
-    // the ARM launch goes to the side stream
+  // the ARM launch goes to the side stream (it depends on nothing the main
+  // stream computes): first, or after the residual-conv backward
+  auto arm = [&]() -> int {
+    int r = fork_to(sd, st);
+    if (r) return r;
     void* descs = B.d_arm;
     void* work = B.w_arm;
     void* argv[] = {&descs, &work};
@@ -904,7 +904,13 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (timed && hipEventRecord(g_ev_begin, sd->stream) != hipSuccess) return CC_EHIP;
     if (hipLaunchKernel(B.armk, dim3(B.n_arm), dim3(ARM_THREADS), argv, 0, sd->stream) != hipSuccess) return CC_EHIP;
     if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
-  }
+    return CC_OK;
+  };
+  if (B.arm_first && (rc = arm())) return rc;
+  if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
+  if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
+  if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
+  if (!B.arm_first && (rc = arm())) return rc;
   if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
   // the side combine, once levels [0, BATCH_SIDE_LEVELS) of every g_y are
   // final (level 0 after the head backward, level 1 after adjoint step 0)

@@ -36,7 +36,7 @@ def batch_cases(arch, sizes, seed0=100):
                     n_blobs=max(3, H * W // 2048)) for k, (H, W) in enumerate(sizes)]
 
 
-def make_encoder(B, BT, cs, tune=(0, 0)):
+def make_encoder(B, BT, cs, tune=(0, 0, 0)):
     probs = [B.Problem(c.H, c.W, B.Arch(*c.arch), B.CC_QUANT_ROUND, c.lam) for c in cs]
     return BT.BatchEncoder(probs, [c.img for c in cs], [c.y for c in cs], [(c.arm, c.ups, c.syn) for c in cs],
                            tune=tune)
@@ -77,7 +77,7 @@ def test_batch_default_equals_single_calls(B, BT, arch):
             assert np.array_equal(a, b), k
 
 
-@pytest.mark.parametrize("tune", [(0, 0), (7, 5), (4096, 4096)])
+@pytest.mark.parametrize("tune", [(0, 0, 0), (7, 5, 0), (4096, 4096, 0), (0, 0, 1), (512, 2048, 1)])
 def test_batch_vs_oracle(B, BT, tune):
     cs = batch_cases(CS.LOW, SMALL_SIZES, seed0=200)
     enc = make_encoder(B, BT, cs, tune=tune)
@@ -90,7 +90,7 @@ def test_batch_vs_oracle(B, BT, tune):
 
 def test_batch_full_arch_vs_oracle(B, BT):
     cs = batch_cases(CS.FULL, [(64, 192), (128, 128)], seed0=300)
-    enc = make_encoder(B, BT, cs, tune=(37, 11))
+    enc = make_encoder(B, BT, cs, tune=(37, 11, 1))
     enc.backward()
     torch.cuda.synchronize()
     L = enc.loss.cpu().numpy()
@@ -201,7 +201,8 @@ def test_autotune_restores_state_and_caches(B, BT, tmp_path, monkeypatch):
     before = enc.theta.clone()
     res = BT.autotune(enc, iters=2, reps=1)
     assert not res["cached"]
-    assert tuple(res["tune"]) in {(a, s) for a in BT.ARM_CANDIDATES for s in BT.SYN_CANDIDATES}
+    assert tuple(res["tune"]) in {(a, s, f) for a in BT.ARM_CANDIDATES for s in BT.SYN_CANDIDATES
+                                  for f in BT.ARM_FIRST_CANDIDATES}
     assert enc.tune == tuple(res["tune"])
     assert torch.equal(enc.theta, before)
     assert int(enc.step_ctr[0]) == 0
