@@ -188,7 +188,14 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
   if (shared && tid < UPS_SHARED_TAPS) s_w2[tid] = a.taps[tid];
   const int jr0 = 2 * r0 - 7, jc0 = 2 * c0 - 7;
   const int lo = a.geo.loff[s + 1];
-  float pf[NPF];
+  // the thread's input position (one per thread) and, per channel, its
+  // forward value (the tap gradients' input): fetched with the channel's
+  // output-gradient region, a channel ahead
+  const int my_r = r0 + tid / UT, my_c = c0 + tid % UT;
+  const bool my_in = my_r < hi && my_c < wi;
+  const int my_idx = my_r * wi + my_c;
+  const float alpha = proxy_alpha(a.u, a.quant, a.geo.n_lat);
+  float pf[NPF], pin = 0.0f;
   auto fetch = [&](int ch) {
     const float* gin = a.g_in + (size_t)ch * ho * wo;
     int t = tid;
@@ -199,6 +206,9 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
       const int jr = jr0 + p / UR_N, jc = jc0 + p % UR_N;
       pf[q] = (p < UR_N * UR_N && jr >= 0 && jr < ho && jc >= 0 && jc < wo) ? gin[jr * wo + jc] : 0.0f;
     }
+    pin = !my_in ? 0.0f
+                 : ch == 0 ? quantise(a.y, a.u, lo + my_idx, a.quant, alpha)
+                           : a.up_in[(size_t)(ch - 1) * hi * wi + my_idx];
   };
   fetch(c_lo);
   for (int ch = c_lo; ch < c_hi; ++ch) {
@@ -207,6 +217,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
       const int p = tid + 256 * q;
       if (p < UR_N * UR_N) s_g[p] = pf[q];
     }
+    const float inval = pin;
     __syncthreads();
     if (ch + 1 < c_hi) fetch(ch + 1);
     // the thread's indices pass through an empty asm statement so that the
@@ -223,10 +234,6 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     cb[0] = tc + 2; cb[1] = c == 0 ? 1 : -1; cb[2] = c == 0 ? 0 : -1;
     cb[3] = c == wi - 1 ? tc + 3 : -1; cb[4] = c == wi - 1 ? tc + 4 : -1;
     const int idx = r * wi + c;
-    float inval = 0.0f;
-    if (in_tile)
-      inval = ch == 0 ? quantise(a.y, a.u, lo + idx, a.quant, proxy_alpha(a.u, a.quant, a.geo.n_lat))
-                      : a.up_in[(size_t)(ch - 1) * hi * wi + idx];
     for (int p = t; !shared && p < UR_N * UP_N; p += 256) {
       {  // T[row][pc] = sum_kx h[kx] g[row][2 pc + kx]
         const int row = p / UP_N, pc = p % UP_N;
