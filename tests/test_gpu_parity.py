@@ -71,13 +71,19 @@ def assert_grad_close(name, g, go, tol=1e-3):
     assert np.max(np.abs(g - go)) <= tol * np.max(np.abs(go)) + 1e-30, (name, np.max(np.abs(g - go)), np.max(np.abs(go)))
 
 
+# FP32 perturbation of the ARM's (mu, s) that the per-latent rate bar allows
+# for: 4.4x the largest one measured over every parity case (4.5e-7, on 8 of
+# ~1.1 M latents whose scale sits at the 0.01 clamp)
+RATE_EPS = 2e-6
+
+
 def assert_rate_close(r, ref):
     """1e-4 bits (1e-6 relative above 100 bits), plus the first-order effect of
-    a 1e-5 perturbation of the FP32 mean and log-scale: with the scale
+    a RATE_EPS perturbation of the FP32 mean and log-scale: with the scale
     clamped at 0.01 the rate turns an error in mu into 144x as many bits."""
     ro = ref["rate"]
     _, gmu, gs = O.rate_grads(ref["yq"], ref["mu"], ref["s"])
-    tol = np.maximum(1e-4, 1e-6 * np.abs(ro)) + 1e-5 * (np.abs(gmu) + np.abs(gs))
+    tol = np.maximum(1e-4, 1e-6 * np.abs(ro)) + RATE_EPS * (np.abs(gmu) + np.abs(gs))
     bad = np.abs(r - ro) > tol
     assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(r - ro))), float(np.max(np.abs(r - ro) / tol)))
     plain = np.abs(gmu) < 15.0  # scale >= 0.1: the plain 1e-4-bit bar
@@ -162,7 +168,7 @@ def test_rate_error_conditioning_768x512(B, which):
     per-latent rate error above 1e-5 bits (ten times below the plain bar)
     divided by |dr/dmu| + |dr/ds| (the oracle's derivatives): the size of the
     FP32 error in (mu, s) that the rate error corresponds to.  It must stay
-    below the 1e-5 the rate bar grants."""
+    below the RATE_EPS the rate bar grants."""
     c = CS.low() if which == "low" else CS.full()
     out = gpu_forward(B, c)
     ref = O.forward(O.Arch(*c.arch), c.img, c.y, c.arm, c.ups, c.syn, c.lam, u=c.u)
@@ -173,7 +179,7 @@ def test_rate_error_conditioning_768x512(B, which):
     print(f"{which}: max |dr| / (|dr/dmu| + |dr/ds|) = {ratio[k]:.3e} at latent {k} (|dr| {err[k]:.3e} bits, "
           f"b {np.exp(np.clip(ref['s'][k], O.S_MIN, O.S_MAX)):.4g}); max |dr| {err.max():.3e} bits; "
           f"latents with b < 0.1: {int(np.sum(np.abs(gmu) >= 15.0))}")
-    assert ratio[k] < 1e-5
+    assert ratio[k] < RATE_EPS
 
 
 @pytest.mark.parametrize("which", ["low", "full"])
