@@ -658,8 +658,13 @@ __device__ __forceinline__ void syn_bwd_body(const SynArgs& a, const int bid, co
 template <int HS, int NRES, bool HALF>
 __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bid) {
   constexpr int T = SYN_HD, RS = T / 2 + 4;
-  constexpr int NC = (HS + 1 + 15) / 16;  // chunks of the hidden units (+ the bias unit)
-  constexpr int NCG = (HS + 15) / 16;     // chunks holding hidden units
+  // chunks of 16 hidden units.  The second layer's bias gradient (the sum of
+  // g_pre_t) rides in the last chunk as a unit of ones when that chunk has
+  // room (BU); with HS a multiple of 16 it would take a chunk of its own, and
+  // is a plain per-lane sum instead
+  constexpr bool BU = HS % 16 != 0;
+  constexpr int NC = (HS + (BU ? 1 : 0) + 15) / 16;
+  constexpr int NCG = (HS + 15) / 16;  // chunks holding hidden units
   constexpr int SYZ = 9, SXT = 3, SYA = 17, SXG = 17;      // staged row lengths
   // per wave: z and g_pre_t of its 64 pixels, and a chunk's a and g_a for
   // 32 of them (the two halves of the wave are staged in turn)
@@ -782,7 +787,7 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
         gv = g;
         gz[0] += w0.x * g; gz[1] += w0.y * g; gz[2] += w0.z * g; gz[3] += w0.w * g;
         gz[4] += w1.x * g; gz[5] += w1.y * g; gz[6] += w1.z * g;
-      } else if (f == HS) {
+      } else if (BU && f == HS) {
         av = own ? 1.0f : 0.0f;  // the bias unit of the second layer
       }
       avs[u] = av;
@@ -844,9 +849,16 @@ __device__ __forceinline__ void syn_head_bwd_body(const SynArgs& a, const int bi
       const int c = 4 * lg + r, f = 16 * bn + lc;  // X index = output channel, Y index = hidden unit (HS = bias)
       if (c < 3) {
         if (f < HS) rw[oW2 + c * HS + f] = accW2[0][bn][r];
-        else if (f == HS) rw[ob2 + c] = accW2[0][bn][r];
+        else if (BU && f == HS) rw[ob2 + c] = accW2[0][bn][r];
       }
     }
+  if constexpr (!BU) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float b2 = wave_sum(gpt[c]);  // zero for pixels outside the image
+      if (lane == 0) rw[ob2 + c] = b2;
+    }
+  }
   __syncthreads();
   for (int p = tid; p < nh; p += 256)
     a.hpart[(size_t)bid * nh + p] = ((pool[p] + pool[nh + p]) + pool[2 * nh + p]) + pool[3 * nh + p];
