@@ -261,9 +261,10 @@ typedef struct {
    work-groups of the ARM launch and of the synthesis-backward launch, split
    over the images in proportion to their tiles (0 selects, per image, the
    grid coolchic_backward uses; then the results are bit-identical to it);
-   arm_first = 1 forks the ARM launch onto the side stream before the
-   upsampling and synthesis launches instead of after the residual-conv
-   backward (the order changes no result). */
+   arm_first selects where the ARM launch is forked onto the side stream:
+   0 after the residual-conv backward, 1 before the upsampling and synthesis
+   launches, 2 after the head backward (the order changes no result; any
+   other value is CC_EINVAL). */
 typedef struct {
   int32_t arm_blocks;
   int32_t syn_blocks;

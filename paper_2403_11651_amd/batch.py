@@ -225,7 +225,7 @@ class BatchEncoder:
 # ---- autotuner -----------------------------------------------------------
 
 ARM_CANDIDATES = (0, 512, 1024, 2048, 4096)
-ARM_FIRST_CANDIDATES = (0, 1)
+ARM_FIRST_CANDIDATES = (0, 1, 2)
 SYN_CANDIDATES = (0, 512, 1024, 2048, 4096)
 _cache_lock = threading.Lock()
 

@@ -736,6 +736,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     tiles_syn += plans[k].syn_tiles;
   }
   const int ta = tune ? tune->arm_blocks : 0, ts = tune ? tune->syn_blocks : 0;
+  if (tune && (tune->arm_first < 0 || tune->arm_first > 2)) return CC_EINVAL;
   img_off.resize(n);
   size_t cur = 0;
   for (int k = 0; k < n; ++k) {
@@ -811,7 +812,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.n = n;
   B.L = L;
   B.shared = plans[0].shared;
-  B.arm_first = tune ? (tune->arm_first != 0) : 0;
+  B.arm_first = tune ? tune->arm_first : 0;
   B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
   B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
   B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
@@ -908,7 +909,8 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
   if ((rc = side_for_current_device(&sd))) return rc;
   (void)hipGetLastError();
   // the ARM launch goes to the side stream (it depends on nothing the main
-  // stream computes): first, or after the residual-conv backward
+  // stream computes): first, after the residual-conv backward, or after the
+  // head backward
   auto arm = [&]() -> int {
     int r = fork_to(sd, st);
     if (r) return r;
@@ -921,12 +923,13 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (timed && hipEventRecord(g_ev_end, sd->stream) != hipSuccess) return CC_EHIP;
     return CC_OK;
   };
-  if (B.arm_first && (rc = arm())) return rc;
+  if (B.arm_first == 1 && (rc = arm())) return rc;
   if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
   if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
   if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
-  if (!B.arm_first && (rc = arm())) return rc;
+  if (B.arm_first == 0 && (rc = arm())) return rc;
   if ((rc = go(CC_STAGE_NONE, B.hdk, B.n_head, 256, B.d_syn, B.w_head))) return rc;
+  if (B.arm_first == 2 && (rc = arm())) return rc;
   // the side combine, once levels [0, BATCH_SIDE_LEVELS) of every g_y are
   // final (level 0 after the head backward, level 1 after adjoint step 0)
   auto side_combine = [&]() -> int {

@@ -77,7 +77,8 @@ def test_batch_default_equals_single_calls(B, BT, arch):
             assert np.array_equal(a, b), k
 
 
-@pytest.mark.parametrize("tune", [(0, 0, 0), (7, 5, 0), (4096, 4096, 0), (0, 0, 1), (512, 2048, 1)])
+@pytest.mark.parametrize("tune", [(0, 0, 0), (7, 5, 0), (4096, 4096, 0), (0, 0, 1), (512, 2048, 1), (0, 0, 2),
+                                  (1024, 512, 2)])
 def test_batch_vs_oracle(B, BT, tune):
     cs = batch_cases(CS.LOW, SMALL_SIZES, seed0=200)
     enc = make_encoder(B, BT, cs, tune=tune)
@@ -86,6 +87,12 @@ def test_batch_vs_oracle(B, BT, tune):
     L = enc.loss.cpu().numpy()
     for k, c in enumerate(cs):
         check_vs_oracle(c, L[k], enc.grads(k))
+
+
+def test_batch_rejects_unknown_arm_order(B, BT):
+    cs = batch_cases(CS.LOW, SMALL_SIZES[:2], seed0=210)
+    with pytest.raises(B.CoolChicError):
+        make_encoder(B, BT, cs, tune=(0, 0, 3))
 
 
 def test_batch_full_arch_vs_oracle(B, BT):

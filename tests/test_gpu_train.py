@@ -166,3 +166,42 @@ def test_coolchicfn_backward_matches_oracle(B, which):
     for name, t in (("g_y", y), ("g_arm", arm), ("g_ups", ups), ("g_syn", syn)):
         _rel_close(name, t.grad.cpu().numpy(), ref[name], 1e-3)
     assert CoolChicFn is not None
+
+
+def test_train_step_graph_replay_matches_eager(B):
+    """coolchic_train_step captured in a graph (under capture the ARM is forked
+    after the head backward) and replayed: every replay equals the same
+    number of eager steps bit for bit, with unrelated eager work and
+    synchronisations between the replays (24-wide ARM, ragged 64x192)."""
+    c = CS.make("ragged_L7_64x192", 64, 192, CS.FULL, seeds=(20, 21, 22, 23), noise=True)
+    p = _problem(B, c)
+    theta0 = np.concatenate([c.y, c.arm, c.ups, c.syn]).astype(np.float32)
+    img, u = _dev(c.img), _dev(c.u)
+
+    def state():
+        th = _dev(theta0)
+        return [th, torch.zeros_like(th), torch.zeros_like(th), torch.zeros_like(th),
+                torch.zeros(2, dtype=torch.int32, device="cuda"), torch.zeros(4, device="cuda")]
+
+    def step(sv):
+        th, g, m, v, st, l4 = sv
+        B.coolchic_train_step(p, img, u, 1.0, l4, th, g, m, v, st, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8)
+
+    eager, graphed = state(), state()
+    step(eager)  # the first calls on the device run eagerly (side stream set-up)
+    step(graphed)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        step(graphed)
+        step(graphed)
+    scratch = torch.randn(1 << 16, device="cuda")
+    for r in range(3):
+        step(eager)
+        step(eager)
+        gr.replay()
+        scratch = torch.tanh(scratch * 1.01) + scratch.sum() * 0.0
+        torch.cuda.synchronize()
+        for a, b in zip(eager, graphed):
+            assert torch.equal(a, b), r
+    assert eager[4].cpu().tolist()[0] == 7
