@@ -1,0 +1,152 @@
+"""Pins of the analysis-transform oracle (oracle/analysis.py) against what
+does not come from it: SciPy's 2-D correlation and normal CDF, torch's CPU
+convolution / layer-norm / GELU / pooling in float64, brute-force loops on
+tiny inputs, closed forms, and the complexity the paper plots."""
+import math
+
+import numpy as np
+import pytest
+import scipy.signal
+import scipy.stats
+import torch
+import torch.nn.functional as F
+
+import oracle.analysis as A
+from oracle.warmstart import bf16
+
+
+def _theta(seed, std=0.05):
+    rng = np.random.default_rng(seed)
+    th = rng.normal(0.0, std, A.param_count())
+    # layer-norm scales near 1 so that the features keep their size
+    blocks, _ = A.unpack(th)
+    for p in blocks:
+        p["ln_g"][:] = 1.0 + 0.1 * rng.normal(size=p["ln_g"].size)
+    return th
+
+
+def test_block_structure_and_param_count():
+    specs = A.block_specs()
+    assert len(specs) == 21
+    assert [s for _, _, s, _ in specs].count(2) == 6 and specs[0] == (0, 3, 1, False)
+    assert sum(1 for *_, last in specs if last) == 7
+    th = np.arange(A.param_count(), dtype=np.float64)
+    blocks, heads = A.unpack(th)
+    # every parameter is used exactly once, in order
+    seen = np.concatenate([np.ravel(p[k]) for p in blocks for k in
+                           ("dw_w", "dw_b", "ln_g", "ln_b", "W1", "b1", "W2", "b2", "Wid", "bid")] +
+                          [np.concatenate([w, [b]]) for w, b in heads])
+    assert np.array_equal(seen, th)
+
+
+def test_complexity_matches_the_plotted_value():
+    """Section IV-B: N-O Cool-chic's analysis costs about 130 000 MAC per
+    pixel on the complexity plot (160 k in the text)."""
+    m = A.mac_per_pixel(512, 768)
+    assert abs(m - 130000) <= 0.05 * 130000, m
+    assert abs(m - A.mac_per_pixel(1024, 1024)) <= 0.01 * m  # per-pixel cost independent of the size
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_dwconv_vs_scipy(stride):
+    rng = np.random.default_rng(1 + stride)
+    x = rng.normal(size=(3, 16, 24))
+    w = rng.normal(size=(3, 7, 7))
+    b = rng.normal(size=3)
+    got = A.dwconv(x, w, b, stride)
+    for c in range(3):
+        full = scipy.signal.correlate2d(x[c], w[c], mode="same", boundary="fill", fillvalue=0.0) + b[c]
+        assert np.allclose(got[c], full[::stride, ::stride], rtol=0, atol=1e-12)
+
+
+def test_layer_norm_closed_form():
+    rng = np.random.default_rng(3)
+    x = rng.normal(2.0, 3.0, size=(64, 4, 5))
+    y = A.layer_norm(x, np.ones(64), np.zeros(64))
+    var = x.var(axis=0)
+    assert np.allclose(y.mean(axis=0), 0.0, atol=1e-12)
+    assert np.allclose(y.var(axis=0), var / (var + A.LN_EPS), rtol=1e-12)
+    g, b = rng.normal(size=64), rng.normal(size=64)
+    assert np.allclose(A.layer_norm(x, g, b), y * g[:, None, None] + b[:, None, None], atol=1e-12)
+
+
+def test_gelu_vs_normal_cdf():
+    x = np.linspace(-8.0, 8.0, 161)
+    assert np.allclose(A.gelu(x), x * scipy.stats.norm.cdf(x), rtol=1e-13, atol=1e-15)
+    assert A.gelu(np.array([0.0]))[0] == 0.0
+
+
+def test_pool_and_1x1_brute_force():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(5, 6, 8))
+    p = A.avgpool2(x)
+    for c in range(5):
+        for i in range(3):
+            for j in range(4):
+                assert math.isclose(p[c, i, j], x[c, 2 * i:2 * i + 2, 2 * j:2 * j + 2].sum() / 4.0, abs_tol=1e-14)
+    W, b = rng.normal(size=(7, 5)), rng.normal(size=7)
+    y = A.conv1x1(W, x, b)
+    for o in range(7):
+        for i in range(6):
+            for j in range(8):
+                assert math.isclose(y[o, i, j], sum(W[o, k] * x[k, i, j] for k in range(5)) + b[o], abs_tol=1e-12)
+
+
+def _torch_forward(x, theta):
+    """The same transform written with torch's CPU float64 layers."""
+    blocks, heads = A.unpack(theta)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))  # noqa: E731
+    f = t(x)[None]
+    ys = []
+    for p in blocks:
+        ci, s = p["c_in"], p["stride"]
+        d = F.conv2d(f, t(p["dw_w"])[:, None], t(p["dw_b"]), stride=s, padding=3, groups=ci)
+        d = F.layer_norm(d.permute(0, 2, 3, 1), (ci,), t(p["ln_g"]), t(p["ln_b"]), eps=A.LN_EPS).permute(0, 3, 1, 2)
+        h = F.gelu(F.conv2d(d, t(p["W1"])[:, :, None, None], t(p["b1"])), approximate="none")
+        m = F.conv2d(h, t(p["W2"])[:, :, None, None], t(p["b2"]))
+        if p["Wid"].size:
+            src = F.avg_pool2d(f, 2) if s == 2 else f
+            ident = F.conv2d(src, t(p["Wid"])[:, :, None, None], t(p["bid"]))
+        else:
+            ident = f
+        f = m + ident
+        if p["last"]:
+            hw, hb = heads[p["level"]]
+            ys.append((f[0] * t(hw)[:, None, None]).sum(0) + hb)
+    return [y.numpy() for y in ys]
+
+
+def test_forward_vs_torch_layers():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, size=(3, 64, 128))
+    th = _theta(6)
+    ys, feats = A.forward(x, th, round_bf16=False)
+    ref = _torch_forward(x, th)
+    assert [y.shape for y in ys] == [(64 >> l, 128 >> l) for l in range(7)]
+    for y, r in zip(ys, ref):
+        assert np.allclose(y, r, rtol=1e-10, atol=1e-10 * np.max(np.abs(r)))
+
+
+def test_rounding_points():
+    """With rounding on, every stored block output is a bfloat16 value, and
+    the result stays within bfloat16-size error of the unrounded one."""
+    rng = np.random.default_rng(7)
+    x = rng.uniform(0.0, 1.0, size=(3, 64, 64))
+    th = _theta(8)
+    ys_r, feats = A.forward(x, th, round_bf16=True)
+    for f in feats:
+        assert np.array_equal(f, bf16(f))
+    ys, _ = A.forward(x, th, round_bf16=False)
+    for a, b in zip(ys_r, ys):
+        assert np.max(np.abs(a - b)) <= 0.05 * np.max(np.abs(b)) + 1e-6
+
+
+def test_encode_layout():
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0.0, 1.0, size=(3, 64, 64))
+    th = _theta(10)
+    yq, y = A.encode(x, th)
+    assert y.size == sum((64 >> l) ** 2 for l in range(7))
+    assert np.array_equal(yq, np.rint(y))
+    ys, _ = A.forward(x, th)
+    assert np.array_equal(y[:64 * 64], ys[0].ravel()) and y[-1] == ys[6].ravel()[-1]
