@@ -351,6 +351,49 @@ int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const 
                                 const float* g_theta, float* loss4, float* g_net, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* ---------------------------------------------------------------------
+   Non-overfitted analysis transform (Section IV-B, Eq. (3)): the latents of
+   every grid from the image in one forward pass, y = f_alpha(x), instead of
+   overfitting them.  The paper describes the network in words only (its
+   figure is not available); the reading implemented:
+     block (c_in -> 64, stride s): depth-wise 7x7 convolution (zero padding
+       3, stride s, bias), layer normalisation over the c_in channels of
+       each position (eps 1e-6, scale and shift), 1x1 c_in -> 256 with bias,
+       GELU (erf form), 1x1 256 -> 64 with bias, plus the identity branch:
+       the input itself (c_in = 64, s = 1), else a 1x1 convolution c_in ->
+       64 with bias of the input, 2x2 average-pooled with stride 2 when s = 2;
+     level 0: block 3 -> 64 (s = 1) then two blocks 64 -> 64; levels 1..6:
+       block 64 -> 64 (s = 2) then two blocks; 21 blocks, 126.6 kMAC per
+       pixel;
+     latent l: 1x1 convolution 64 -> 1 (with bias) of the level's last block
+       output, at (H >> l) x (W >> l).
+   Arithmetic: the 1x1 convolutions run on the bfloat16 matrix cores with
+   FP32 accumulation -- their weights and inputs (the normalised features,
+   the GELU output, the image and the pooled input of the identity branches)
+   are rounded to bfloat16, and every block output is stored in bfloat16;
+   the depth-wise convolutions, the normalisation, GELU, biases and the
+   latent heads are FP32.
+   Parameters (FP32, packed): per block in order dw_w [c_in][7][7], dw_b
+   [c_in], ln_g [c_in], ln_b [c_in], W1 [256][c_in], b1 [256], W2 [64][256],
+   b2 [64], and for the first block of each level Wid [64][c_in], bid [64];
+   then per level the head w [64], b. */
+
+/* Packed parameter count of the analysis transform. */
+int64_t coolchic_analysis_param_count(void);
+
+/* Device workspace bytes for n images of H x W (multiples of 64); 0 if the
+   sizes are invalid. */
+size_t coolchic_analysis_workspace_bytes(int32_t H, int32_t W, int32_t n);
+
+/* x (device) [n][3][H][W] in [0, 1]; theta (device) the packed parameters;
+   y (device) [n][N_lat]: each image's latents before quantisation, packed
+   like coolchic_forward's y (level 0 first, raster order), N_lat over 7
+   levels.  Errors: CC_EINVAL (null pointer, n < 1, H or W not a positive
+   multiple of 64), CC_EWORKSPACE, CC_EHIP.  Enqueues on `stream`; allocates
+   nothing. */
+int coolchic_analysis_forward(int32_t H, int32_t W, int32_t n, const float* x, const float* theta, float* y,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* Quantisation of the decoder parameters (Section II: after the encoding the
    network parameters are quantised and entropy coded with an ad-hoc
    probability model).  Each module m (0 ARM, 1 upsampling, 2 synthesis) on a

@@ -48,6 +48,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.special
 
 from .warmstart import bf16
 
@@ -149,8 +150,7 @@ def layer_norm(x, g, b):
 
 def gelu(x):
     """x Phi(x) with Phi the standard normal CDF (the erf form)."""
-    erf = np.vectorize(math.erf)
-    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+    return 0.5 * x * (1.0 + scipy.special.erf(x / math.sqrt(2.0)))
 
 
 def conv1x1(W, x, b=None):

@@ -30,7 +30,8 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_timing_event_elapsed", "coolchic_timing_event_destroy", "coolchic_train_step",
            "coolchic_train_step_noalloc", "coolchic_entropy_workspace_bytes", "coolchic_entropy_bound",
            "coolchic_entropy_tables", "coolchic_entropy_encode", "coolchic_entropy_decode",
-           "coolchic_param_quantize")
+           "coolchic_param_quantize", "coolchic_analysis_param_count", "coolchic_analysis_workspace_bytes",
+           "coolchic_analysis_forward")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -99,6 +100,9 @@ def _load():
         "coolchic_entropy_encode": (I, [pp, P, P, P, SZ, P, P, SZ, P]),
         "coolchic_entropy_decode": (I, [pp, P, SZ, P, P, P, P, SZ, P]),
         "coolchic_warm_param_count": (I64, [pa]),
+        "coolchic_analysis_param_count": (I64, []),
+        "coolchic_analysis_workspace_bytes": (SZ, [I, I, I]),
+        "coolchic_analysis_forward": (I, [I, I, I, P, P, P, P, SZ, P]),
         "coolchic_warm_workspace_bytes": (SZ, [ctypes.POINTER(CCWarmProblem), I]),
         "coolchic_warm_forward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, SZ, P]),
         "coolchic_warm_backward": (I, [ctypes.POINTER(CCWarmProblem), P, P, P, P, P, P, P, SZ, P]),
@@ -455,6 +459,28 @@ def warm_param_count(arch: Arch) -> int:
     if n < 0:
         raise CoolChicError(CC_EUNSUPPORTED, "coolchic_warm_param_count")
     return int(n)
+
+
+def analysis_param_count() -> int:
+    return int(_lib.coolchic_analysis_param_count())
+
+
+def analysis_workspace(H: int, W: int, n: int, device="cuda") -> torch.Tensor:
+    nb = int(_lib.coolchic_analysis_workspace_bytes(int(H), int(W), int(n)))
+    if nb == 0:
+        raise CoolChicError(CC_EINVAL, "coolchic_analysis_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def coolchic_analysis_forward(H: int, W: int, n: int, x, theta, y, ws=None, stream=None):
+    """Non-overfitted analysis transform: x [n][3][H][W] -> y [n][N_lat]."""
+    n_lat = sum((H >> l) * (W >> l) for l in range(7))
+    if ws is None:
+        ws = analysis_workspace(H, W, n, device=x.device)
+    rc = _lib.coolchic_analysis_forward(int(H), int(W), int(n), _ptr(x, n * 3 * H * W, "x"),
+                                        _ptr(theta, analysis_param_count(), "theta"), _ptr(y, n * n_lat, "y"),
+                                        _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
+    _check(rc, "coolchic_analysis_forward")
 
 
 def warm_workspace(wp: WarmProblem, which: int, device="cuda") -> torch.Tensor:

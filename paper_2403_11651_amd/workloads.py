@@ -19,6 +19,8 @@ Workloads (all FP32, NumPy PCG64 ``default_rng``):
 * noise: the additive quantisation noise u ~ U[-0.5, 0.5).
 * normal_blocks: initial parameters of a network, block by block N(0, std^2)
   (the caller gives each block's size and std).
+* analysis_params: parameters of the analysis transform, fan-in-scaled
+  normal weights, small biases, layer-norm scales near 1.
 """
 from __future__ import annotations
 
@@ -79,6 +81,37 @@ def normal_blocks(seed: int, blocks) -> np.ndarray:
     parts = []
     for n, std in blocks:
         parts.append(rng.normal(0.0, std, size=n) if std > 0 else np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def analysis_params(seed: int, c: int = 64, hid: int = 256, k: int = 7, levels: int = 7, extra: int = 2) -> np.ndarray:
+    """Seeded parameters of the analysis transform in its packed layout: per
+    block (the first of each level takes the image's 3 channels at level 0,
+    else c, and has a 1x1 identity branch) dw_w [c_in][k][k], dw_b, ln_g,
+    ln_b [c_in], W1 [hid][c_in], b1 [hid], W2 [c][hid], b2 [c], (Wid [c][c_in],
+    bid [c]); then per level a head of c weights and a bias.  Weights
+    N(0, 1 / fan_in), biases and shifts N(0, 0.02^2), layer-norm scales
+    1 + N(0, 0.1^2), float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    g = lambda n, std, mean=0.0: parts.append(rng.normal(mean, std, size=n))  # noqa: E731
+    for lvl in range(levels):
+        for e in range(1 + extra):
+            ci = 3 if (lvl == 0 and e == 0) else c
+            g(ci * k * k, 1.0 / k)
+            g(ci, 0.02)
+            g(ci, 0.1, 1.0)
+            g(ci, 0.02)
+            g(hid * ci, 1.0 / np.sqrt(ci))
+            g(hid, 0.02)
+            g(c * hid, 1.0 / np.sqrt(hid))
+            g(c, 0.02)
+            if e == 0:
+                g(c * ci, 1.0 / np.sqrt(ci))
+                g(c, 0.02)
+    for lvl in range(levels):
+        g(c, 1.0 / np.sqrt(c))
+        g(1, 0.02)
     return np.concatenate(parts).astype(np.float32)
 
 

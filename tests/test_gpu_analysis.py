@@ -1,0 +1,142 @@
+"""GPU: the non-overfitted analysis transform (coolchic_analysis_forward)
+against the float64 oracle (oracle/analysis.py, same bfloat16 rounding
+points), through the C ABI.
+
+The rounding points make the transform sensitive to last-bit differences:
+the GPU computes the depth-wise convolution, the normalisation, GELU and the
+products' sums in float32, the oracle in float64, and a value within that
+difference of a bfloat16 rounding boundary rounds the other way (one
+bfloat16 step) and the blocks after it carry the change on.  The oracle
+itself moves by 0.07 % (level 0) to 1.4 % (level 6) of a grid's 2-norm when
+its input is perturbed at the float32 resolution (1e-7 relative), and by
+0.2 % to 0.6 % at 1e-6, the size of a float32 sum's rounding over the
+products' 64-256 terms.  The bar of the full transform is therefore
+measured per case: the GPU's deviation from the oracle, per latent grid, in
+the 2-norm and in the largest element, must be within ANA_K times the
+oracle's own deviation under a PERTURB perturbation of its input (plus
+ANA_FLOOR); the quantised latents agree wherever the oracle's value is
+farther than the element bar from a rounding boundary.
+
+A second case removes the chaos: with the second 1x1 convolution of every
+block zero (weights and bias), each block is its identity branch, so the
+latents depend only on the image, the pooling, the identity convolutions
+and the heads, through a few rounding points that the float32 sums rarely
+straddle: there the bar is half a bfloat16 step (2^-9) of each grid's
+2-norm (measured: below 1e-4 for levels 0-5, 3.3e-4 for level 6, which sits
+after six chained poolings)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.analysis as A
+from paper_2403_11651_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+ANA_K = 3.0
+ANA_FLOOR = 1e-4
+PERTURB = 1e-6
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_11651_amd import binding
+    return binding
+
+
+def _run(B, imgs, theta):
+    n, _, H, W = imgs.shape
+    n_lat = sum((H >> l) * (W >> l) for l in range(7))
+    x = torch.from_numpy(np.ascontiguousarray(imgs, np.float32)).cuda()
+    th = torch.from_numpy(np.ascontiguousarray(theta, np.float32)).cuda()
+    y = torch.full((n * n_lat,), float("nan"), device="cuda")
+    B.coolchic_analysis_forward(H, W, n, x, th, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().reshape(n, n_lat).astype(np.float64)
+
+
+def _sensitivity(img, theta, seed):
+    """Per grid: (relative 2-norm, largest element / largest magnitude) of the
+    oracle's change under a float32-resolution perturbation of the image."""
+    ys, _ = A.forward(img, theta)
+    rng = np.random.default_rng(seed)
+    ys2, _ = A.forward(img * (1.0 + PERTURB * rng.normal(size=img.shape)), theta)
+    out = []
+    for a, b in zip(ys, ys2):
+        out.append((np.linalg.norm(a - b) / np.linalg.norm(a), np.abs(a - b).max() / np.abs(a).max()))
+    return ys, out
+
+
+def _check(got, ys, sens, tag):
+    off = 0
+    rows = []
+    for l, (ref, (s_rel, s_elem)) in enumerate(zip(ys, sens)):
+        r = ref.ravel()
+        g = got[off:off + r.size]
+        off += r.size
+        assert np.all(np.isfinite(g)), (tag, l)
+        rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+        elem = np.abs(g - r).max() / np.abs(r).max()
+        bar_rel, bar_elem = ANA_K * s_rel + ANA_FLOOR, ANA_K * s_elem + ANA_FLOOR
+        rows.append((l, round(float(rel), 6), round(float(bar_rel), 6), round(float(elem), 6), round(float(bar_elem), 6)))
+        assert rel <= bar_rel and elem <= bar_elem, (tag, rows)
+        far = np.abs(r - np.floor(r) - 0.5) > bar_elem * np.abs(r).max()
+        assert np.array_equal(np.rint(g)[far], np.rint(r)[far]), (tag, l)
+    print(tag, "(level, rel, bar, elem, bar)", rows)
+
+
+@pytest.mark.parametrize("H,W,n", [(64, 64, 2), (128, 192, 1)])
+def test_analysis_matches_oracle(B, H, W, n):
+    theta = WL.analysis_params(40 + H)
+    imgs = np.stack([WL.image(50 + k, H, W, max(1, round(200 * H * W / (768 * 512)))) for k in range(n)])
+    got = _run(B, imgs, theta)
+    for k in range(n):
+        ys, sens = _sensitivity(imgs[k].astype(np.float64), theta.astype(np.float64), 90 + k)
+        _check(got[k], ys, sens, f"{H}x{W}[{k}]")
+
+
+def test_analysis_identity_paths_match_oracle(B):
+    """Every block reduced to its identity branch (W2 = 0, b2 = 0)."""
+    H, W = 128, 192
+    theta = WL.analysis_params(77).astype(np.float64)
+    blocks, _ = A.unpack(theta)  # views into theta
+    for p in blocks:
+        p["W2"][:] = 0.0
+        p["b2"][:] = 0.0
+    imgs = WL.image(78, H, W, 6)[None]
+    got = _run(B, imgs, theta)[0]
+    ys, _ = A.forward(imgs[0].astype(np.float64), theta)
+    off = 0
+    for l, ref in enumerate(ys):
+        r = ref.ravel()
+        g = got[off:off + r.size]
+        off += r.size
+        rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+        assert rel <= 2.0 ** -9, (l, rel)
+
+
+def test_analysis_batch_equals_single_images(B):
+    """Images are independent: a batch of three equals three single calls bit
+    for bit."""
+    H, W = 64, 128
+    theta = WL.analysis_params(7)
+    imgs = np.stack([WL.image(60 + k, H, W, 3) for k in range(3)])
+    got = _run(B, imgs, theta)
+    for k in range(3):
+        assert np.array_equal(got[k], _run(B, imgs[k:k + 1], theta)[0])
+
+
+def test_analysis_rejects_bad_sizes(B):
+    th = torch.zeros(B.analysis_param_count(), device="cuda")
+    x = torch.zeros(3 * 64 * 96, device="cuda")
+    y = torch.zeros(1, device="cuda")
+    ws = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+    assert B._lib.coolchic_analysis_forward(64, 96, 1, x.data_ptr(), th.data_ptr(), y.data_ptr(), ws.data_ptr(),
+                                            ws.numel(), None) == B.CC_EINVAL
+    n_lat = sum((64 >> l) * (64 >> l) for l in range(7))
+    x = torch.zeros(3 * 64 * 64, device="cuda")
+    y = torch.zeros(n_lat, device="cuda")
+    assert B._lib.coolchic_analysis_forward(64, 64, 1, x.data_ptr(), th.data_ptr(), y.data_ptr(), ws.data_ptr(),
+                                            16, None) == B.CC_EWORKSPACE

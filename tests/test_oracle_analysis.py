@@ -12,17 +12,12 @@ import torch
 import torch.nn.functional as F
 
 import oracle.analysis as A
+from paper_2403_11651_amd import workloads as WL
 from oracle.warmstart import bf16
 
 
-def _theta(seed, std=0.05):
-    rng = np.random.default_rng(seed)
-    th = rng.normal(0.0, std, A.param_count())
-    # layer-norm scales near 1 so that the features keep their size
-    blocks, _ = A.unpack(th)
-    for p in blocks:
-        p["ln_g"][:] = 1.0 + 0.1 * rng.normal(size=p["ln_g"].size)
-    return th
+def _theta(seed):
+    return WL.analysis_params(seed).astype(np.float64)
 
 
 def test_block_structure_and_param_count():
@@ -139,6 +134,13 @@ def test_rounding_points():
     ys, _ = A.forward(x, th, round_bf16=False)
     for a, b in zip(ys_r, ys):
         assert np.max(np.abs(a - b)) <= 0.05 * np.max(np.abs(b)) + 1e-6
+
+
+def test_seeded_parameters_match_the_layout():
+    th = WL.analysis_params(0)
+    assert th.size == A.param_count()
+    blocks, _ = A.unpack(th.astype(np.float64))
+    assert all(abs(np.mean(p["ln_g"]) - 1.0) < 0.1 for p in blocks)
 
 
 def test_encode_layout():
