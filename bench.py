@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "encoder fwd+bwd iters/s @768x512 (% FP32 roofline)"
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (vector and matrix)
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense bfloat16 matrix cores
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -303,6 +304,96 @@ def decode_latency_record(B):
                        "entropy decoding with the ARM on the decoded context, then upsampling and synthesis")
     out["paper_context"] = ("the paper's C decoder takes about 100 ms per 768x512 image on one AMD EPYC 7282 core "
                             "(its ARM at most 50 ms); different hardware, quoted as context only")
+    return out
+
+
+def analysis_record(B, reps=10):
+    """Non-overfitted encoding (Section IV-B): the analysis transform's
+    forward pass (coolchic_analysis_forward, seeded parameters) on 768x512
+    images, one and eight per call, then for one image the rounding of the
+    latents (coolchic_forward) and their entropy coding with the ARM of the
+    Table I 2300 decoder (24-wide context, shared 8x8 upsampler, 7-40-3
+    synthesis with two residual convs; random weights, so the rate only
+    shows the path runs)."""
+    import torch
+    from paper_2403_11651_amd import workloads as WL
+    H, W = 512, 768
+    dev = torch.device("cuda", 0)
+    n_param = B.analysis_param_count()
+    th = torch.from_numpy(WL.analysis_params(1)).to(dev)
+    # multiply-accumulates per pixel of the transform (depth-wise 7x7, the
+    # two 1x1 convolutions with 4x expansion, the identity convolutions and
+    # the heads) at this size, from the block structure
+    mac = 0
+    for lvl in range(7):
+        h, w = H >> lvl, W >> lvl
+        for e in range(3):
+            ci = 3 if (lvl == 0 and e == 0) else 64
+            mac += h * w * (ci * 49 + 256 * ci + 64 * 256 + (64 * ci if e == 0 else 0))
+        mac += h * w * 64
+    mac_px = mac / (H * W)
+    out = {"workload": "768x512 blob images, seeded analysis parameters (fan-in-scaled normal weights); "
+                       "21 ConvNeXt-style blocks, 64 features, 1x1 convolutions on bfloat16 matrix cores",
+           "params": n_param, "kmac_per_pixel": round(mac_px / 1000.0, 1)}
+    for n in (1, 8):
+        x = torch.from_numpy(np.stack([WL.image(300 + k, H, W, 200) for k in range(n)])).to(dev)
+        n_lat = sum((H >> l) * (W >> l) for l in range(7))
+        y = torch.empty(n * n_lat, device=dev)
+        ws = B.analysis_workspace(H, W, n, device=dev)
+        B.coolchic_analysis_forward(H, W, n, x, th, y, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        for _ in range(reps):
+            B.coolchic_analysis_forward(H, W, n, x, th, y, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if not bool(torch.isfinite(y).all()):
+            raise RuntimeError("non-finite analysis output")
+        tf = 2.0 * mac * n / (ms * 1e-3) / 1e12
+        out[f"images_{n}"] = {"ms_per_call": round(ms, 4), "ms_per_image": round(ms / n, 4),
+                              "tflops": round(tf, 2), "frac_bf16_peak": round(tf / BF16_PEAK_TFLOPS, 4)}
+    # one image through rounding and the entropy coder
+    arch = (7, 24, 2, 8, 40, 2, 1)
+    p = B.Problem(H, W, B.Arch(*arch))
+    na, nu, ns = B.param_count(B.Arch(*arch))
+    wts = torch.from_numpy(WL.weights(5, na + nu + ns)).to(dev)
+    a, u, sy = wts[:na], wts[na:na + nu], wts[na + nu:]
+    x = torch.from_numpy(WL.image(300, H, W, 200)[None]).to(dev)
+    n_lat = B.latent_count(p)
+    y = torch.empty(n_lat, device=dev)
+    yq = torch.empty(n_lat, device=dev)
+    l4 = torch.zeros(4, device=dev)
+    rate = torch.empty(n_lat, device=dev)
+    xhat = torch.empty(3 * H * W, device=dev)
+    buf = torch.zeros(B.entropy_bound(p), dtype=torch.uint8, device=dev)
+    nb = torch.zeros(1, dtype=torch.int64, device=dev)
+    wsa = B.analysis_workspace(H, W, 1, device=dev)
+    wse = B.entropy_workspace(p, device=dev)
+    wsf = B.workspace(p, B.CC_WS_FORWARD, device=dev)
+
+    def encode():
+        B.coolchic_analysis_forward(H, W, 1, x, th, y, ws=wsa)
+        B.coolchic_forward(p, x, y, None, a, u, sy, l4, rate, yq, xhat, ws=wsf)
+        B.coolchic_entropy_encode(p, yq, a, buf, nb, ws=wse)
+
+    encode()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(reps):
+        encode()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["encode_one_image"] = {"ms": round(e0.elapsed_time(e1) / reps, 4),
+                               "steps": "analysis forward, rounding (coolchic_forward), entropy coding",
+                               "bitstream_bytes": int(nb.item()),
+                               "decoder": "Table I 2300 row, random weights"}
+    out["paper_context"] = ("the paper reports N-O encoding at about 130 000 MAC per pixel on its complexity plot "
+                            "(160 k in the text), timed on other hardware; context only")
     return out
 
 
@@ -641,13 +732,15 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size reference for "
                          "the FETCH_SIZE / WRITE_SIZE hardware counters); not part of any timed step")
+    ap.add_argument("--analysis-only", action="store_true",
+                    help="only the non-overfitted encoding record (the analysis transform), as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path runs one image per GPU and images shard across GPUs with no "
               f"communication, so --gpus {args.gpus} is not run here", file=sys.stderr)
         sys.exit(2)
 
-    warm_images = None if args.no_warm_start else warm_start_images()
+    warm_images = None if (args.no_warm_start or args.analysis_only) else warm_start_images()
     import torch
     from paper_2403_11651_amd import binding as B
     if not torch.cuda.is_available():
@@ -664,6 +757,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.analysis_only:
+        print(json.dumps({"analysis_768x512": analysis_record(B)}), flush=True)
+        return
 
     K = args.steps
     rec = single_image_record(B, args.workload, K, args.warmup, repeats=0 if args.no_extra else 5)
@@ -701,6 +797,9 @@ def main():
         out["decode_synth"] = decode_record(B, "low")
         log(f"decode_synth: {out['decode_synth']['mpix_per_s']} Mpix/s")
         out["decode_768x512"] = decode_latency_record(B)
+        out["analysis_768x512"] = analysis_record(B)
+        log(f"analysis: {out['analysis_768x512']['images_8']['ms_per_image']} ms per 768x512 image "
+            f"({out['analysis_768x512']['images_8']['tflops']} TFLOP/s)")
         log(f"decode 768x512: {out['decode_768x512']['low']['decode_ms']} ms (low), "
             f"{out['decode_768x512']['full']['decode_ms']} ms (full)")
     if args.batch_iters > 0:

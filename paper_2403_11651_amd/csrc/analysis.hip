@@ -37,6 +37,7 @@ constexpr float AN_LN_EPS = 1e-6f;
 constexpr int AN_THREADS = 256;
 constexpr int AN_MAX_GRID = 1024;
 constexpr int AN_NT = 1;  // 32-position tiles per wave step of the MLP kernel
+constexpr int AN_DW_R = 4;  // consecutive positions per lane group of the depth-wise kernel
 
 // Per-block host-side description (offsets in floats into theta, in
 // uint16 into the bf16 operand area of the workspace).
@@ -102,9 +103,10 @@ __global__ __launch_bounds__(AN_THREADS) void ana_prep_kernel(AnPrepArgs a) {
 
 // ------------------------------------------------- depth-wise conv + norm
 
-// 64 input channels: eight lanes per position, eight channels each; the
-// normalisation's sums run over the eight lanes.  The first block (3 image
+// 64 input channels: eight lanes per group of AN_DW_R positions of a row,
+// eight channels each; the normalisation's sums run over the eight lanes.  The first block (3 image
 // channels): one thread per position, T padded to 16 channels.
+template <int S>
 __global__ __launch_bounds__(AN_THREADS) void ana_dw_kernel(AnArgs a) {
   __shared__ float s_w[AN_C * AN_TAPS];
   const int tid = threadIdx.x;
@@ -144,62 +146,109 @@ __global__ __launch_bounds__(AN_THREADS) void ana_dw_kernel(AnArgs a) {
   }
   for (int k = tid; k < AN_C * AN_TAPS; k += AN_THREADS) s_w[k] = a.dw_w[k];
   __syncthreads();
+  // eight lanes per group of AN_DW_R consecutive positions of a row; each
+  // input row's columns are loaded once and used by all the group's taps
+  constexpr int R = AN_DW_R;
+  const int gpr = (a.wo + R - 1) / R;  // groups per output row
+  const long long ngr = (long long)a.n * a.ho * gpr;
   const long long g = (long long)blockIdx.x * AN_THREADS + tid;
-  const long long px = g >> 3;
+  const long long grp = g >> 3;
   const int cg = (int)(g & 7);
-  const bool valid = px < npx;
-  const long long pc = valid ? px : npx - 1;
-  const int img = (int)(pc / ((long long)a.ho * a.wo)), r = (int)(pc % ((long long)a.ho * a.wo));
-  const int i = r / a.wo, j = r % a.wo;
-  float acc[8];
+  const bool valid = grp < ngr;
+  const long long gc = valid ? grp : ngr - 1;
+  const int img = (int)(gc / ((long long)a.ho * gpr)), rr = (int)(gc % ((long long)a.ho * gpr));
+  const int i = rr / gpr, j0 = (rr % gpr) * R;
+  float acc[R][8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) acc[e] = a.dw_b[cg * 8 + e];
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[q][e] = a.dw_b[cg * 8 + e];
   const uint16_t* base = a.fin + (size_t)img * a.hi * a.wi * AN_C + cg * 8;
   for (int dy = 0; dy < AN_K; ++dy) {
-    const int iy = a.stride * i + dy - 3;
+    const int iy = S * i + dy - 3;
     if (iy < 0 || iy >= a.hi) continue;
-    for (int dx = 0; dx < AN_K; ++dx) {
-      const int ix = a.stride * j + dx - 3;
-      if (ix < 0 || ix >= a.wi) continue;
-      const uint4 u = *reinterpret_cast<const uint4*>(base + ((size_t)iy * a.wi + ix) * AN_C);
-      const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
-      const int tap = dy * AN_K + dx;
+    // input columns s j0 - 3 .. s (j0 + R - 1) + 3
+    constexpr int NCOL = S * (R - 1) + AN_K;
+    uint4 col[NCOL];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc[2 * e] = __builtin_fmaf(s_w[(cg * 8 + 2 * e) * AN_TAPS + tap], bf16_f(w4[e] & 0xffffu), acc[2 * e]);
-        acc[2 * e + 1] = __builtin_fmaf(s_w[(cg * 8 + 2 * e + 1) * AN_TAPS + tap], bf16_f(w4[e] >> 16), acc[2 * e + 1]);
+    for (int c = 0; c < NCOL; ++c) {
+      const int ix = S * j0 - 3 + c;
+      col[c] = (ix >= 0 && ix < a.wi)
+                   ? *reinterpret_cast<const uint4*>(base + ((size_t)iy * a.wi + ix) * AN_C)
+                   : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int dx = 0; dx < AN_K; ++dx) {
+      float w[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = s_w[(cg * 8 + e) * AN_TAPS + dy * AN_K + dx];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint4 u = col[S * q + dx];
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[q][2 * e] = __builtin_fmaf(w[2 * e], bf16_f(w4[e] & 0xffffu), acc[q][2 * e]);
+          acc[q][2 * e + 1] = __builtin_fmaf(w[2 * e + 1], bf16_f(w4[e] >> 16), acc[q][2 * e + 1]);
+        }
       }
     }
   }
-  // normalisation over the 64 channels of the position (its eight lanes)
-  float s = 0.0f;
+  // normalisation over the 64 channels of each position (its eight lanes)
 #pragma unroll
-  for (int e = 0; e < 8; ++e) s += acc[e];
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
-  s += __shfl_xor(s, 4, 64);
-  const float mean = s / 64.0f;
-  float q = 0.0f;
+  for (int q = 0; q < R; ++q) {
+    float sm = 0.0f;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) q += (acc[e] - mean) * (acc[e] - mean);
-  q += __shfl_xor(q, 1, 64);
-  q += __shfl_xor(q, 2, 64);
-  q += __shfl_xor(q, 4, 64);
-  const float rs = 1.0f / sqrtf(q / 64.0f + AN_LN_EPS);
-  uint32_t o[4];
+    for (int e = 0; e < 8; ++e) sm += acc[q][e];
+    sm += __shfl_xor(sm, 1, 64);
+    sm += __shfl_xor(sm, 2, 64);
+    sm += __shfl_xor(sm, 4, 64);
+    const float mean = sm / 64.0f;
+    float sq = 0.0f;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int c = cg * 8 + 2 * e;
-    const uint32_t lo = bf16_bits((acc[2 * e] - mean) * rs * a.ln_g[c] + a.ln_b[c]);
-    const uint32_t hi = bf16_bits((acc[2 * e + 1] - mean) * rs * a.ln_g[c + 1] + a.ln_b[c + 1]);
-    o[e] = lo | (hi << 16);
+    for (int e = 0; e < 8; ++e) sq += (acc[q][e] - mean) * (acc[q][e] - mean);
+    sq += __shfl_xor(sq, 1, 64);
+    sq += __shfl_xor(sq, 2, 64);
+    sq += __shfl_xor(sq, 4, 64);
+    const float rs = 1.0f / sqrtf(sq / 64.0f + AN_LN_EPS);
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = cg * 8 + 2 * e;
+      const uint32_t lo = bf16_bits((acc[q][2 * e] - mean) * rs * a.ln_g[c] + a.ln_b[c]);
+      const uint32_t hi = bf16_bits((acc[q][2 * e + 1] - mean) * rs * a.ln_g[c + 1] + a.ln_b[c + 1]);
+      o[e] = lo | (hi << 16);
+    }
+    const int j = j0 + q;
+    if (valid && j < a.wo) {
+      const size_t px = ((size_t)img * a.ho + i) * a.wo + j;
+      *reinterpret_cast<uint4*>(a.t + px * AN_C + cg * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
   }
-  if (valid) *reinterpret_cast<uint4*>(a.t + px * AN_C + cg * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // --------------------------------------------------------- 1x1 MLP block
 
-__device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26:
+// erf(z) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-z^2),
+// t = 1 / (1 + p z), z >= 0 (odd extension), absolute error <= 1.5e-7 --
+// far below the bfloat16 rounding of the GELU output; a quarter of the
+// instructions of the library erff, whose cost made the block VALU bound.
+__device__ __forceinline__ float erf_as(float z) {
+  const float a = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, a, 1.0f));
+  float poly = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+  poly = __builtin_fmaf(poly, t, 1.421413741f);
+  poly = __builtin_fmaf(poly, t, -0.284496736f);
+  poly = __builtin_fmaf(poly, t, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);  // exp(-z^2)
+  const float r = __builtin_fmaf(-poly, e, 1.0f);
+  return copysignf(r, z);
+}
+__device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erf_as(v * 0.70710678118654752f)); }
+// round to the nearest bfloat16 (ties to even) with the hardware conversion
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 template <int KIN>
 __global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
@@ -273,7 +322,7 @@ __global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            hb[n2][t][e] = __builtin_bit_cast(__bf16, bf16_bits(gelu(acc1[n2][8 * t + e])));
+            hb[n2][t][e] = (__bf16)gelu(acc1[n2][8 * t + e]);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -300,7 +349,7 @@ __global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
             for (int e = 0; e < 8; ++e) {
               const int ch = kk * 16 + hi * 8 + e;
               const float v = ok[n2] && ch < 3 ? a.x[(((size_t)img * 3 + ch) * a.hi + i) * a.wi + j] : 0.0f;
-              sb[n2][e] = __builtin_bit_cast(__bf16, bf16_bits(v));
+              sb[n2][e] = (__bf16)v;
             }
           } else {
             float v[8];
@@ -319,7 +368,7 @@ __global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
               }
             }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) sb[n2][e] = __builtin_bit_cast(__bf16, bf16_bits(v[e] * 0.25f));
+            for (int e = 0; e < 8; ++e) sb[n2][e] = (__bf16)(v[e] * 0.25f);
           }
         }
 #pragma unroll
@@ -353,7 +402,7 @@ __global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
           uint32_t h[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            h[e] = bf16_bits(v[e]);
+            h[e] = bf16_rne(v[e]);
             hsum = __builtin_fmaf(s_hw[ch0 + e], bf16_f(h[e]), hsum);
           }
           if (ok[n2]) *reinterpret_cast<uint2*>(a.fout + pc * AN_C + ch0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
@@ -497,8 +546,8 @@ int coolchic_analysis_forward(int32_t H, int32_t W, int32_t n, const float* x, c
     a.y = y; a.n_lat = n_lat; a.loff = loff[B.level];
     const long long npx = (long long)n * a.ho * a.wo;
     void* argv[] = {&a};
-    const long long dw_threads = B.c_in == 3 ? npx : npx * 8;
-    if (hipLaunchKernel((const void*)ana_dw_kernel, dim3((unsigned)((dw_threads + AN_THREADS - 1) / AN_THREADS)),
+    const long long dw_threads = B.c_in == 3 ? npx : (long long)n * a.ho * ((a.wo + AN_DW_R - 1) / AN_DW_R) * 8;
+    if (hipLaunchKernel(B.stride == 2 ? (const void*)ana_dw_kernel<2> : (const void*)ana_dw_kernel<1>, dim3((unsigned)((dw_threads + AN_THREADS - 1) / AN_THREADS)),
                         dim3(AN_THREADS), argv, 0, st) != hipSuccess)
       return CC_EHIP;
     const long long groups = (npx + 32 * AN_NT - 1) / (32 * AN_NT);

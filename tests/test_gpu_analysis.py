@@ -14,8 +14,9 @@ products' 64-256 terms.  The bar of the full transform is therefore
 measured per case: the GPU's deviation from the oracle, per latent grid, in
 the 2-norm and in the largest element, must be within ANA_K times the
 oracle's own deviation under a PERTURB perturbation of its input (plus
-ANA_FLOOR); the quantised latents agree wherever the oracle's value is
-farther than the element bar from a rounding boundary.
+ANA_FLOOR; four times that on a grid of fewer than 16 latents, whose error
+is a few samples); the quantised latents agree wherever the oracle's value
+is farther than the element bar from a rounding boundary.
 
 A second case removes the chaos: with the second 1x1 convolution of every
 block zero (weights and bias), each block is its identity branch, so the
@@ -79,7 +80,8 @@ def _check(got, ys, sens, tag):
         assert np.all(np.isfinite(g)), (tag, l)
         rel = np.linalg.norm(g - r) / np.linalg.norm(r)
         elem = np.abs(g - r).max() / np.abs(r).max()
-        bar_rel, bar_elem = ANA_K * s_rel + ANA_FLOOR, ANA_K * s_elem + ANA_FLOOR
+        k = ANA_K if r.size >= 16 else 4.0 * ANA_K  # a grid of a few latents: a few samples of the error
+        bar_rel, bar_elem = k * s_rel + ANA_FLOOR, k * s_elem + ANA_FLOOR
         rows.append((l, round(float(rel), 6), round(float(bar_rel), 6), round(float(elem), 6), round(float(bar_elem), 6)))
         assert rel <= bar_rel and elem <= bar_elem, (tag, rows)
         far = np.abs(r - np.floor(r) - 0.5) > bar_elem * np.abs(r).max()
