@@ -196,6 +196,33 @@ def forward(x, theta, round_bf16=True):
     return ys, feats
 
 
+def window_latents(x, theta, level, i0, j0, n, round_bf16=True):
+    """Latents [i0:i0+n][j0:j0+n] of grid `level` (< 4) computed from a window
+    of the image only.  A block's output at a position depends on its input
+    within 3 positions (the 7x7 depth-wise kernel; the pooled identity reads
+    2q and 2q + 1), so the last block of level l depends on the image within
+    9 (l = 0), 25, 57, 121 pixels of its footprint; a margin of 16 * 2^l
+    pixels, aligned to 2^l so that every stride keeps its phase, covers it,
+    and where the window meets the image border the zero padding is the
+    image's own."""
+    x = np.asarray(x, dtype=np.float64)
+    s = 1 << level
+    H, W = x.shape[1:]
+    m = 16 * s
+    r0, r1 = max(0, i0 * s - m), min(H, (i0 + n) * s + m)
+    c0, c1 = max(0, j0 * s - m), min(W, (j0 + n) * s + m)
+    blocks, heads = unpack(theta)
+    f = x[:, r0:r1, c0:c1]
+    for p in blocks:
+        if p["level"] > level:
+            break
+        f = block(f, p, round_bf16)
+    hw, hb = heads[level]
+    y = np.einsum("i,ihw->hw", hw, f) + hb
+    a, b = i0 - r0 // s, j0 - c0 // s
+    return y[a:a + n, b:b + n]
+
+
 def encode(x, theta, round_bf16=True):
     """N-O encoding (Section IV-B): the packed latent vector of Cool-chic's
     layout (level 0 first, each grid in raster order), quantised by

@@ -99,6 +99,47 @@ def test_analysis_matches_oracle(B, H, W, n):
         _check(got[k], ys, sens, f"{H}x{W}[{k}]")
 
 
+def _grid(flat, H, W, level):
+    off = sum((H >> l) * (W >> l) for l in range(level))
+    return flat[off:off + (H >> level) * (W >> level)].reshape(H >> level, W >> level)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_analysis_full_size_windows(B, level):
+    """768x512 in the launch the benchmark times for one image: windows of
+    latent grids 0-2 (a corner, where the zero padding is the image's, and an
+    interior window) against the oracle computed from a window of the image
+    (oracle.analysis.window_latents), with the bar of the oracle's own
+    sensitivity measured on the same window."""
+    H, W = 512, 768
+    theta = WL.analysis_params(31)
+    img = WL.image(10, H, W, 200)
+    got = _run(B, img[None], theta)[0]
+    th64, x64 = theta.astype(np.float64), img.astype(np.float64)
+    rng = np.random.default_rng(5 + level)
+    h, w = H >> level, W >> level
+    n = 8
+    for (i0, j0) in [(0, 0), (int(rng.integers(8, h - 16)), int(rng.integers(8, w - 16)))]:
+        ref = A.window_latents(x64, th64, level, i0, j0, n)
+        pert = x64 * (1.0 + PERTURB * rng.normal(size=x64.shape))
+        ref2 = A.window_latents(pert, th64, level, i0, j0, n)
+        sens = [(np.linalg.norm(ref - ref2) / np.linalg.norm(ref), np.abs(ref - ref2).max() / np.abs(ref).max())]
+        g = _grid(got, H, W, level)[i0:i0 + n, j0:j0 + n]
+        _check(g.ravel(), [ref], sens, f"768x512 level {level} window ({i0}, {j0})")
+
+
+def test_analysis_full_size_eight_images_per_call(B):
+    """The benchmark's batched launch (eight 768x512 images per call) gives
+    every image exactly its single-image result; every latent is finite."""
+    H, W = 512, 768
+    theta = WL.analysis_params(32)
+    imgs = np.stack([WL.image(100 + k, H, W, 200) for k in range(8)])
+    got = _run(B, imgs, theta)
+    assert np.all(np.isfinite(got))
+    for k in (0, 5, 7):
+        assert np.array_equal(got[k], _run(B, imgs[k:k + 1], theta)[0]), k
+
+
 def test_analysis_identity_paths_match_oracle(B):
     """Every block reduced to its identity branch (W2 = 0, b2 = 0)."""
     H, W = 128, 192

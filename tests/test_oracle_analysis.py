@@ -152,3 +152,15 @@ def test_encode_layout():
     assert np.array_equal(yq, np.rint(y))
     ys, _ = A.forward(x, th)
     assert np.array_equal(y[:64 * 64], ys[0].ravel()) and y[-1] == ys[6].ravel()[-1]
+
+
+def test_window_latents_equal_the_whole_transform():
+    """The receptive-field margins of window_latents: grids 0-3 from windows
+    of the image equal the whole-image transform exactly, at the border and
+    inside (rounding on, so the same float64 operations must be done)."""
+    x = WL.image(2, 128, 192, 6).astype(np.float64)
+    th = _theta(1)
+    ys, _ = A.forward(x, th)
+    for l, i0, j0, n in [(0, 0, 0, 8), (0, 60, 100, 8), (1, 0, 88, 8), (1, 30, 40, 6), (2, 8, 20, 8), (3, 2, 3, 4)]:
+        w = A.window_latents(x, th, l, i0, j0, n)
+        assert np.array_equal(w, ys[l][i0:i0 + n, j0:j0 + n]), (l, i0, j0)
