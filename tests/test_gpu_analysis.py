@@ -110,7 +110,11 @@ def test_analysis_full_size_windows(B, level):
     latent grids 0-2 (a corner, where the zero padding is the image's, and an
     interior window) against the oracle computed from a window of the image
     (oracle.analysis.window_latents), with the bar of the oracle's own
-    sensitivity measured on the same window."""
+    sensitivity measured on the same window.  A window holds 1024 (grids 0
+    and 1) or 144 latents: in an 8x8 window of grid 0 the oracle's
+    sensitivity is zero for some perturbations (no rounding flips reach its
+    64 latents) and 2-3e-3 for others; over 32x32 latents it stays within
+    1.2-2.6e-3 over five draws, so the bar takes the larger of two draws."""
     H, W = 512, 768
     theta = WL.analysis_params(31)
     img = WL.image(10, H, W, 200)
@@ -118,14 +122,17 @@ def test_analysis_full_size_windows(B, level):
     th64, x64 = theta.astype(np.float64), img.astype(np.float64)
     rng = np.random.default_rng(5 + level)
     h, w = H >> level, W >> level
-    n = 8
-    for (i0, j0) in [(0, 0), (int(rng.integers(8, h - 16)), int(rng.integers(8, w - 16)))]:
+    n = (32, 32, 12)[level]
+    for (i0, j0) in [(0, 0), (int(rng.integers(8, h - n - 8)), int(rng.integers(8, w - n - 8)))]:
         ref = A.window_latents(x64, th64, level, i0, j0, n)
-        pert = x64 * (1.0 + PERTURB * rng.normal(size=x64.shape))
-        ref2 = A.window_latents(pert, th64, level, i0, j0, n)
-        sens = [(np.linalg.norm(ref - ref2) / np.linalg.norm(ref), np.abs(ref - ref2).max() / np.abs(ref).max())]
+        s_rel = s_elem = 0.0
+        for _ in range(2):
+            pert = x64 * (1.0 + PERTURB * rng.normal(size=x64.shape))
+            ref2 = A.window_latents(pert, th64, level, i0, j0, n)
+            s_rel = max(s_rel, np.linalg.norm(ref - ref2) / np.linalg.norm(ref))
+            s_elem = max(s_elem, np.abs(ref - ref2).max() / np.abs(ref).max())
         g = _grid(got, H, W, level)[i0:i0 + n, j0:j0 + n]
-        _check(g.ravel(), [ref], sens, f"768x512 level {level} window ({i0}, {j0})")
+        _check(g.ravel(), [ref], [(s_rel, s_elem)], f"768x512 level {level} window ({i0}, {j0})")
 
 
 def test_analysis_full_size_eight_images_per_call(B):
