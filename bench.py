@@ -158,7 +158,7 @@ def run_batched(B, iters, graph_steps=50, log=None):
             "ms_per_iteration": round(1000.0 * secs / iters, 5),
             "mpix_iters_per_s": round(px * iters / secs / 1e6, 1),
             "tuning": {"arm_blocks": tuned["tune"][0], "syn_blocks": tuned["tune"][1],
-                       "arm_first": tuned["tune"][2], "cached": tuned["cached"],
+                       "arm_first": tuned["tune"][2], "ups_tile": tuned["tune"][3], "cached": tuned["cached"],
                        "tune_s": round(tune_s, 2), "candidates_ms": tuned.get("timings")},
             "graph_steps": graph_steps, "capture_s": round(capture_s, 4),
             "loss_start_mean": float(loss0[:, 0].mean()), "loss_end_mean": float(l4[:, 0].mean()),

@@ -263,12 +263,14 @@ typedef struct {
    grid coolchic_backward uses; then the results are bit-identical to it);
    arm_first selects where the ARM launch is forked onto the side stream:
    0 after the residual-conv backward, 1 before the upsampling and synthesis
-   launches, 2 after the head backward (the order changes no result; any
-   other value is CC_EINVAL). */
+   launches, 2 after the head backward; ups_tile is the side of the level-1
+   tile of one work-group of the upsampling forward, 16 or 32 (0 selects 32).
+   Neither changes a result; any other value is CC_EINVAL. */
 typedef struct {
   int32_t arm_blocks;
   int32_t syn_blocks;
   int32_t arm_first;
+  int32_t ups_tile;
 } cc_batch_tuning;
 
 typedef struct cc_batch cc_batch; /* opaque host-side plan */

@@ -82,7 +82,7 @@ class BatchEncoder:
         self._na, self._nu, self._ns = na, nu, ns
         self.plans = {}
         self.mode = B.CC_QUANT_ROUND
-        self.tune = tuple(int(t) for t in tune) + (0,) * (3 - len(tune))
+        self.tune = tuple(int(t) for t in tune) + (0,) * (4 - len(tune))
         self.plan = self._plan(self.mode)
 
     # -- views of image k's parameters and gradients
@@ -113,7 +113,7 @@ class BatchEncoder:
         return self.plans[mode]
 
     def set_tuning(self, tune):
-        tune = tuple(int(t) for t in tune) + (0,) * (3 - len(tune))
+        tune = tuple(int(t) for t in tune) + (0,) * (4 - len(tune))
         if tune != self.tune:
             for p in self.plans.values():
                 p.close()
@@ -227,6 +227,7 @@ class BatchEncoder:
 ARM_CANDIDATES = (0, 512, 1024, 2048, 4096)
 ARM_FIRST_CANDIDATES = (0, 1, 2)
 SYN_CANDIDATES = (0, 512, 1024, 2048, 4096)
+UPS_TILE_CANDIDATES = (32, 16)  # level-1 tile side of the upsampling forward
 _cache_lock = threading.Lock()
 
 
@@ -297,10 +298,11 @@ def time_iteration(enc: BatchEncoder, iters=10, reps=3):
 
 
 def autotune(enc: BatchEncoder, use_cache=True, iters=10, reps=3, log=None):
-    """Chooses (arm_blocks, syn_blocks, arm_first) for enc by coordinate
-    search over the candidate lists (the ARM's launch position, then its
-    grid with the default synthesis shape, then the synthesis shape), timing
-    whole training iterations.  The encoder's state is restored afterwards;
+    """Chooses (arm_blocks, syn_blocks, arm_first, ups_tile) for enc by
+    coordinate search over the candidate lists (the ARM's launch position,
+    then its grid with the default synthesis shape, then the synthesis
+    shape, then the upsampling forward's tile side), timing whole training
+    iterations.  The encoder's state is restored afterwards;
     the choice is applied and returned, with the timings, and cached."""
     path = cache_path()
     key = tuning_key(enc)
@@ -320,9 +322,11 @@ def autotune(enc: BatchEncoder, use_cache=True, iters=10, reps=3, log=None):
                 log(f"autotune {t}: {timings[t]:.4f} ms/iter")
         return timings[t]
 
-    best_f = min(ARM_FIRST_CANDIDATES, key=lambda f: measure((0, 0, f)))
-    best_a = min(ARM_CANDIDATES, key=lambda a: measure((a, 0, best_f)))
-    best = min(((best_a, s, best_f) for s in SYN_CANDIDATES), key=measure)
+    t0 = UPS_TILE_CANDIDATES[0]
+    best_f = min(ARM_FIRST_CANDIDATES, key=lambda f: measure((0, 0, f, t0)))
+    best_a = min(ARM_CANDIDATES, key=lambda a: measure((a, 0, best_f, t0)))
+    best_s = min(SYN_CANDIDATES, key=lambda s: measure((best_a, s, best_f, t0)))
+    best = min(((best_a, best_s, best_f, t) for t in UPS_TILE_CANDIDATES), key=measure)
     enc.load(state)
     enc.set_tuning(best)
     result = dict(tune=list(best), ms_per_iter=timings[best],

@@ -56,7 +56,8 @@ class CCImageIO(ctypes.Structure):
 
 
 class CCBatchTuning(ctypes.Structure):
-    _fields_ = [("arm_blocks", ctypes.c_int32), ("syn_blocks", ctypes.c_int32), ("arm_first", ctypes.c_int32)]
+    _fields_ = [("arm_blocks", ctypes.c_int32), ("syn_blocks", ctypes.c_int32), ("arm_first", ctypes.c_int32),
+                ("ups_tile", ctypes.c_int32)]
 
 
 class CoolChicError(RuntimeError):
@@ -393,9 +394,18 @@ class TimingEvent:
             self.handle = None
 
 
-def batch_workspace_bytes(probs, tune=(0, 0, 0)) -> int:
+def _tuning(tune):
+    """cc_batch_tuning from a tuple (arm_blocks, syn_blocks, arm_first,
+    ups_tile); missing trailing entries are 0 (the defaults)."""
+    tune = tuple(int(t) for t in tune)
+    if len(tune) > 4:
+        raise ValueError("tune has at most 4 entries")
+    return CCBatchTuning(*(tune + (0,) * (4 - len(tune))))
+
+
+def batch_workspace_bytes(probs, tune=(0, 0, 0, 0)) -> int:
     arr = (CCProblem * len(probs))(*[p.c() for p in probs])
-    t = CCBatchTuning(*(tuple(tune) + (0,) * (3 - len(tune))))
+    t = _tuning(tune)
     return int(_lib.coolchic_batch_workspace_bytes(len(probs), arr, ctypes.byref(t)))
 
 
@@ -405,7 +415,7 @@ class BatchPlan:
     keeps references to them and to its workspace so the pointers it holds stay
     valid."""
 
-    def __init__(self, probs, io, tune=(0, 0, 0), dloss=1.0, device="cuda"):
+    def __init__(self, probs, io, tune=(0, 0, 0, 0), dloss=1.0, device="cuda"):
         n = len(probs)
         if n == 0 or len(io) != n:
             raise ValueError("probs and io must be non-empty lists of equal length")
@@ -419,7 +429,7 @@ class BatchPlan:
                      "loss4": 4, "g_y": n_lat, "g_arm": na, "g_ups": nu, "g_syn": ns}
             for name, size in sizes.items():
                 setattr(ios[k], name, _ptr(d.get(name), size, f"io[{k}].{name}"))
-        t = CCBatchTuning(*(tuple(self.tune) + (0,) * (3 - len(self.tune))))
+        t = _tuning(self.tune)
         nbytes = int(_lib.coolchic_batch_workspace_bytes(n, arr, ctypes.byref(t)))
         if nbytes == 0:
             raise CoolChicError(CC_EINVAL, "coolchic_batch_workspace_bytes")

@@ -701,7 +701,7 @@ namespace {
 
 // Host-side plan of a batch.
 struct BatchPlan {
-  int n = 0, L = 0, device = 0, shared = 0, arm_first = 0;
+  int n = 0, L = 0, device = 0, shared = 0, arm_first = 0, ups_tile = UF_T_BATCH;
   const void *armk = nullptr, *t0k = nullptr, *bwk = nullptr, *hdk = nullptr;
   // device arrays inside the workspace
   ArmArgs* d_arm = nullptr;
@@ -713,6 +713,12 @@ struct BatchPlan {
            *w_upb[MAXL] = {}, *w_comb_side = nullptr, *w_comb_main = nullptr;
   int n_arm = 0, n_upf = 0, n_t0 = 0, n_syn = 0, n_head = 0, n_upb[MAXL] = {}, n_comb_side = 0, n_comb_main = 0;
 };
+
+// level-1 tile side of the batched upsampling forward; 0 for an invalid choice
+int batch_ups_tile(const cc_batch_tuning* tune) {
+  const int t = tune ? tune->ups_tile : 0;
+  return t == 0 ? UF_T_BATCH : (t == 16 || t == 32) ? t : 0;
+}
 
 int share(int total, long long part, long long whole, int cap) {
   if (total <= 0) return 0;  // default grid
@@ -737,6 +743,8 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
   }
   const int ta = tune ? tune->arm_blocks : 0, ts = tune ? tune->syn_blocks : 0;
   if (tune && (tune->arm_first < 0 || tune->arm_first > 2)) return CC_EINVAL;
+  const int ut = batch_ups_tile(tune);
+  if (!ut) return CC_EINVAL;
   img_off.resize(n);
   size_t cur = 0;
   for (int k = 0; k < n; ++k) {
@@ -763,7 +771,7 @@ int batch_layout(int n, const cc_problem* probs, const cc_batch_tuning* tune, st
     // the combine launches: reduction and fold blocks, and the loss block
     items += P.arm_grid + P.syn_grid + t0_tiles(P.geo.H, P.geo.W) + P.head_grid + P.red_grid + P.fold_grid0 +
              P.fold_grid1 + 1;
-    items += cdiv(P.geo.lh[1], UF_T_BATCH) * cdiv(P.geo.lw[1], UF_T_BATCH);
+    items += cdiv(P.geo.lh[1], ut) * cdiv(P.geo.lw[1], ut);
     for (int s = 0; s + 1 < L; ++s) items += (long long)P.ups_grid[s] * P.ups_chunks[s];
   }
   blk(sizeof(WorkItem) * items + 256 * (L + 8));
@@ -813,6 +821,7 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
   B.L = L;
   B.shared = plans[0].shared;
   B.arm_first = tune ? tune->arm_first : 0;
+  B.ups_tile = batch_ups_tile(tune);
   B.armk = arm_kernel_for(P0.C, P0.NH, true, true);
   B.t0k = syn_t0_kernel_for(P0.Hs, P0.nres, true);
   B.bwk = syn_bwd_kernel_for(P0.Hs, P0.nres, true);
@@ -839,8 +848,8 @@ int coolchic_batch_create(int32_t n, const cc_problem* probs, const cc_image_io*
     h_comb_side[k] = b->comb_side; h_comb_main[k] = b->comb_main;
     for (int s = 0; s + 1 < L; ++s) h_upb[s][k] = b->upb[s];
     for (int i = 0; i < P.arm_grid; ++i) w_arm.push_back(WorkItem{k, i, P.arm_grid, 0});
-    // the batched upsampling forward takes UF_T_BATCH tiles
-    const int upf = b->upf_grid ? cdiv(P.geo.lh[1], UF_T_BATCH) * cdiv(P.geo.lw[1], UF_T_BATCH) : 0;
+    // the batched upsampling forward takes tiles of side B.ups_tile
+    const int upf = b->upf_grid ? cdiv(P.geo.lh[1], B.ups_tile) * cdiv(P.geo.lw[1], B.ups_tile) : 0;
     for (int i = 0; i < upf; ++i) w_upf.push_back(WorkItem{k, i, upf, 0});
     for (int i = 0; i < b->t0_grid; ++i) w_t0.push_back(WorkItem{k, i, b->t0_grid, 0});
     for (int i = 0; i < P.syn_grid; ++i) w_syn.push_back(WorkItem{k, i, P.syn_grid, 0});
@@ -924,7 +933,7 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     return CC_OK;
   };
   if (B.arm_first == 1 && (rc = arm())) return rc;
-  if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
+  if ((rc = go(CC_STAGE_NONE, ups_fwd_kernel_for(B.shared, true, B.ups_tile), B.n_upf, 256, B.d_upf, B.w_upf))) return rc;
   if ((rc = go(CC_STAGE_NONE, B.t0k, B.n_t0, 256, B.d_syn, B.w_t0))) return rc;
   if ((rc = go(CC_STAGE_SYNTHESIS, B.bwk, B.n_syn, SYN_THREADS, B.d_syn, B.w_syn))) return rc;
   if (B.arm_first == 0 && (rc = arm())) return rc;

@@ -54,7 +54,8 @@ struct FoldArgs {
 // ---------------------------------------------------------------- upsampling
 // level-1 tile side of the upsampling forward (one work-group per tile):
 // small tiles fill the device for one image; a batch has work-groups to
-// spare and keeps the halo recompute of larger tiles low
+// spare and keeps the halo recompute of larger tiles low (its default; the
+// batch also runs 16)
 constexpr int UF_T = 16, UF_T_BATCH = 32;
 // Upsampler kernels: separable, [L-1][2][8] (vertical, horizontal taps per
 // step), or shared (Table I "1-1-TConv-K"): one non-separable [8][8] kernel
@@ -70,8 +71,9 @@ struct UpsFwdArgs {
   float* up_out[MAXL];         // U_s output [(L-1-s)][h_s][w_s] for s = 1..L-2
 };
 // kernel handles (host stub addresses); batch: the variant taking
-// (const UpsFwdArgs* descs, const WorkItem* work)
-const void* ups_fwd_kernel_for(bool shared, bool batch);
+// (const UpsFwdArgs* descs, const WorkItem* work) with level-1 tiles of side
+// tile (16 or 32; nullptr otherwise); the single-image kernel ignores tile
+const void* ups_fwd_kernel_for(bool shared, bool batch, int tile = UF_T);
 
 struct UpsBwdArgs {
   Geo geo;

@@ -336,11 +336,11 @@ __global__ void ups_expand_kernel(const float* __restrict__ src, float* __restri
 
 template <bool SH>
 __global__ __launch_bounds__(256) void ups_fwd_kernel_t(UpsFwdArgs a) { ups_fwd_body<UF_T, SH>(a, blockIdx.x); }
-template <bool SH>
+template <int T, bool SH>
 __global__ __launch_bounds__(256) void ups_fwd_kernel_batch_t(const UpsFwdArgs* __restrict__ d,
                                                               const WorkItem* __restrict__ w) {
   const WorkItem it = w[blockIdx.x];
-  ups_fwd_body<UF_T_BATCH, SH>(d[it.img], it.bid);
+  ups_fwd_body<T, SH>(d[it.img], it.bid);
 }
 template <bool SH>
 __global__ __launch_bounds__(256) void ups_bwd_kernel_t(UpsBwdArgs a) {
@@ -353,8 +353,12 @@ __global__ __launch_bounds__(256) void ups_bwd_kernel_batch_t(const UpsBwdArgs* 
   ups_bwd_body<SH>(d[it.img], it.bid, it.nblk, it.aux);
 }
 
-const void* ups_fwd_kernel_for(bool shared, bool batch) {
-  if (batch) return shared ? (const void*)ups_fwd_kernel_batch_t<true> : (const void*)ups_fwd_kernel_batch_t<false>;
+const void* ups_fwd_kernel_for(bool shared, bool batch, int tile) {
+  if (batch && tile == 16)
+    return shared ? (const void*)ups_fwd_kernel_batch_t<16, true> : (const void*)ups_fwd_kernel_batch_t<16, false>;
+  if (batch && tile == 32)
+    return shared ? (const void*)ups_fwd_kernel_batch_t<32, true> : (const void*)ups_fwd_kernel_batch_t<32, false>;
+  if (batch) return nullptr;
   return shared ? (const void*)ups_fwd_kernel_t<true> : (const void*)ups_fwd_kernel_t<false>;
 }
 const void* ups_bwd_kernel_for(bool shared, bool batch) {

@@ -98,7 +98,7 @@ def test_null_pointers_and_small_workspace(B):
 
 def _batch(B, probs):
     arr = (B.CCProblem * len(probs))(*[p.c() for p in probs])
-    return arr, B.CCBatchTuning(0, 0)
+    return arr, B.CCBatchTuning(0, 0, 0, 0)
 
 
 def test_batch_workspace_bytes(B):
@@ -117,6 +117,12 @@ def test_batch_workspace_bytes(B):
     assert B.lib.coolchic_batch_workspace_bytes(0, arr, ctypes.byref(t)) == 0
     assert B.lib.coolchic_batch_workspace_bytes(1, None, ctypes.byref(t)) == 0
     assert B.lib.coolchic_batch_workspace_bytes(1, arr, None) == one  # NULL tuning = default shapes
+    # the upsampling forward's tile side: 16 means four times the work items of 32; others are invalid
+    assert B.batch_workspace_bytes([a, b], (0, 0, 0, 32)) == two
+    assert B.batch_workspace_bytes([a, b], (0, 0, 0, 16)) >= two
+    for bad in (8, 24, 64, -16):
+        assert B.batch_workspace_bytes([a, b], (0, 0, 0, bad)) == 0
+    assert B.batch_workspace_bytes([a, b], (0, 0, 3)) == 0
 
 
 def test_batch_create_argument_checks(B):

@@ -36,7 +36,7 @@ def batch_cases(arch, sizes, seed0=100):
                     n_blobs=max(3, H * W // 2048)) for k, (H, W) in enumerate(sizes)]
 
 
-def make_encoder(B, BT, cs, tune=(0, 0, 0)):
+def make_encoder(B, BT, cs, tune=(0, 0, 0, 0)):
     probs = [B.Problem(c.H, c.W, B.Arch(*c.arch), B.CC_QUANT_ROUND, c.lam) for c in cs]
     return BT.BatchEncoder(probs, [c.img for c in cs], [c.y for c in cs], [(c.arm, c.ups, c.syn) for c in cs],
                            tune=tune)
@@ -61,12 +61,14 @@ def check_vs_oracle(c, loss4, grads):
         assert_grad_close(f"{c.name}.{name}", g, ref[name])
 
 
-@pytest.mark.parametrize("arch", [CS.LOW, CS.FULL], ids=["low", "full"])
-def test_batch_default_equals_single_calls(B, BT, arch):
+@pytest.mark.parametrize("arch,tile", [(CS.LOW, 0), (CS.FULL, 0), (CS.LOW, 16)], ids=["low", "full", "low_tile16"])
+def test_batch_default_equals_single_calls(B, BT, arch, tile):
     """With the default launch shape the batched pass runs the same blocks
-    over the same tiles as one coolchic_backward per image: bit-identical."""
+    over the same tiles as one coolchic_backward per image: bit-identical.
+    The upsampling forward's tile side only changes which work-group
+    computes an output, not its arithmetic: bit-identical too."""
     cs = batch_cases(arch, SMALL_SIZES)
-    enc = make_encoder(B, BT, cs)
+    enc = make_encoder(B, BT, cs, tune=(0, 0, 0, tile))
     enc.backward()
     torch.cuda.synchronize()
     L = enc.loss.cpu().numpy()
@@ -78,7 +80,7 @@ def test_batch_default_equals_single_calls(B, BT, arch):
 
 
 @pytest.mark.parametrize("tune", [(0, 0, 0), (7, 5, 0), (4096, 4096, 0), (0, 0, 1), (512, 2048, 1), (0, 0, 2),
-                                  (1024, 512, 2)])
+                                  (1024, 512, 2), (7, 5, 1, 16), (0, 0, 2, 32)])
 def test_batch_vs_oracle(B, BT, tune):
     cs = batch_cases(CS.LOW, SMALL_SIZES, seed0=200)
     enc = make_encoder(B, BT, cs, tune=tune)
@@ -89,10 +91,11 @@ def test_batch_vs_oracle(B, BT, tune):
         check_vs_oracle(c, L[k], enc.grads(k))
 
 
-def test_batch_rejects_unknown_arm_order(B, BT):
+@pytest.mark.parametrize("tune", [(0, 0, 3), (0, 0, 0, 24), (0, 0, 0, 64)])
+def test_batch_rejects_unknown_arm_order_or_tile(B, BT, tune):
     cs = batch_cases(CS.LOW, SMALL_SIZES[:2], seed0=210)
     with pytest.raises(B.CoolChicError):
-        make_encoder(B, BT, cs, tune=(0, 0, 3))
+        make_encoder(B, BT, cs, tune=tune)
 
 
 def test_batch_full_arch_vs_oracle(B, BT):
@@ -208,8 +211,8 @@ def test_autotune_restores_state_and_caches(B, BT, tmp_path, monkeypatch):
     before = enc.theta.clone()
     res = BT.autotune(enc, iters=2, reps=1)
     assert not res["cached"]
-    assert tuple(res["tune"]) in {(a, s, f) for a in BT.ARM_CANDIDATES for s in BT.SYN_CANDIDATES
-                                  for f in BT.ARM_FIRST_CANDIDATES}
+    assert tuple(res["tune"]) in {(a, s, f, t) for a in BT.ARM_CANDIDATES for s in BT.SYN_CANDIDATES
+                                  for f in BT.ARM_FIRST_CANDIDATES for t in BT.UPS_TILE_CANDIDATES}
     assert enc.tune == tuple(res["tune"])
     assert torch.equal(enc.theta, before)
     assert int(enc.step_ctr[0]) == 0
