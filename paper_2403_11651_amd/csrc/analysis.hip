@@ -2,16 +2,16 @@
 // y = f_alpha(x), the latent grids of Cool-chic in one forward pass.
 //
 // 21 ConvNeXt-style blocks (three per latent level, the first of levels
-// 1..6 with stride 2), each run as two launches over the positions of its
-// output level:
-//   ana_dw_kernel   depth-wise 7x7 convolution and the layer normalisation
-//                   over channels, FP32; writes the normalised features T in
-//                   bfloat16 (position-major, 64 or 16 channels per position)
-//   ana_mlp_kernel  the block's 1x1 convolutions on the bfloat16 matrix
-//                   cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation),
-//                   GELU between them, the identity branch, the bfloat16
-//                   block output and, for a level's last block, its latent
-//                   head.
+// 1..6 with stride 2).  A block with 64 input channels is one launch,
+// ana_block_kernel: per wave and 32 output positions, the depth-wise 7x7
+// convolution and the layer normalisation over channels in FP32, the
+// normalised features T (bfloat16) handed to the MLP through LDS, then the
+// block's 1x1 convolutions on the bfloat16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation), GELU between them, the
+// identity branch, the bfloat16 block output and, for a level's last block,
+// its latent head.  The first block (3 image channels) runs as
+// ana_dw3_kernel (depth-wise conv + norm, T with 16 channels in global
+// memory) and ana_mlp16_kernel.
 // The MLP works transposed: with the weights as the A operand and 32
 // positions as the columns, the hidden layer's accumulators (rows = hidden
 // units) feed the second product as its B operand without leaving the
@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "coolchic.h"
 #include "common.hpp"
@@ -35,9 +36,9 @@ constexpr int AN_C = 64, AN_HID = 256, AN_K = 7, AN_TAPS = AN_K * AN_K, AN_L = 7
 constexpr int AN_BLOCKS = AN_L * (1 + AN_E);
 constexpr float AN_LN_EPS = 1e-6f;
 constexpr int AN_THREADS = 256;
-constexpr int AN_MAX_GRID = 1024;
-constexpr int AN_NT = 1;  // 32-position tiles per wave step of the MLP kernel
-constexpr int AN_DW_R = 4;  // consecutive positions per lane group of the depth-wise kernel
+constexpr int AN_MAX_GRID = 1024;  // work-groups of the first block's MLP launch at most
+constexpr int AN_BW = 8, AN_BT = 64 * AN_BW;  // waves, threads per work-group of the fused block kernel
+constexpr int AN_BLOCK_GRID = 256;  // fused block kernel: one work-group per CU (its LDS holds one)
 
 // Per-block host-side description (offsets in floats into theta, in
 // uint16 into the bf16 operand area of the workspace).
@@ -103,324 +104,510 @@ __global__ __launch_bounds__(AN_THREADS) void ana_prep_kernel(AnPrepArgs a) {
 
 // ------------------------------------------------- depth-wise conv + norm
 
-// 64 input channels: eight lanes per group of AN_DW_R positions of a row,
-// eight channels each; the normalisation's sums run over the eight lanes.  The first block (3 image
-// channels): one thread per position, T padded to 16 channels.
-template <int S>
-__global__ __launch_bounds__(AN_THREADS) void ana_dw_kernel(AnArgs a) {
-  __shared__ float s_w[AN_C * AN_TAPS];
-  const int tid = threadIdx.x;
+// The first block (3 image channels): one thread per position, FP32 planar
+// image, T padded to 16 channels (the K step of the matrix cores).
+__global__ __launch_bounds__(AN_THREADS) void ana_dw3_kernel(AnArgs a) {
   const long long npx = (long long)a.n * a.ho * a.wo;
-  if (a.c_in == 3) {
-    const long long px = (long long)blockIdx.x * AN_THREADS + tid;
-    if (px >= npx) return;
-    const int img = (int)(px / ((long long)a.ho * a.wo)), r = (int)(px % ((long long)a.ho * a.wo));
-    const int i = r / a.wo, j = r % a.wo;
-    float acc[3];
+  const long long px = (long long)blockIdx.x * AN_THREADS + threadIdx.x;
+  if (px >= npx) return;
+  const int img = (int)(px / ((long long)a.ho * a.wo)), r = (int)(px % ((long long)a.ho * a.wo));
+  const int i = r / a.wo, j = r % a.wo;
+  float acc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float s = a.dw_b[c];
-      const float* xc = a.x + ((size_t)img * 3 + c) * a.hi * a.wi;
-      for (int dy = 0; dy < AN_K; ++dy) {
-        const int iy = a.stride * i + dy - 3;
-        if (iy < 0 || iy >= a.hi) continue;
-        for (int dx = 0; dx < AN_K; ++dx) {
-          const int ix = a.stride * j + dx - 3;
-          if (ix >= 0 && ix < a.wi) s = __builtin_fmaf(a.dw_w[c * AN_TAPS + dy * AN_K + dx], xc[iy * a.wi + ix], s);
-        }
-      }
-      acc[c] = s;
-    }
-    const float mean = (acc[0] + acc[1] + acc[2]) / 3.0f;
-    float var = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) var += (acc[c] - mean) * (acc[c] - mean);
-    const float rs = 1.0f / sqrtf(var / 3.0f + AN_LN_EPS);
-    uint16_t o[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) o[c] = c < 3 ? bf16_bits((acc[c] - mean) * rs * a.ln_g[c] + a.ln_b[c]) : 0;
-    uint4* dst = reinterpret_cast<uint4*>(a.t + px * 16);
-    dst[0] = make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
-    dst[1] = make_uint4(o[8] | (o[9] << 16), o[10] | (o[11] << 16), o[12] | (o[13] << 16), o[14] | (o[15] << 16));
-    return;
-  }
-  for (int k = tid; k < AN_C * AN_TAPS; k += AN_THREADS) s_w[k] = a.dw_w[k];
-  __syncthreads();
-  // eight lanes per group of AN_DW_R consecutive positions of a row; each
-  // input row's columns are loaded once and used by all the group's taps
-  constexpr int R = AN_DW_R;
-  const int gpr = (a.wo + R - 1) / R;  // groups per output row
-  const long long ngr = (long long)a.n * a.ho * gpr;
-  const long long g = (long long)blockIdx.x * AN_THREADS + tid;
-  const long long grp = g >> 3;
-  const int cg = (int)(g & 7);
-  const bool valid = grp < ngr;
-  const long long gc = valid ? grp : ngr - 1;
-  const int img = (int)(gc / ((long long)a.ho * gpr)), rr = (int)(gc % ((long long)a.ho * gpr));
-  const int i = rr / gpr, j0 = (rr % gpr) * R;
-  float acc[R][8];
-#pragma unroll
-  for (int q = 0; q < R; ++q)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) acc[q][e] = a.dw_b[cg * 8 + e];
-  const uint16_t* base = a.fin + (size_t)img * a.hi * a.wi * AN_C + cg * 8;
-  for (int dy = 0; dy < AN_K; ++dy) {
-    const int iy = S * i + dy - 3;
-    if (iy < 0 || iy >= a.hi) continue;
-    // input columns s j0 - 3 .. s (j0 + R - 1) + 3
-    constexpr int NCOL = S * (R - 1) + AN_K;
-    uint4 col[NCOL];
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      const int ix = S * j0 - 3 + c;
-      col[c] = (ix >= 0 && ix < a.wi)
-                   ? *reinterpret_cast<const uint4*>(base + ((size_t)iy * a.wi + ix) * AN_C)
-                   : make_uint4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int dx = 0; dx < AN_K; ++dx) {
-      float w[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) w[e] = s_w[(cg * 8 + e) * AN_TAPS + dy * AN_K + dx];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const uint4 u = col[S * q + dx];
-        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc[q][2 * e] = __builtin_fmaf(w[2 * e], bf16_f(w4[e] & 0xffffu), acc[q][2 * e]);
-          acc[q][2 * e + 1] = __builtin_fmaf(w[2 * e + 1], bf16_f(w4[e] >> 16), acc[q][2 * e + 1]);
-        }
+  for (int c = 0; c < 3; ++c) {
+    float s = a.dw_b[c];
+    const float* xc = a.x + ((size_t)img * 3 + c) * a.hi * a.wi;
+    for (int dy = 0; dy < AN_K; ++dy) {
+      const int iy = i + dy - 3;
+      if (iy < 0 || iy >= a.hi) continue;
+      for (int dx = 0; dx < AN_K; ++dx) {
+        const int ix = j + dx - 3;
+        if (ix >= 0 && ix < a.wi) s = __builtin_fmaf(a.dw_w[c * AN_TAPS + dy * AN_K + dx], xc[iy * a.wi + ix], s);
       }
     }
+    acc[c] = s;
   }
-  // normalisation over the 64 channels of each position (its eight lanes)
+  const float mean = (acc[0] + acc[1] + acc[2]) / 3.0f;
+  float var = 0.0f;
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    float sm = 0.0f;
+  for (int c = 0; c < 3; ++c) var += (acc[c] - mean) * (acc[c] - mean);
+  const float rs = 1.0f / sqrtf(var / 3.0f + AN_LN_EPS);
+  uint16_t o[16];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sm += acc[q][e];
-    sm += __shfl_xor(sm, 1, 64);
-    sm += __shfl_xor(sm, 2, 64);
-    sm += __shfl_xor(sm, 4, 64);
-    const float mean = sm / 64.0f;
-    float sq = 0.0f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) sq += (acc[q][e] - mean) * (acc[q][e] - mean);
-    sq += __shfl_xor(sq, 1, 64);
-    sq += __shfl_xor(sq, 2, 64);
-    sq += __shfl_xor(sq, 4, 64);
-    const float rs = 1.0f / sqrtf(sq / 64.0f + AN_LN_EPS);
-    uint32_t o[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = cg * 8 + 2 * e;
-      const uint32_t lo = bf16_bits((acc[q][2 * e] - mean) * rs * a.ln_g[c] + a.ln_b[c]);
-      const uint32_t hi = bf16_bits((acc[q][2 * e + 1] - mean) * rs * a.ln_g[c + 1] + a.ln_b[c + 1]);
-      o[e] = lo | (hi << 16);
-    }
-    const int j = j0 + q;
-    if (valid && j < a.wo) {
-      const size_t px = ((size_t)img * a.ho + i) * a.wo + j;
-      *reinterpret_cast<uint4*>(a.t + px * AN_C + cg * 8) = make_uint4(o[0], o[1], o[2], o[3]);
-    }
-  }
+  for (int c = 0; c < 16; ++c) o[c] = c < 3 ? bf16_bits((acc[c] - mean) * rs * a.ln_g[c] + a.ln_b[c]) : 0;
+  uint4* dst = reinterpret_cast<uint4*>(a.t + px * 16);
+  dst[0] = make_uint4(o[0] | (o[1] << 16), o[2] | (o[3] << 16), o[4] | (o[5] << 16), o[6] | (o[7] << 16));
+  dst[1] = make_uint4(o[8] | (o[9] << 16), o[10] | (o[11] << 16), o[12] | (o[13] << 16), o[14] | (o[15] << 16));
 }
 
 // --------------------------------------------------------- 1x1 MLP block
 
-// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26:
-// erf(z) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-z^2),
-// t = 1 / (1 + p z), z >= 0 (odd extension), absolute error <= 1.5e-7 --
-// far below the bfloat16 rounding of the GELU output; a quarter of the
-// instructions of the library erff, whose cost made the block VALU bound.
-__device__ __forceinline__ float erf_as(float z) {
-  const float a = fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, a, 1.0f));
-  float poly = __builtin_fmaf(1.061405429f, t, -1.453152027f);
-  poly = __builtin_fmaf(poly, t, 1.421413741f);
-  poly = __builtin_fmaf(poly, t, -0.284496736f);
-  poly = __builtin_fmaf(poly, t, 0.254829592f);
-  poly *= t;
-  const float e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);  // exp(-z^2)
-  const float r = __builtin_fmaf(-poly, e, 1.0f);
-  return copysignf(r, z);
+// GELU(v) = v Phi(v) = max(v, 0) - |v| Phi(-|v|), with
+// Phi(-|v|) = erfc(|v| / sqrt 2) / 2 by Abramowitz & Stegun, Handbook of
+// Mathematical Functions, 7.1.26: erfc(z) = (a1 t + a2 t^2 + a3 t^3 + a4 t^4
+// + a5 t^5) exp(-z^2), t = 1 / (1 + p z), z >= 0, absolute error <= 1.5e-7
+// -- far below the bfloat16 rounding of the GELU output.  The 1/2 and the
+// 1/sqrt 2 are folded into the constants: 13 instructions (two of them
+// transcendental) against about 60 for the library erff, whose cost made
+// the block VALU bound.
+__device__ __forceinline__ float gelu(float v) {
+  const float u = fabsf(v);
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.23164189f, u, 1.0f));  // p / sqrt 2
+  float q = __builtin_fmaf(0.5307027145f, t, -0.7265760135f);                     // a5 / 2, a4 / 2
+  q = __builtin_fmaf(q, t, 0.7107068705f);                                        // a3 / 2
+  q = __builtin_fmaf(q, t, -0.142248368f);                                        // a2 / 2
+  q = __builtin_fmaf(q, t, 0.127414796f);                                         // a1 / 2
+  q *= t;
+  const float e = __builtin_amdgcn_exp2f(v * v * -0.7213475204f);  // exp(-v^2 / 2)
+  return __builtin_fmaf(-u, q * e, fmaxf(v, 0.0f));
 }
-__device__ __forceinline__ float gelu(float v) { return 0.5f * v * (1.0f + erf_as(v * 0.70710678118654752f)); }
 // round to the nearest bfloat16 (ties to even) with the hardware conversion
 __device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
+// LDS copies of a block's 1x1 weights (rows padded against bank conflicts),
+// biases and head weights, by nthr threads.
 template <int KIN>
-__global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp_kernel(AnArgs a) {
-  constexpr int S1 = KIN + 8, S2 = AN_HID + 8;  // padded LDS row strides (bf16)
-  constexpr int NT = AN_NT, PW = 32 * NT;       // 32-position tiles per wave step, positions per step
-  __shared__ __align__(16) uint16_t s_w1[AN_HID * S1];
-  __shared__ __align__(16) uint16_t s_w2[AN_C * S2];
-  __shared__ float s_b1[AN_HID], s_b2[AN_C], s_hw[AN_C];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hi = lane >> 5, col = lane & 31;
-  for (int k = tid; k < AN_HID * KIN / 8; k += AN_THREADS) {
-    const int r = k / (KIN / 8), c8 = k % (KIN / 8);
-    *reinterpret_cast<uint4*>(&s_w1[r * S1 + c8 * 8]) = *reinterpret_cast<const uint4*>(a.w1 + (size_t)r * KIN + c8 * 8);
+struct AnMlpLds {
+  static constexpr int S1 = KIN + 8, S2 = AN_HID + 8;
+  __align__(16) uint16_t w1[AN_HID * S1];
+  __align__(16) uint16_t w2[AN_C * S2];
+  float b1[AN_HID], b2[AN_C], hw[AN_C];
+};
+
+// Every thread's elements are read into registers first and written to LDS
+// afterwards: a loop of load-store pairs waits for each load in turn.
+template <int KIN, int NTHR>
+__device__ __forceinline__ void an_stage_mlp(const AnArgs& a, AnMlpLds<KIN>& s, int tid) {
+  constexpr int S1 = AnMlpLds<KIN>::S1, S2 = AnMlpLds<KIN>::S2;
+  constexpr int N1 = AN_HID * KIN / 8, N2 = AN_C * AN_HID / 8;  // 16-byte units
+  constexpr int R1 = (N1 + NTHR - 1) / NTHR, R2 = (N2 + NTHR - 1) / NTHR;
+  static_assert(NTHR >= AN_HID, "one bias per thread");
+  uint4 v1[R1], v2[R2];  // (a thread past the end re-reads the last unit and stores nothing)
+#pragma unroll
+  for (int q = 0; q < R1; ++q) v1[q] = *reinterpret_cast<const uint4*>(a.w1 + (size_t)min(tid + q * NTHR, N1 - 1) * 8);
+#pragma unroll
+  for (int q = 0; q < R2; ++q) v2[q] = *reinterpret_cast<const uint4*>(a.w2 + (size_t)min(tid + q * NTHR, N2 - 1) * 8);
+  const float b1 = tid < AN_HID ? a.b1[tid] : 0.0f;
+  const float b2 = tid < AN_C ? a.b2[tid] + (a.kid ? a.bid[tid] : 0.0f) : 0.0f;
+  const float hw = tid < AN_C && a.head ? a.head[tid] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < R1; ++q) {
+    const int k = tid + q * NTHR;
+    if (N1 % NTHR == 0 || k < N1) *reinterpret_cast<uint4*>(&s.w1[(k / (KIN / 8)) * S1 + (k % (KIN / 8)) * 8]) = v1[q];
   }
-  for (int k = tid; k < AN_C * AN_HID / 8; k += AN_THREADS) {
-    const int r = k / (AN_HID / 8), c8 = k % (AN_HID / 8);
-    *reinterpret_cast<uint4*>(&s_w2[r * S2 + c8 * 8]) =
-        *reinterpret_cast<const uint4*>(a.w2 + (size_t)r * AN_HID + c8 * 8);
+#pragma unroll
+  for (int q = 0; q < R2; ++q) {
+    const int k = tid + q * NTHR;
+    if (N2 % NTHR == 0 || k < N2) *reinterpret_cast<uint4*>(&s.w2[(k / (AN_HID / 8)) * S2 + (k % (AN_HID / 8)) * 8]) = v2[q];
   }
-  for (int k = tid; k < AN_HID; k += AN_THREADS) s_b1[k] = a.b1[k];
-  for (int k = tid; k < AN_C; k += AN_THREADS) {
-    s_b2[k] = a.b2[k] + (a.kid ? a.bid[k] : 0.0f);
-    s_hw[k] = a.head ? a.head[k] : 0.0f;
+  if (tid < AN_HID) s.b1[tid] = b1;
+  if (tid < AN_C) {
+    s.b2[tid] = b2;
+    s.hw[tid] = hw;
   }
-  __syncthreads();
+}
+
+// Output position of a lane in a block's level: image, row, column (a
+// position beyond the last one has ok = false and the coordinates of the
+// first).  Positions are counted in 32 bits (the host bounds n h w).
+struct AnPos {
+  int img, i, j;
+  bool ok;
+};
+__device__ __forceinline__ AnPos an_pos(const AnArgs& a, int p) {
   const int hw = a.ho * a.wo;
-  const long long npx = (long long)a.n * hw;
-  const float head_b = a.head ? a.head[AN_C] : 0.0f;
-  for (long long g = (long long)blockIdx.x * 4 + wave; g * PW < npx; g += (long long)gridDim.x * 4) {
-    const long long px0 = g * PW;
-    long long pxn[NT];
-    bool ok[NT];
+  AnPos q;
+  q.ok = p < a.n * hw;
+  const int pc = q.ok ? p : 0;
+  q.img = pc / hw;
+  const int r = pc - q.img * hw;
+  q.i = r / a.wo;
+  q.j = r - q.i * a.wo;
+  return q;
+}
+
+// One wave, 32 positions: both 1x1 layers, GELU, the identity branch, the
+// bfloat16 block output and the head.  tb holds the B operands of the first
+// product (the lane's position pos, column lane % 32 of the products,
+// channels kk * 16 + 8 (lane / 32) .. + 7 of k-step kk).
+template <int KIN>
+__device__ __forceinline__ void an_mlp_tile(const AnArgs& a, const AnMlpLds<KIN>& s, const bf16x8 (&tb)[KIN / 16],
+                                            const AnPos& pos, int lane) {
+  constexpr int S1 = AnMlpLds<KIN>::S1, S2 = AnMlpLds<KIN>::S2;
+  const int hi = lane >> 5, col = lane & 31;
+  const bool ok = pos.ok;
+  f32x16 acc2[2];
 #pragma unroll
-    for (int n2 = 0; n2 < NT; ++n2) {
-      pxn[n2] = px0 + 32 * n2 + col;
-      ok[n2] = pxn[n2] < npx;
-    }
-    // B operands of the first product: the position's normalised features
-    bf16x8 tb[NT][KIN / 16];
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int n2 = 0; n2 < NT; ++n2)
+    for (int r = 0; r < 16; ++r) acc2[mt][r] = 0.0f;
+#pragma unroll 1
+  for (int c = 0; c < AN_HID / 32; ++c) {
+    // hidden units c*32 + 8 (r / 4) + 4 hi + r % 4 of the 32 positions
+    f32x16 acc1;
 #pragma unroll
-      for (int kk = 0; kk < KIN / 16; ++kk)
-        tb[n2][kk] = ok[n2] ? load8(a.t + pxn[n2] * KIN + kk * 16 + hi * 8) : zero8();
-    f32x16 acc2[2][NT];
+    for (int r = 0; r < 16; ++r) acc1[r] = s.b1[c * 32 + 8 * (r >> 2) + 4 * hi + (r & 3)];
+#pragma unroll
+    for (int kk = 0; kk < KIN / 16; ++kk) acc1 = mfma_bf16(load8(&s.w1[(c * 32 + col) * S1 + kk * 16 + hi * 8]), tb[kk], acc1);
+    // GELU, rounded: K-step t of the second product takes accumulators
+    // 8 t .. 8 t + 7, i.e. hidden units c*32 + 16 t + 8 (e / 4) + 4 hi + e % 4
+    bf16x8 hb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) hb[t][e] = (__bf16)gelu(acc1[8 * t + e]);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int n2 = 0; n2 < NT; ++n2)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc2[mt][n2][r] = 0.0f;
-#pragma unroll 1
-    for (int c = 0; c < AN_HID / 32; ++c) {
-      // hidden units c*32 + 8 (r / 4) + 4 hi + r % 4 of the 64 positions
-      f32x16 acc1[NT];
-#pragma unroll
-      for (int n2 = 0; n2 < NT; ++n2)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc1[n2][r] = s_b1[c * 32 + 8 * (r >> 2) + 4 * hi + (r & 3)];
-#pragma unroll
-      for (int kk = 0; kk < KIN / 16; ++kk) {
-        const bf16x8 aw = load8(&s_w1[(c * 32 + col) * S1 + kk * 16 + hi * 8]);
-#pragma unroll
-        for (int n2 = 0; n2 < NT; ++n2) acc1[n2] = mfma_bf16(aw, tb[n2][kk], acc1[n2]);
+      for (int t = 0; t < 2; ++t) {
+        const uint16_t* w = &s.w2[(mt * 32 + col) * S2 + c * 32 + 16 * t + 4 * hi];
+        const uint2 u0 = *reinterpret_cast<const uint2*>(w), u1 = *reinterpret_cast<const uint2*>(w + 8);
+        acc2[mt] = mfma_bf16(__builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y)), hb[t], acc2[mt]);
       }
-      // GELU, rounded: K-step t of the second product takes accumulators
-      // 8 t .. 8 t + 7, i.e. hidden units c*32 + 16 t + 8 (e / 4) + 4 hi + e % 4
-      bf16x8 hb[NT][2];
+  }
+  const int img = pos.img, i = pos.i, j = pos.j, rr = i * a.wo + j;
+  const size_t pc = ((size_t)img * a.ho + i) * a.wo + j;
+  // identity branch through a 1x1 convolution: the image (first block) or
+  // the 2x2-average-pooled input (downsampling blocks), rounded
+  if (a.kid) {
+#pragma unroll 1
+    for (int kk = 0; kk < a.kid / 16; ++kk) {
+      bf16x8 sb;
+      if (a.c_in == 3) {
 #pragma unroll
-      for (int n2 = 0; n2 < NT; ++n2)
+        for (int e = 0; e < 8; ++e) {
+          const int ch = kk * 16 + hi * 8 + e;
+          const float v = ok && ch < 3 ? a.x[(((size_t)img * 3 + ch) * a.hi + i) * a.wi + j] : 0.0f;
+          sb[e] = (__bf16)v;
+        }
+      } else {
+        float v[8];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int e = 0; e < 8; ++e) v[e] = 0.0f;
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            hb[n2][t][e] = (__bf16)gelu(acc1[n2][8 * t + e]);
+        for (int q = 0; q < 4; ++q) {
+          const size_t pin = ((size_t)img * a.hi + 2 * i + (q >> 1)) * a.wi + 2 * j + (q & 1);
+          const uint4 u = ok ? *reinterpret_cast<const uint4*>(a.fin + pin * AN_C + kk * 16 + hi * 8) : make_uint4(0, 0, 0, 0);
+          const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            v[2 * e] += bf16_f(w4[e] & 0xffffu);
+            v[2 * e + 1] += bf16_f(w4[e] >> 16);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sb[e] = (__bf16)(v[e] * 0.25f);
+      }
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const uint16_t* w = &s_w2[(mt * 32 + col) * S2 + c * 32 + 16 * t + 4 * hi];
-          const uint2 u0 = *reinterpret_cast<const uint2*>(w), u1 = *reinterpret_cast<const uint2*>(w + 8);
-          const bf16x8 aw = __builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y));
-#pragma unroll
-          for (int n2 = 0; n2 < NT; ++n2) acc2[mt][n2] = mfma_bf16(aw, hb[n2][t], acc2[mt][n2]);
-        }
+        acc2[mt] = mfma_bf16(load8(a.wid + (size_t)(mt * 32 + col) * a.kid + kk * 16 + hi * 8), sb, acc2[mt]);
     }
-    // identity branch through a 1x1 convolution: the image (first block) or
-    // the 2x2-average-pooled input (downsampling blocks), rounded
-    if (a.kid) {
+  }
+  // output: + biases (+ the input itself), rounded to bfloat16; the head
+  float hsum = 0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const int ch0 = mt * 32 + 8 * qd + 4 * hi;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = acc2[mt][4 * qd + e] + s.b2[ch0 + e];
+      if (!a.kid && ok) {
+        const uint2 u = *reinterpret_cast<const uint2*>(a.fin + pc * AN_C + ch0);
+        v[0] += bf16_f(u.x & 0xffffu);
+        v[1] += bf16_f(u.x >> 16);
+        v[2] += bf16_f(u.y & 0xffffu);
+        v[3] += bf16_f(u.y >> 16);
+      }
+      uint32_t h[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[e] = bf16_rne(v[e]);
+        hsum = __builtin_fmaf(s.hw[ch0 + e], bf16_f(h[e]), hsum);
+      }
+      if (ok) *reinterpret_cast<uint2*>(a.fout + pc * AN_C + ch0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+  if (a.head) {
+    hsum += __shfl_xor(hsum, 32, 64);
+    if (hi == 0 && ok) a.y[(size_t)img * a.n_lat + a.loff + rr] = hsum + a.head[AN_C];
+  }
+}
+
+// The first block's MLP: T (16 channels, the image's 3 and zeros) from the
+// depth-wise kernel.
+__global__ __launch_bounds__(AN_THREADS, 2) void ana_mlp16_kernel(AnArgs a) {
+  __shared__ AnMlpLds<16> s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hi = lane >> 5, col = lane & 31;
+  an_stage_mlp<16, AN_THREADS>(a, s, tid);
+  __syncthreads();
+  const int npx = a.n * a.ho * a.wo;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  for (int g = blockIdx.x * 4 + wave_u; g * 32 < npx; g += gridDim.x * 4) {
+    const int px = g * 32 + col;
+    const AnPos pos = an_pos(a, px);
+    bf16x8 tb[1];
+    tb[0] = pos.ok ? load8(a.t + (size_t)px * 16 + hi * 8) : zero8();
+    an_mlp_tile<16>(a, s, tb, pos, lane);
+  }
+}
+
+// Blocks with 64 input channels, one launch each: per wave and 32 output
+// positions, the depth-wise 7x7 convolution (stride S) and the layer norm
+// in FP32, the normalised features through the wave's LDS slot (bfloat16)
+// into the MLP's operand layout, then the MLP (an_mlp_tile).  Depth-wise
+// lanes: eight lanes per group of four positions, eight channels each; with
+// ROWSEG (output rows a multiple of 32 wide) a tile is one row segment and a
+// group's positions are consecutive, so each input row is loaded once per
+// group as S * 3 + 7 columns and converted to FP32 once; otherwise (the small
+// coarse levels) each position loads its own 7 x 7 window.
+template <int S, bool ROWSEG>
+__global__ __launch_bounds__(AN_BT) void ana_block_kernel(AnArgs a) {
+  constexpr int ST = AN_C + 8;  // LDS row stride of the normalised features (bf16)
+  __shared__ AnMlpLds<AN_C> s;
+  __shared__ __align__(16) float s_dw[AN_TAPS * AN_C];  // [tap][channel]
+  __shared__ __align__(16) uint16_t s_t[AN_BW * 32 * ST];
+  __shared__ __align__(16) float s_dwb[AN_C], s_lg[AN_C], s_lb[AN_C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hi = lane >> 5, col = lane & 31;
+  {
+    // depth-wise weights transposed to [tap][channel] (loads first, as in an_stage_mlp)
+    constexpr int RD = (AN_TAPS * AN_C + AN_BT - 1) / AN_BT;
+    float v[RD];
+#pragma unroll
+    for (int q = 0; q < RD; ++q) {
+      const int k = min(tid + q * AN_BT, AN_TAPS * AN_C - 1);
+      v[q] = a.dw_w[(k % AN_C) * AN_TAPS + k / AN_C];
+    }
+    float vb = 0.0f, vg = 0.0f, vl = 0.0f;
+    if (tid < AN_C) {
+      vb = a.dw_b[tid];
+      vg = a.ln_g[tid];
+      vl = a.ln_b[tid];
+    }
+    an_stage_mlp<AN_C, AN_BT>(a, s, tid);
+#pragma unroll
+    for (int q = 0; q < RD; ++q) {
+      const int k = tid + q * AN_BT;
+      if (k < AN_TAPS * AN_C) s_dw[k] = v[q];
+    }
+    if (tid < AN_C) {
+      s_dwb[tid] = vb;
+      s_lg[tid] = vg;
+      s_lb[tid] = vl;
+    }
+  }
+  __syncthreads();
+  const int cg = lane & 7, pg = lane >> 3;
+  const int hw = a.ho * a.wo, npx = a.n * hw;
+  uint16_t* st = s_t + wave * 32 * ST;
+  const uint16_t* fin = a.fin + cg * 8;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  // Tiles are walked in row-major order.  Work-groups are dispatched to the
+  // eight XCDs in turn (work-group b on XCD b mod 8), each XCD with its own
+  // L2: with a grid that is a multiple of 8, XCD x takes the x-th eighth of
+  // the tiles, so that the rows above and below a tile, which the 7x7 window
+  // reads again, are fetched by work-groups sharing its L2.
+  const int tiles = (npx + 31) / 32, G = gridDim.x;
+  int g0, gstep, gend;
+  if (G % 8 == 0) {
+    const int tx = (tiles + 7) / 8, x = blockIdx.x % 8;
+    g0 = x * tx + (blockIdx.x / 8) * AN_BW + wave_u;
+    gstep = (G / 8) * AN_BW;
+    gend = min(tiles, (x + 1) * tx);
+  } else {
+    g0 = blockIdx.x * AN_BW + wave_u;
+    gstep = G * AN_BW;
+    gend = tiles;
+  }
+  for (int g = g0; g < gend; g += gstep) {
+    const int px0 = g * 32;
+    // the lane's position for the products; with ROWSEG a tile is one row
+    // segment, its image and row the same for the whole wave
+    AnPos pos;
+    int jw = 0;
+    if constexpr (ROWSEG) {
+      pos.img = px0 / hw;
+      const int r = px0 - pos.img * hw;
+      pos.i = r / a.wo;
+      jw = r - pos.i * a.wo;
+      pos.j = jw + col;
+      pos.ok = true;  // npx is a multiple of 32
+    } else {
+      pos = an_pos(a, px0 + col);
+    }
+    float acc[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[q][e] = s_dwb[cg * 8 + e];
+    if constexpr (ROWSEG) {
+      const int img = pos.img, i = pos.i, j0 = jw + 4 * pg;
+      const uint16_t* base = fin + (size_t)img * a.hi * a.wi * AN_C;
+      constexpr int NCOL = S * 3 + AN_K;
+      // input row S i + dy - 3, columns S j0 - 3 .. S j0 - 3 + NCOL - 1
+      // rows outside the image add nothing and are skipped (the row is the
+      // same for the whole wave); columns of a group away from the image's
+      // left and right borders need no checks
+      const bool inside = S * j0 - 3 >= 0 && S * j0 - 3 + NCOL <= a.wi;
+      auto rows = [&](auto checked) {
 #pragma unroll 1
-      for (int kk = 0; kk < a.kid / 16; ++kk) {
-        bf16x8 sb[NT];
+        for (int dy = 0; dy < AN_K; ++dy) {
+          const int iy = S * i + dy - 3;
+          if (iy < 0 || iy >= a.hi) continue;
+          const uint16_t* rowp = base + (size_t)iy * a.wi * AN_C;
+          uint4 u[NCOL];
 #pragma unroll
-        for (int n2 = 0; n2 < NT; ++n2) {
-          const long long pc = ok[n2] ? pxn[n2] : 0;
-          const int img = (int)(pc / hw), r = (int)(pc % hw), i = r / a.wo, j = r % a.wo;
-          if (a.c_in == 3) {
+          for (int c = 0; c < NCOL; ++c) {
+            const int ix = S * j0 - 3 + c;
+            if constexpr (decltype(checked)::value)
+              u[c] = (ix >= 0 && ix < a.wi) ? *reinterpret_cast<const uint4*>(rowp + (size_t)ix * AN_C) : make_uint4(0, 0, 0, 0);
+            else
+              u[c] = *reinterpret_cast<const uint4*>(rowp + (size_t)(S * j0 - 3) * AN_C + c * AN_C);
+          }
+          // each column converted to FP32 once (stride 1) or where it is used
+          // (stride 2: 13 columns, whose FP32 copies would not fit the registers)
+          if constexpr (S == 1) {
+            float f[NCOL][8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int ch = kk * 16 + hi * 8 + e;
-              const float v = ok[n2] && ch < 3 ? a.x[(((size_t)img * 3 + ch) * a.hi + i) * a.wi + j] : 0.0f;
-              sb[n2][e] = (__bf16)v;
-            }
-          } else {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = 0.0f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const size_t pin = ((size_t)img * a.hi + 2 * i + (q >> 1)) * a.wi + 2 * j + (q & 1);
-              const uint4 u = ok[n2] ? *reinterpret_cast<const uint4*>(a.fin + pin * AN_C + kk * 16 + hi * 8)
-                                     : make_uint4(0, 0, 0, 0);
-              const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+            for (int c = 0; c < NCOL; ++c) {
+              const uint32_t w4[4] = {u[c].x, u[c].y, u[c].z, u[c].w};
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
-                v[2 * e] += bf16_f(w4[e] & 0xffffu);
-                v[2 * e + 1] += bf16_f(w4[e] >> 16);
+                f[c][2 * e] = bf16_f(w4[e] & 0xffffu);
+                f[c][2 * e + 1] = bf16_f(w4[e] >> 16);
               }
             }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) sb[n2][e] = (__bf16)(v[e] * 0.25f);
+            for (int dx = 0; dx < AN_K; ++dx) {
+              const float4 w0 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8]);
+              const float4 w1 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8 + 4]);
+              const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[q][e] = __builtin_fmaf(w[e], f[q + dx][e], acc[q][e]);
+            }
+          } else {
+#pragma unroll
+            for (int dx = 0; dx < AN_K; ++dx) {
+              const float4 w0 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8]);
+              const float4 w1 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8 + 4]);
+              const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const uint4 x = u[S * q + dx];
+                const uint32_t w4[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  acc[q][2 * e] = __builtin_fmaf(w[2 * e], bf16_f(w4[e] & 0xffffu), acc[q][2 * e]);
+                  acc[q][2 * e + 1] = __builtin_fmaf(w[2 * e + 1], bf16_f(w4[e] >> 16), acc[q][2 * e + 1]);
+                }
+              }
+            }
           }
         }
+      };
+      if (inside)
+        rows(std::false_type{});
+      else
+        rows(std::true_type{});
+    } else {
+      // per input row, the seven columns of two positions in flight
+      int img[4], pi[4], pj[4];
+      bool pok[4];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          const bf16x8 aw = load8(a.wid + (size_t)(mt * 32 + col) * a.kid + kk * 16 + hi * 8);
+      for (int q = 0; q < 4; ++q) {
+        const AnPos pq = an_pos(a, px0 + 4 * pg + q);  // features beyond the last position are never used
+        pok[q] = pq.ok;
+        img[q] = pq.img;
+        pi[q] = pq.i;
+        pj[q] = pq.j;
+      }
 #pragma unroll
-          for (int n2 = 0; n2 < NT; ++n2) acc2[mt][n2] = mfma_bf16(aw, sb[n2], acc2[mt][n2]);
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
+        for (int dy = 0; dy < AN_K; ++dy) {
+          uint4 u[2][AN_K];
+#pragma unroll
+          for (int q2 = 0; q2 < 2; ++q2) {
+            const int q = 2 * h + q2;
+            const int iy = S * pi[q] + dy - 3;
+            const bool row_ok = pok[q] && iy >= 0 && iy < a.hi;
+            const uint16_t* base = fin + ((size_t)img[q] * a.hi + (row_ok ? iy : 0)) * a.wi * AN_C;
+#pragma unroll
+            for (int dx = 0; dx < AN_K; ++dx) {
+              const int ix = S * pj[q] + dx - 3;
+              u[q2][dx] = (row_ok && ix >= 0 && ix < a.wi) ? *reinterpret_cast<const uint4*>(base + (size_t)ix * AN_C)
+                                                           : make_uint4(0, 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int dx = 0; dx < AN_K; ++dx) {
+            const float4 w0 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8]);
+            const float4 w1 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8 + 4]);
+            const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+              const uint32_t w4[4] = {u[q2][dx].x, u[q2][dx].y, u[q2][dx].z, u[q2][dx].w};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                acc[2 * h + q2][2 * e] = __builtin_fmaf(w[2 * e], bf16_f(w4[e] & 0xffffu), acc[2 * h + q2][2 * e]);
+                acc[2 * h + q2][2 * e + 1] = __builtin_fmaf(w[2 * e + 1], bf16_f(w4[e] >> 16), acc[2 * h + q2][2 * e + 1]);
+              }
+            }
+          }
         }
       }
     }
-    // output: + biases (+ the input itself), rounded to bfloat16; the head
+    // normalisation over the 64 channels of each position (its eight lanes),
+    // rounded into the wave's LDS slot
 #pragma unroll
-    for (int n2 = 0; n2 < NT; ++n2) {
-      const long long pc = ok[n2] ? pxn[n2] : 0;
-      float hsum = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+      float sm = 0.0f;
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+      for (int e = 0; e < 8; ++e) sm += acc[q][e];
+      sm += __shfl_xor(sm, 1, 64);
+      sm += __shfl_xor(sm, 2, 64);
+      sm += __shfl_xor(sm, 4, 64);
+      const float mean = sm / 64.0f;
+      float sq = 0.0f;
 #pragma unroll
-        for (int qd = 0; qd < 4; ++qd) {
-          const int ch0 = mt * 32 + 8 * qd + 4 * hi;
-          float v[4];
+      for (int e = 0; e < 8; ++e) sq += (acc[q][e] - mean) * (acc[q][e] - mean);
+      sq += __shfl_xor(sq, 1, 64);
+      sq += __shfl_xor(sq, 2, 64);
+      sq += __shfl_xor(sq, 4, 64);
+      const float rs = 1.0f / sqrtf(sq / 64.0f + AN_LN_EPS);
+      uint32_t o[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = acc2[mt][n2][4 * qd + e] + s_b2[ch0 + e];
-          if (!a.kid && ok[n2]) {
-            const uint2 u = *reinterpret_cast<const uint2*>(a.fin + pc * AN_C + ch0);
-            v[0] += bf16_f(u.x & 0xffffu);
-            v[1] += bf16_f(u.x >> 16);
-            v[2] += bf16_f(u.y & 0xffffu);
-            v[3] += bf16_f(u.y >> 16);
-          }
-          uint32_t h[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            h[e] = bf16_rne(v[e]);
-            hsum = __builtin_fmaf(s_hw[ch0 + e], bf16_f(h[e]), hsum);
-          }
-          if (ok[n2]) *reinterpret_cast<uint2*>(a.fout + pc * AN_C + ch0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-        }
-      if (a.head) {
-        hsum += __shfl_xor(hsum, 32, 64);
-        if (hi == 0 && ok[n2]) {
-          const int img = (int)(pc / hw), r = (int)(pc % hw);
-          a.y[(size_t)img * a.n_lat + a.loff + r] = hsum + head_b;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int c = cg * 8 + 2 * e;
+        const uint32_t lo = bf16_bits((acc[q][2 * e] - mean) * rs * s_lg[c] + s_lb[c]);
+        const uint32_t hb = bf16_bits((acc[q][2 * e + 1] - mean) * rs * s_lg[c + 1] + s_lb[c + 1]);
+        o[e] = lo | (hb << 16);
       }
+      *reinterpret_cast<uint4*>(&st[(4 * pg + q) * ST + cg * 8]) = make_uint4(o[0], o[1], o[2], o[3]);
     }
+    // the slot is the wave's own: order its writes before the reads of
+    // other lanes of the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    bf16x8 tb[AN_C / 16];
+#pragma unroll
+    for (int kk = 0; kk < AN_C / 16; ++kk) tb[kk] = pos.ok ? load8(&st[col * ST + kk * 16 + hi * 8]) : zero8();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    an_mlp_tile<AN_C>(a, s, tb, pos, lane);
   }
 }
 
 // ------------------------------------------------------------------ host
 
-bool an_sizes_ok(int H, int W, int n) { return n >= 1 && H >= 64 && W >= 64 && H % 64 == 0 && W % 64 == 0; }
+// positions are counted in 32 bits on the device: n H W < 2^31
+bool an_sizes_ok(int H, int W, int n) {
+  return n >= 1 && H >= 64 && W >= 64 && H % 64 == 0 && W % 64 == 0 && (long long)n * H * W <= 0x7fffffffLL;
+}
 
 // The blocks' parameter offsets; returns the packed parameter count.
 long long an_layout(AnBlock* bl) {
@@ -468,8 +655,8 @@ AnWs an_ws(int H, int W, int n, const AnBlock* bl) {
   w.q = 0;
   w.f0 = up(an_q_elems(bl) * sizeof(uint16_t));
   w.f1 = w.f0 + up(feat);
-  w.t = w.f1 + up(feat);
-  w.total = w.t + up(feat);
+  w.t = w.f1 + up(feat);  // the first block's T: 16 channels per position
+  w.total = w.t + up((size_t)n * H * W * 16 * sizeof(uint16_t));
   return w;
 }
 
@@ -546,14 +733,21 @@ int coolchic_analysis_forward(int32_t H, int32_t W, int32_t n, const float* x, c
     a.y = y; a.n_lat = n_lat; a.loff = loff[B.level];
     const long long npx = (long long)n * a.ho * a.wo;
     void* argv[] = {&a};
-    const long long dw_threads = B.c_in == 3 ? npx : (long long)n * a.ho * ((a.wo + AN_DW_R - 1) / AN_DW_R) * 8;
-    if (hipLaunchKernel(B.stride == 2 ? (const void*)ana_dw_kernel<2> : (const void*)ana_dw_kernel<1>, dim3((unsigned)((dw_threads + AN_THREADS - 1) / AN_THREADS)),
-                        dim3(AN_THREADS), argv, 0, st) != hipSuccess)
-      return CC_EHIP;
-    const long long groups = (npx + 32 * AN_NT - 1) / (32 * AN_NT);
-    const unsigned grid = (unsigned)std::min<long long>((groups + 3) / 4, AN_MAX_GRID);
-    const void* mlp = B.kin == 16 ? (const void*)ana_mlp_kernel<16> : (const void*)ana_mlp_kernel<AN_C>;
-    if (hipLaunchKernel(mlp, dim3(grid), dim3(AN_THREADS), argv, 0, st) != hipSuccess) return CC_EHIP;
+    const long long tiles = (npx + 31) / 32;  // 32 positions per wave step
+    if (B.c_in == 3) {
+      if (hipLaunchKernel((const void*)ana_dw3_kernel, dim3((unsigned)((npx + AN_THREADS - 1) / AN_THREADS)),
+                          dim3(AN_THREADS), argv, 0, st) != hipSuccess)
+        return CC_EHIP;
+      const unsigned grid = (unsigned)std::min<long long>((tiles + 3) / 4, AN_MAX_GRID);
+      if (hipLaunchKernel((const void*)ana_mlp16_kernel, dim3(grid), dim3(AN_THREADS), argv, 0, st) != hipSuccess)
+        return CC_EHIP;
+    } else {
+      const bool rowseg = a.wo % 32 == 0;
+      const void* k = B.stride == 2 ? (rowseg ? (const void*)ana_block_kernel<2, true> : (const void*)ana_block_kernel<2, false>)
+                                    : (rowseg ? (const void*)ana_block_kernel<1, true> : (const void*)ana_block_kernel<1, false>);
+      const unsigned grid = (unsigned)std::min<long long>((tiles + AN_BW - 1) / AN_BW, AN_BLOCK_GRID);
+      if (hipLaunchKernel(k, dim3(grid), dim3(AN_BT), argv, 0, st) != hipSuccess) return CC_EHIP;
+    }
     hin = a.ho;
     win = a.wo;
   }
