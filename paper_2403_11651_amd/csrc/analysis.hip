@@ -108,7 +108,11 @@ __global__ __launch_bounds__(AN_THREADS) void ana_prep_kernel(AnPrepArgs a) {
 // image, T padded to 16 channels (the K step of the matrix cores).
 __global__ __launch_bounds__(AN_THREADS) void ana_dw3_kernel(AnArgs a) {
   const long long npx = (long long)a.n * a.ho * a.wo;
-  const long long px = (long long)blockIdx.x * AN_THREADS + threadIdx.x;
+  // work-group b runs on XCD b mod 8: with a grid that is a multiple of 8,
+  // XCD x takes the x-th eighth of the positions, so that the rows the 7x7
+  // window reads again are fetched through one L2
+  const unsigned G = gridDim.x, b = G % 8 == 0 ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const long long px = (long long)b * AN_THREADS + threadIdx.x;
   if (px >= npx) return;
   const int img = (int)(px / ((long long)a.ho * a.wo)), r = (int)(px % ((long long)a.ho * a.wo));
   const int i = r / a.wo, j = r % a.wo;
