@@ -383,15 +383,15 @@ int coolchic_warm_backward_grad(const cc_warm_problem* p, const float* x, const 
 /* Packed parameter count of the analysis transform. */
 int64_t coolchic_analysis_param_count(void);
 
-/* Device workspace bytes for n images of H x W (multiples of 64); 0 if the
-   sizes are invalid. */
+/* Device workspace bytes for n images of H x W (multiples of 64, n H W below
+   2^31); 0 if the sizes are invalid. */
 size_t coolchic_analysis_workspace_bytes(int32_t H, int32_t W, int32_t n);
 
 /* x (device) [n][3][H][W] in [0, 1]; theta (device) the packed parameters;
    y (device) [n][N_lat]: each image's latents before quantisation, packed
    like coolchic_forward's y (level 0 first, raster order), N_lat over 7
    levels.  Errors: CC_EINVAL (null pointer, n < 1, H or W not a positive
-   multiple of 64), CC_EWORKSPACE, CC_EHIP.  Enqueues on `stream`; allocates
+   multiple of 64, n H W >= 2^31), CC_EWORKSPACE, CC_EHIP.  Enqueues on `stream`; allocates
    nothing. */
 int coolchic_analysis_forward(int32_t H, int32_t W, int32_t n, const float* x, const float* theta, float* y,
                               void* ws, size_t ws_bytes, void* stream);

@@ -231,3 +231,21 @@ def test_batch_refuses_four_tap_upsamplers(B):
     assert B.batch_workspace_bytes([p]) == 0
     q = B.Problem(64, 64, B.Arch(7, 24, 2, 8, 40, 2, 1))
     assert B.batch_workspace_bytes([q]) > 0
+
+
+def test_analysis_sizes_and_argument_checks(B):
+    """The analysis transform's host checks (no device work): parameter count
+    of the oracle's layout, workspace sizes, and the sizes it refuses."""
+    import oracle.analysis as A
+    assert B._lib.coolchic_analysis_param_count() == A.param_count()
+    one = B._lib.coolchic_analysis_workspace_bytes(512, 768, 1)
+    assert one > 2 * 512 * 768 * 64 * 2  # two bfloat16 feature buffers at level-0 size
+    assert B._lib.coolchic_analysis_workspace_bytes(512, 768, 8) > 7 * one
+    for H, W, n in [(64, 96, 1), (96, 64, 1), (0, 64, 1), (64, 64, 0), (64, 64, -1), (32768, 32768, 2)]:
+        assert B._lib.coolchic_analysis_workspace_bytes(H, W, n) == 0, (H, W, n)
+    assert B._lib.coolchic_analysis_workspace_bytes(32768, 32704, 2) > 0  # n H W just below 2^31
+    d = 0x1000
+    assert B._lib.coolchic_analysis_forward(64, 64, 1, None, d, d, d, 1 << 30, None) == B.CC_EINVAL
+    assert B._lib.coolchic_analysis_forward(64, 64, 1, d, d, d, None, 1 << 30, None) == B.CC_EINVAL
+    assert B._lib.coolchic_analysis_forward(32768, 32768, 2, d, d, d, d, 1 << 62, None) == B.CC_EINVAL
+    assert B._lib.coolchic_analysis_forward(64, 64, 1, d, d, d, d, 16, None) == B.CC_EWORKSPACE
