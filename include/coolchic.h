@@ -195,6 +195,19 @@ int coolchic_decode_synth(const cc_problem* p, const float* yq, const float* ups
 int coolchic_adam_step(float* theta, const float* grad, float* m, float* v, int64_t n,
                        int32_t* step, float lr, float beta1, float beta2, float eps, void* stream);
 
+/* Streams.  coolchic_forward, coolchic_backward, coolchic_train_step and
+   coolchic_batch_backward fork the ARM kernel onto a side stream and join it
+   back with events.  The library keeps one side stream and event set per
+   (device, caller stream), created on the first call on that stream with the
+   device current, so calls on different streams run concurrently; calls on
+   one stream from several threads are serialised while they enqueue.  A
+   stream being captured into a graph that has no set of its own uses one the
+   device already has.  coolchic_stream_prepare creates the set for `stream`
+   on the current device ahead of time (for instance before the stream is
+   captured); calling it is optional.  Returns CC_OK, CC_EHIP, or
+   CC_EUNSUPPORTED after 256 (device, stream) pairs. */
+int coolchic_stream_prepare(void* stream);
+
 /* Measurement hook (for profilers and benchmarks, not part of the method):
    while set, every coolchic_forward / coolchic_backward call records the HIP
    event ev_begin on its stream right before the launch of the named stage and

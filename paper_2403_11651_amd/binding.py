@@ -7,6 +7,7 @@ loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from dataclasses import dataclass
@@ -31,7 +32,7 @@ EXPORTS = ("coolchic_param_count", "coolchic_latent_count", "coolchic_workspace_
            "coolchic_train_step_noalloc", "coolchic_entropy_workspace_bytes", "coolchic_entropy_bound",
            "coolchic_entropy_tables", "coolchic_entropy_encode", "coolchic_entropy_decode",
            "coolchic_param_quantize", "coolchic_analysis_param_count", "coolchic_analysis_workspace_bytes",
-           "coolchic_analysis_forward")
+           "coolchic_analysis_forward", "coolchic_stream_prepare")
 CC_STAGE_NONE, CC_STAGE_ARM, CC_STAGE_SYNTHESIS = 0, 1, 2
 
 
@@ -84,6 +85,7 @@ def _load():
         "coolchic_train_step": (I, [pp, P, P, F, P, P, P, P, P, P, F, F, F, F, P, SZ, P]),
         "coolchic_train_step_noalloc": (I, [pp, P, P, F, P, P, P, P, P, P, F, F, F, F, P]),
         "coolchic_set_stage_events": (I, [I, P, P]),
+        "coolchic_stream_prepare": (I, [P]),
         "coolchic_timing_event_create": (I, [ctypes.POINTER(P)]),
         "coolchic_timing_event_elapsed": (I, [P, P, ctypes.POINTER(F)]),
         "coolchic_timing_event_destroy": (I, [P]),
@@ -199,6 +201,19 @@ def _stream(stream):
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _on(stream):
+    """Context in which a temporary workspace is allocated for a call on
+    `stream`: torch's caching allocator ties a block to the stream that was
+    current when it was allocated, and may hand it out again on that stream
+    as soon as it is freed; allocating it on the call's own stream keeps a
+    later allocation from overwriting it while the call's kernels run."""
+    if stream is None:
+        return contextlib.nullcontext()
+    if not isinstance(stream, torch.cuda.Stream):
+        stream = torch.cuda.ExternalStream(_stream(stream))
+    return torch.cuda.stream(stream)
+
+
 def _check(rc, where):
     if rc != CC_OK:
         raise CoolChicError(rc, where)
@@ -216,7 +231,8 @@ def coolchic_forward(p: Problem, img, y, u, arm_w, ups_w, syn_w, loss4, rate_map
     na, nu, ns = param_count(p.arch)
     hw3 = 3 * p.H * p.W
     if ws is None:
-        ws = workspace(p, CC_WS_FORWARD, device=y.device)
+        with _on(stream):
+            ws = workspace(p, CC_WS_FORWARD, device=y.device)
     rc = _lib.coolchic_forward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"),
                                _ptr(u, _n_noise(p, n_lat), "u"),
                                _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
@@ -232,7 +248,8 @@ def coolchic_backward(p: Problem, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, 
     na, nu, ns = param_count(p.arch)
     hw3 = 3 * p.H * p.W
     if ws is None:
-        ws = workspace(p, CC_WS_BACKWARD, device=y.device)
+        with _on(stream):
+            ws = workspace(p, CC_WS_BACKWARD, device=y.device)
     rc = _lib.coolchic_backward(ctypes.byref(p.c()), _ptr(img, hw3, "img"), _ptr(y, n_lat, "y"),
                                 _ptr(u, _n_noise(p, n_lat), "u"),
                                 _ptr(arm_w, na, "arm_w"), _ptr(ups_w, nu, "ups_w"), _ptr(syn_w, ns, "syn_w"),
@@ -246,7 +263,8 @@ def coolchic_decode_synth(p: Problem, yq, ups_w, syn_w, xhat, ws=None, stream=No
     n_lat = latent_count(p)
     _, nu, ns = param_count(p.arch)
     if ws is None:
-        ws = workspace(p, CC_WS_DECODE, device=yq.device)
+        with _on(stream):
+            ws = workspace(p, CC_WS_DECODE, device=yq.device)
     rc = _lib.coolchic_decode_synth(ctypes.byref(p.c()), _ptr(yq, n_lat, "yq"), _ptr(ups_w, nu, "ups_w"),
                                     _ptr(syn_w, ns, "syn_w"), _ptr(xhat, 3 * p.H * p.W, "xhat"),
                                     _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
@@ -272,7 +290,8 @@ def coolchic_train_step(p: Problem, img, u, dloss, loss4, theta, grad, m, v, ste
     if step.dtype != torch.int32 or step.numel() != 2:
         raise TypeError("step must be a device int32 tensor of 2 elements: steps taken, completion counter (0)")
     if ws is None:
-        ws = workspace(p, CC_WS_BACKWARD, device=theta.device)
+        with _on(stream):
+            ws = workspace(p, CC_WS_BACKWARD, device=theta.device)
     rc = _lib.coolchic_train_step(ctypes.byref(p.c()), _ptr(img, 3 * p.H * p.W, "img"), _ptr(u, _n_noise(p, n_lat), "u"),
                                   float(dloss), _ptr(loss4, 4, "loss4"), _ptr(theta, n, "theta"),
                                   _ptr(grad, n, "grad"), _ptr(m, n, "m"), _ptr(v, n, "v"), _ptr(step, 2, "step"),
@@ -335,7 +354,8 @@ def coolchic_entropy_encode(p: Problem, yq, arm_w, out, out_nbytes, ws=None, str
     n_lat = latent_count(p)
     na, _, _ = param_count(p.arch)
     if ws is None:
-        ws = entropy_workspace(p, device=yq.device)
+        with _on(stream):
+            ws = entropy_workspace(p, device=yq.device)
     rc = _lib.coolchic_entropy_encode(ctypes.byref(p.c()), _ptr(yq, n_lat, "yq"), _ptr(arm_w, na, "arm_w"),
                                       _ptr(out, None, "out"), out.numel(), _ptr(out_nbytes, 1, "out_nbytes"),
                                       _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
@@ -348,7 +368,8 @@ def coolchic_entropy_decode(p: Problem, data, nbytes: int, arm_w, yq_out, status
     n_lat = latent_count(p)
     na, _, _ = param_count(p.arch)
     if ws is None:
-        ws = entropy_workspace(p, device=yq_out.device)
+        with _on(stream):
+            ws = entropy_workspace(p, device=yq_out.device)
     if nbytes > data.numel():
         raise ValueError("nbytes exceeds the data tensor")
     rc = _lib.coolchic_entropy_decode(ctypes.byref(p.c()), _ptr(data, None, "data"), int(nbytes),
@@ -366,6 +387,12 @@ def coolchic_uniform_noise(u, seed: int, step=None, stream_id: int = 0, stream=N
                                      None if step is None else step.data_ptr(), int(stream_id) & 0xffffffff,
                                      _stream(stream))
     _check(rc, "coolchic_uniform_noise")
+
+
+def coolchic_stream_prepare(stream=None):
+    """Creates the library's side stream and events for `stream` (default:
+    the current torch stream) on the current device ahead of time."""
+    _check(_lib.coolchic_stream_prepare(_stream(stream)), "coolchic_stream_prepare")
 
 
 def coolchic_set_stage_events(stage: int, ev_begin=None, ev_end=None):
@@ -486,7 +513,8 @@ def coolchic_analysis_forward(H: int, W: int, n: int, x, theta, y, ws=None, stre
     """Non-overfitted analysis transform: x [n][3][H][W] -> y [n][N_lat]."""
     n_lat = sum((H >> l) * (W >> l) for l in range(7))
     if ws is None:
-        ws = analysis_workspace(H, W, n, device=x.device)
+        with _on(stream):
+            ws = analysis_workspace(H, W, n, device=x.device)
     rc = _lib.coolchic_analysis_forward(int(H), int(W), int(n), _ptr(x, n * 3 * H * W, "x"),
                                         _ptr(theta, analysis_param_count(), "theta"), _ptr(y, n * n_lat, "y"),
                                         _ptr(ws, None, "ws"), ws.numel(), _stream(stream))
@@ -504,7 +532,8 @@ def coolchic_warm_forward(wp: WarmProblem, x, net, y_out, theta_out, ws=None, st
     n_lat = latent_count(Problem(wp.H, wp.W, wp.arch))
     n_theta = sum(param_count(wp.arch))
     if ws is None:
-        ws = warm_workspace(wp, CC_WS_FORWARD, device=x.device)
+        with _on(stream):
+            ws = warm_workspace(wp, CC_WS_FORWARD, device=x.device)
     rc = _lib.coolchic_warm_forward(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
                                     _ptr(net, warm_param_count(wp.arch), "net"),
                                     _ptr(y_out, wp.batch * n_lat, "y_out"),
@@ -518,7 +547,8 @@ def coolchic_warm_backward(wp: WarmProblem, x, net, y_target, theta_target, loss
     n_theta = sum(param_count(wp.arch))
     nn = warm_param_count(wp.arch)
     if ws is None:
-        ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
+        with _on(stream):
+            ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
     rc = _lib.coolchic_warm_backward(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
                                      _ptr(net, nn, "net"), _ptr(y_target, wp.batch * n_lat, "y_target"),
                                      _ptr(theta_target, wp.batch * n_theta, "theta_target"),
@@ -532,7 +562,8 @@ def coolchic_warm_backward_grad(wp: WarmProblem, x, net, g_y, g_theta, loss4, g_
     n_theta = sum(param_count(wp.arch))
     nn = warm_param_count(wp.arch)
     if ws is None:
-        ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
+        with _on(stream):
+            ws = warm_workspace(wp, CC_WS_BACKWARD, device=x.device)
     rc = _lib.coolchic_warm_backward_grad(ctypes.byref(wp.c()), _ptr(x, wp.batch * 3 * wp.H * wp.W, "x"),
                                           _ptr(net, nn, "net"), _ptr(g_y, wp.batch * n_lat, "g_y"),
                                           _ptr(g_theta, wp.batch * n_theta, "g_theta"), _ptr(loss4, 4, "loss4"),

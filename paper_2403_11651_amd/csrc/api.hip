@@ -224,31 +224,56 @@ int launch_stage(int stage, const void* fn, int grid, int block, void* args, hip
   return CC_OK;
 }
 
-// Side stream per device for the ARM kernel, which is independent of the
-// upsampling / synthesis chain until the final reductions: the call forks it
-// off the caller's stream with an event and joins it back with another.
-// Created once per device on first use (default priority, non-blocking).
+// Side stream for the ARM kernel, which is independent of the upsampling /
+// synthesis chain until the final reductions: the call forks it off the
+// caller's stream with an event and joins it back with another.  One side
+// stream and event set per (device, caller stream), created on first use
+// (default priority, non-blocking) or by coolchic_stream_prepare: calls on
+// different streams do not share them and run concurrently; calls on one
+// stream take its set's lock while they enqueue.
 struct Side {
+  int dev = -1;
+  hipStream_t main = nullptr;  // the caller's stream this set serves
   hipStream_t stream = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, head = nullptr;
+  std::mutex mu;
 };
-constexpr int MAX_DEVICES = 64;
-Side g_side[MAX_DEVICES];
-std::mutex g_side_mu;  // also serialises the fork/join enqueue of concurrent calls
+constexpr int MAX_DEVICES = 64;  // devices with a static-scratch address (coolchic_train_step_noalloc)
+constexpr int MAX_SIDES = 256;
+Side g_side[MAX_SIDES];
+int g_n_side = 0;
+std::mutex g_side_mu;  // guards the table
 
-int side_for_current_device(Side** out) {
+int side_for(hipStream_t main, Side** out) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return CC_EHIP;
-  Side& sd = g_side[dev];
-  if (!sd.stream) {
-    if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return CC_EHIP;
-    // the events only order the two streams of one device: no system-scope
-    // cache fence when they are recorded (1-2 % of the training iteration)
-    const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
-    if (hipEventCreateWithFlags(&sd.fork, fl) != hipSuccess) return CC_EHIP;
-    if (hipEventCreateWithFlags(&sd.join, fl) != hipSuccess) return CC_EHIP;
-    if (hipEventCreateWithFlags(&sd.head, fl) != hipSuccess) return CC_EHIP;
-  }
+  if (hipGetDevice(&dev) != hipSuccess) return CC_EHIP;
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  for (int i = 0; i < g_n_side; ++i)
+    if (g_side[i].dev == dev && g_side[i].main == main) {
+      *out = &g_side[i];
+      return CC_OK;
+    }
+  // a stream being captured into a graph without a set of its own uses one
+  // the device already has (no stream or event is created during capture)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(main, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
+    for (int i = 0; i < g_n_side; ++i)
+      if (g_side[i].dev == dev) {
+        *out = &g_side[i];
+        return CC_OK;
+      }
+  if (g_n_side == MAX_SIDES) return CC_EUNSUPPORTED;
+  Side& sd = g_side[g_n_side];
+  if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess) return CC_EHIP;
+  // the events only order the two streams of one device: no system-scope
+  // cache fence when they are recorded (1-2 % of the training iteration)
+  const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+  if (hipEventCreateWithFlags(&sd.fork, fl) != hipSuccess || hipEventCreateWithFlags(&sd.join, fl) != hipSuccess ||
+      hipEventCreateWithFlags(&sd.head, fl) != hipSuccess)
+    return CC_EHIP;
+  sd.dev = dev;
+  sd.main = main;
+  ++g_n_side;  // published only once complete
   *out = &sd;
   return CC_OK;
 }
@@ -351,9 +376,9 @@ int coolchic_forward(const cc_problem* p, const float* img, const float* y, cons
   if (!armk || !t0k || !resk) return CC_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   float* W = (float*)ws;
-  std::lock_guard<std::mutex> lock(g_side_mu);
   Side* sd = nullptr;
-  if ((rc = side_for_current_device(&sd))) return rc;
+  if ((rc = side_for(st, &sd))) return rc;
+  std::lock_guard<std::mutex> lock(sd->mu);
   (void)hipGetLastError();
   ArmArgs aa;
   std::memset(&aa, 0, sizeof(aa));
@@ -559,9 +584,10 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
     fuse_adam(*fused, b.comb_side, false, t_slot);
     fuse_adam(*fused, b.comb_main, true, t_slot);
   }
-  std::lock_guard<std::mutex> lock(g_side_mu);
   Side* sd = nullptr;
-  if (!one_stream && (rc = side_for_current_device(&sd))) return rc;
+  if (!one_stream && (rc = side_for(st, &sd))) return rc;
+  std::unique_lock<std::mutex> lock;
+  if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
   hipStream_t side = one_stream ? st : sd->stream;
   (void)hipGetLastError();
   if ((rc = launch_expand(P, (float*)ws, ups_w, st))) return rc;
@@ -913,9 +939,9 @@ int coolchic_batch_backward(const cc_batch* batch, void* stream) {
     if (timed && hipEventRecord(g_ev_end, st) != hipSuccess) return CC_EHIP;
     return CC_OK;
   };
-  std::lock_guard<std::mutex> lock(g_side_mu);
   Side* sd = nullptr;
-  if ((rc = side_for_current_device(&sd))) return rc;
+  if ((rc = side_for(st, &sd))) return rc;
+  std::lock_guard<std::mutex> lock(sd->mu);
   (void)hipGetLastError();
   // the ARM launch goes to the side stream (it depends on nothing the main
   // stream computes): first, after the residual-conv backward, or after the
@@ -1018,6 +1044,11 @@ int coolchic_uniform_noise(float* u, int64_t n, uint64_t seed, const int32_t* st
   if (hipLaunchKernel((const void*)noise_kernel, dim3(grid), dim3(256), argv, 0, (hipStream_t)stream) != hipSuccess)
     return CC_EHIP;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
+}
+
+int coolchic_stream_prepare(void* stream) {
+  Side* sd = nullptr;
+  return side_for((hipStream_t)stream, &sd);
 }
 
 int coolchic_set_stage_events(int stage, void* ev_begin, void* ev_end) {

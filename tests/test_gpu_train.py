@@ -205,3 +205,57 @@ def test_train_step_graph_replay_matches_eager(B):
         for a, b in zip(eager, graphed):
             assert torch.equal(a, b), r
     assert eager[4].cpu().tolist()[0] == 7
+
+
+def test_train_steps_on_two_streams_run_concurrently_and_match(B):
+    """Two problems trained on two streams, their calls interleaved without
+    synchronisation (each stream has its own side stream and events): every
+    state equals that of the same steps run one problem after the other.
+    Then a graph captured on a fresh, prepared stream replays bit-identically
+    to eager steps."""
+    cases = [CS.make("ragged_L7_64x192", 64, 192, CS.FULL, seeds=(30, 31, 32, 33), noise=True),
+             CS.make("small_64x128", 64, 128, CS.LOW, seeds=(34, 35, 36, 37), noise=True)]
+
+    def state(c):
+        th = _dev(np.concatenate([c.y, c.arm, c.ups, c.syn]).astype(np.float32))
+        return [th, torch.zeros_like(th), torch.zeros_like(th), torch.zeros_like(th),
+                torch.zeros(2, dtype=torch.int32, device="cuda"), torch.zeros(4, device="cuda")]
+
+    probs = [_problem(B, c) for c in cases]
+    inputs = [(_dev(c.img), _dev(c.u)) for c in cases]
+
+    def step(k, sv, stream=None):
+        th, g, m, v, st, l4 = sv
+        B.coolchic_train_step(probs[k], inputs[k][0], inputs[k][1], 1.0, l4, th, g, m, v, st, lr=1e-2, beta1=0.9,
+                              beta2=0.999, eps=1e-8, stream=stream)
+
+    seq = [state(c) for c in cases]
+    for k in range(2):
+        for _ in range(4):
+            step(k, seq[k])
+    torch.cuda.synchronize()
+    conc = [state(c) for c in cases]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for _ in range(4):
+        for k in range(2):
+            step(k, conc[k], streams[k])
+    torch.cuda.synchronize()
+    for k in range(2):
+        for a, b in zip(seq[k], conc[k]):
+            assert torch.equal(a, b), k
+
+    # capture on a stream prepared beforehand (no eager call on it first)
+    cap = torch.cuda.Stream()
+    B.coolchic_stream_prepare(cap)
+    eager, graphed = state(cases[0]), state(cases[0])
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=cap):
+        step(0, graphed)
+    for r in range(2):
+        step(0, eager)
+        gr.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, graphed):
+            assert torch.equal(a, b), r
