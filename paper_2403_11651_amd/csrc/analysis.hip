@@ -38,7 +38,8 @@ constexpr float AN_LN_EPS = 1e-6f;
 constexpr int AN_THREADS = 256;
 constexpr int AN_MAX_GRID = 1024;  // work-groups of the first block's MLP launch at most
 constexpr int AN_BW = 8, AN_BT = 64 * AN_BW;  // waves, threads per work-group of the fused block kernel
-constexpr int AN_BLOCK_GRID = 256;  // fused block kernel: one work-group per CU (its LDS holds one)
+constexpr int AN_BLOCK_GRID = 256;  // fused block kernels: one work-group per CU (their LDS holds one)
+constexpr int AN_TEAM_MAX_POSITIONS = 6144;  // blocks of at most this many output positions per image: team kernel
 
 // Per-block host-side description (offsets in floats into theta, in
 // uint16 into the bf16 operand area of the workspace).
@@ -230,6 +231,76 @@ __device__ __forceinline__ AnPos an_pos(const AnArgs& a, int p) {
   return q;
 }
 
+// One hidden chunk c (32 units) of a wave's 32 positions: the first product
+// from tb, GELU, rounded, and the second product added to acc2.
+template <int KIN>
+__device__ __forceinline__ void an_mlp_chunk(const AnMlpLds<KIN>& s, const bf16x8 (&tb)[KIN / 16], int c, int lane,
+                                             f32x16 (&acc2)[2]) {
+  constexpr int S1 = AnMlpLds<KIN>::S1, S2 = AnMlpLds<KIN>::S2;
+  const int hi = lane >> 5, col = lane & 31;
+  // hidden units c*32 + 8 (r / 4) + 4 hi + r % 4 of the 32 positions
+  f32x16 acc1;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc1[r] = s.b1[c * 32 + 8 * (r >> 2) + 4 * hi + (r & 3)];
+#pragma unroll
+  for (int kk = 0; kk < KIN / 16; ++kk) acc1 = mfma_bf16(load8(&s.w1[(c * 32 + col) * S1 + kk * 16 + hi * 8]), tb[kk], acc1);
+  // GELU, rounded: K-step t of the second product takes accumulators
+  // 8 t .. 8 t + 7, i.e. hidden units c*32 + 16 t + 8 (e / 4) + 4 hi + e % 4
+  bf16x8 hb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) hb[t][e] = (__bf16)gelu(acc1[8 * t + e]);
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const uint16_t* w = &s.w2[(mt * 32 + col) * S2 + c * 32 + 16 * t + 4 * hi];
+      const uint2 u0 = *reinterpret_cast<const uint2*>(w), u1 = *reinterpret_cast<const uint2*>(w + 8);
+      acc2[mt] = mfma_bf16(__builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y)), hb[t], acc2[mt]);
+    }
+}
+
+// identity branch through a 1x1 convolution, added to acc2: the image (first
+// block) or the 2x2-average-pooled input (downsampling blocks), rounded
+__device__ __forceinline__ void an_identity(const AnArgs& a, const AnPos& pos, int lane, f32x16 (&acc2)[2]) {
+  const int hi = lane >> 5, col = lane & 31;
+  const bool ok = pos.ok;
+  const int img = pos.img, i = pos.i, j = pos.j;
+#pragma unroll 1
+  for (int kk = 0; kk < a.kid / 16; ++kk) {
+    bf16x8 sb;
+    if (a.c_in == 3) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int ch = kk * 16 + hi * 8 + e;
+        const float v = ok && ch < 3 ? a.x[(((size_t)img * 3 + ch) * a.hi + i) * a.wi + j] : 0.0f;
+        sb[e] = (__bf16)v;
+      }
+    } else {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t pin = ((size_t)img * a.hi + 2 * i + (q >> 1)) * a.wi + 2 * j + (q & 1);
+        const uint4 u = ok ? *reinterpret_cast<const uint4*>(a.fin + pin * AN_C + kk * 16 + hi * 8) : make_uint4(0, 0, 0, 0);
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[2 * e] += bf16_f(w4[e] & 0xffffu);
+          v[2 * e + 1] += bf16_f(w4[e] >> 16);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sb[e] = (__bf16)(v[e] * 0.25f);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+      acc2[mt] = mfma_bf16(load8(a.wid + (size_t)(mt * 32 + col) * a.kid + kk * 16 + hi * 8), sb, acc2[mt]);
+  }
+}
+
 // One wave, 32 positions: both 1x1 layers, GELU, the identity branch, the
 // bfloat16 block output and the head.  tb holds the B operands of the first
 // product (the lane's position pos, column lane % 32 of the products,
@@ -237,8 +308,7 @@ __device__ __forceinline__ AnPos an_pos(const AnArgs& a, int p) {
 template <int KIN>
 __device__ __forceinline__ void an_mlp_tile(const AnArgs& a, const AnMlpLds<KIN>& s, const bf16x8 (&tb)[KIN / 16],
                                             const AnPos& pos, int lane) {
-  constexpr int S1 = AnMlpLds<KIN>::S1, S2 = AnMlpLds<KIN>::S2;
-  const int hi = lane >> 5, col = lane & 31;
+  const int hi = lane >> 5;
   const bool ok = pos.ok;
   f32x16 acc2[2];
 #pragma unroll
@@ -246,67 +316,10 @@ __device__ __forceinline__ void an_mlp_tile(const AnArgs& a, const AnMlpLds<KIN>
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc2[mt][r] = 0.0f;
 #pragma unroll 1
-  for (int c = 0; c < AN_HID / 32; ++c) {
-    // hidden units c*32 + 8 (r / 4) + 4 hi + r % 4 of the 32 positions
-    f32x16 acc1;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc1[r] = s.b1[c * 32 + 8 * (r >> 2) + 4 * hi + (r & 3)];
-#pragma unroll
-    for (int kk = 0; kk < KIN / 16; ++kk) acc1 = mfma_bf16(load8(&s.w1[(c * 32 + col) * S1 + kk * 16 + hi * 8]), tb[kk], acc1);
-    // GELU, rounded: K-step t of the second product takes accumulators
-    // 8 t .. 8 t + 7, i.e. hidden units c*32 + 16 t + 8 (e / 4) + 4 hi + e % 4
-    bf16x8 hb[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) hb[t][e] = (__bf16)gelu(acc1[8 * t + e]);
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const uint16_t* w = &s.w2[(mt * 32 + col) * S2 + c * 32 + 16 * t + 4 * hi];
-        const uint2 u0 = *reinterpret_cast<const uint2*>(w), u1 = *reinterpret_cast<const uint2*>(w + 8);
-        acc2[mt] = mfma_bf16(__builtin_bit_cast(bf16x8, make_uint4(u0.x, u0.y, u1.x, u1.y)), hb[t], acc2[mt]);
-      }
-  }
+  for (int c = 0; c < AN_HID / 32; ++c) an_mlp_chunk<KIN>(s, tb, c, lane, acc2);
   const int img = pos.img, i = pos.i, j = pos.j, rr = i * a.wo + j;
   const size_t pc = ((size_t)img * a.ho + i) * a.wo + j;
-  // identity branch through a 1x1 convolution: the image (first block) or
-  // the 2x2-average-pooled input (downsampling blocks), rounded
-  if (a.kid) {
-#pragma unroll 1
-    for (int kk = 0; kk < a.kid / 16; ++kk) {
-      bf16x8 sb;
-      if (a.c_in == 3) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int ch = kk * 16 + hi * 8 + e;
-          const float v = ok && ch < 3 ? a.x[(((size_t)img * 3 + ch) * a.hi + i) * a.wi + j] : 0.0f;
-          sb[e] = (__bf16)v;
-        }
-      } else {
-        float v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const size_t pin = ((size_t)img * a.hi + 2 * i + (q >> 1)) * a.wi + 2 * j + (q & 1);
-          const uint4 u = ok ? *reinterpret_cast<const uint4*>(a.fin + pin * AN_C + kk * 16 + hi * 8) : make_uint4(0, 0, 0, 0);
-          const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            v[2 * e] += bf16_f(w4[e] & 0xffffu);
-            v[2 * e + 1] += bf16_f(w4[e] >> 16);
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) sb[e] = (__bf16)(v[e] * 0.25f);
-      }
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        acc2[mt] = mfma_bf16(load8(a.wid + (size_t)(mt * 32 + col) * a.kid + kk * 16 + hi * 8), sb, acc2[mt]);
-    }
-  }
+  if (a.kid) an_identity(a, pos, lane, acc2);
   // output: + biases (+ the input itself), rounded to bfloat16; the head
   float hsum = 0.0f;
 #pragma unroll
@@ -606,6 +619,194 @@ __global__ __launch_bounds__(AN_BT) void ana_block_kernel(AnArgs a) {
   }
 }
 
+// Blocks of the coarse levels (a few thousand positions per image or fewer),
+// where a wave's serial chain -- its rows of loads, eight hidden chunks, the
+// epilogue -- sets the time of ana_block_kernel: the whole work-group takes
+// one 32-position tile at a time.  Depth-wise: wave w computes positions
+// 4w .. 4w + 3 of the tile, eight lanes per position (eight channels each)
+// and two lanes per channel group splitting the seven rows (0-3, 4-6), all
+// of a lane's loads issued at once.  MLP: wave w computes hidden chunk w (32
+// units) and writes its share of the second product to LDS (wave 0 adds the
+// identity branch); wave w then sums the eight shares of output channels
+// 32 (w / 4) + 8 (w % 4) .. + 7 of the 32 positions for the epilogue.  The
+// depth-wise sums run in another order than in ana_block_kernel, so a block
+// is run by one kernel or the other according to its size per image only.
+template <int S>
+__global__ __launch_bounds__(AN_BT) void ana_block_team_kernel(AnArgs a) {
+  constexpr int ST = AN_C + 8, SP = 33;  // LDS row strides: features (bf16), second-product shares (floats)
+  static_assert(AN_BW == 8, "one hidden chunk per wave");
+  __shared__ AnMlpLds<AN_C> s;
+  __shared__ __align__(16) float s_dw[AN_TAPS * AN_C];  // [tap][channel]
+  __shared__ __align__(16) uint16_t s_t[32 * ST];
+  __shared__ float s_part[AN_BW * 64 * SP];             // [wave][lane][32 accumulators]
+  __shared__ float s_head[AN_BW * 32];
+  __shared__ float s_dwb[AN_C], s_lg[AN_C], s_lb[AN_C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hi = lane >> 5, col = lane & 31;
+  {
+    constexpr int RD = (AN_TAPS * AN_C + AN_BT - 1) / AN_BT;
+    float v[RD];
+#pragma unroll
+    for (int q = 0; q < RD; ++q) {
+      const int k = min(tid + q * AN_BT, AN_TAPS * AN_C - 1);
+      v[q] = a.dw_w[(k % AN_C) * AN_TAPS + k / AN_C];
+    }
+    float vb = 0.0f, vg = 0.0f, vl = 0.0f;
+    if (tid < AN_C) {
+      vb = a.dw_b[tid];
+      vg = a.ln_g[tid];
+      vl = a.ln_b[tid];
+    }
+    an_stage_mlp<AN_C, AN_BT>(a, s, tid);
+#pragma unroll
+    for (int q = 0; q < RD; ++q) {
+      const int k = tid + q * AN_BT;
+      if (k < AN_TAPS * AN_C) s_dw[k] = v[q];
+    }
+    if (tid < AN_C) {
+      s_dwb[tid] = vb;
+      s_lg[tid] = vg;
+      s_lb[tid] = vl;
+    }
+  }
+  __syncthreads();
+  const int npx = a.n * a.ho * a.wo, tiles = (npx + 31) / 32;
+  const int cg = lane & 7, p4 = (lane >> 3) & 3, half = lane >> 5;
+  const int mt_e = wave >> 2, qd_e = wave & 3;  // this wave's output channels in the epilogue
+  for (int g = blockIdx.x; g < tiles; g += gridDim.x) {  // uniform over the work-group
+    const int px0 = g * 32;
+    // ---- depth-wise 7x7 and layer norm of position 4 wave + p4
+    {
+      const AnPos q = an_pos(a, px0 + 4 * wave + p4);
+      const uint16_t* base = a.fin + (size_t)q.img * a.hi * a.wi * AN_C + cg * 8;
+      uint4 u[4][AN_K];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int dy = 4 * half + r, iy = S * q.i + dy - 3;
+        const bool row_ok = q.ok && dy < AN_K && iy >= 0 && iy < a.hi;
+#pragma unroll
+        for (int dx = 0; dx < AN_K; ++dx) {
+          const int ix = S * q.j + dx - 3;
+          u[r][dx] = (row_ok && ix >= 0 && ix < a.wi) ? *reinterpret_cast<const uint4*>(base + ((size_t)iy * a.wi + ix) * AN_C)
+                                                      : make_uint4(0, 0, 0, 0);
+        }
+      }
+      float acc[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int dy = min(4 * half + r, AN_K - 1);  // row 7 of the second half: zeros, any weights
+#pragma unroll
+        for (int dx = 0; dx < AN_K; ++dx) {
+          const float4 w0 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8]);
+          const float4 w1 = *reinterpret_cast<const float4*>(&s_dw[(dy * AN_K + dx) * AN_C + cg * 8 + 4]);
+          const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          const uint32_t w4[4] = {u[r][dx].x, u[r][dx].y, u[r][dx].z, u[r][dx].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            acc[2 * e] = __builtin_fmaf(w[2 * e], bf16_f(w4[e] & 0xffffu), acc[2 * e]);
+            acc[2 * e + 1] = __builtin_fmaf(w[2 * e + 1], bf16_f(w4[e] >> 16), acc[2 * e + 1]);
+          }
+        }
+      }
+      // rows 0-3 + rows 4-6, then the bias
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float other = __shfl_xor(acc[e], 32, 64);
+        acc[e] = (half == 0 ? acc[e] + other : other + acc[e]) + s_dwb[cg * 8 + e];
+      }
+      float sm = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sm += acc[e];
+      sm += __shfl_xor(sm, 1, 64);
+      sm += __shfl_xor(sm, 2, 64);
+      sm += __shfl_xor(sm, 4, 64);
+      const float mean = sm / 64.0f;
+      float sq = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sq += (acc[e] - mean) * (acc[e] - mean);
+      sq += __shfl_xor(sq, 1, 64);
+      sq += __shfl_xor(sq, 2, 64);
+      sq += __shfl_xor(sq, 4, 64);
+      const float rs = 1.0f / sqrtf(sq / 64.0f + AN_LN_EPS);
+      if (half == 0) {
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = cg * 8 + 2 * e;
+          const uint32_t lo = bf16_bits((acc[2 * e] - mean) * rs * s_lg[c] + s_lb[c]);
+          const uint32_t hb = bf16_bits((acc[2 * e + 1] - mean) * rs * s_lg[c + 1] + s_lb[c + 1]);
+          o[e] = lo | (hb << 16);
+        }
+        *reinterpret_cast<uint4*>(&s_t[(4 * wave + p4) * ST + cg * 8]) = make_uint4(o[0], o[1], o[2], o[3]);
+      }
+    }
+    __syncthreads();
+    // ---- hidden chunk `wave` of the tile's 32 positions
+    const AnPos pos = an_pos(a, px0 + col);
+    {
+      bf16x8 tb[AN_C / 16];
+#pragma unroll
+      for (int kk = 0; kk < AN_C / 16; ++kk) tb[kk] = pos.ok ? load8(&s_t[col * ST + kk * 16 + hi * 8]) : zero8();
+      f32x16 acc2[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc2[mt][r] = 0.0f;
+      an_mlp_chunk<AN_C>(s, tb, wave, lane, acc2);
+      if (wave == 0 && a.kid) an_identity(a, pos, lane, acc2);
+      float* dst = &s_part[(wave * 64 + lane) * SP];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[mt * 16 + r] = acc2[mt][r];
+    }
+    __syncthreads();
+    // ---- epilogue: output channels ch0 .. ch0 + 3 of the lane's position
+    {
+      const int ch0 = mt_e * 32 + 8 * qd_e + 4 * hi;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = 0.0f;
+#pragma unroll
+      for (int w = 0; w < AN_BW; ++w)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] += s_part[(w * 64 + lane) * SP + mt_e * 16 + 4 * qd_e + e];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += s.b2[ch0 + e];
+      const size_t pc = ((size_t)pos.img * a.ho + pos.i) * a.wo + pos.j;
+      if (!a.kid && pos.ok) {
+        const uint2 u = *reinterpret_cast<const uint2*>(a.fin + pc * AN_C + ch0);
+        v[0] += bf16_f(u.x & 0xffffu);
+        v[1] += bf16_f(u.x >> 16);
+        v[2] += bf16_f(u.y & 0xffffu);
+        v[3] += bf16_f(u.y >> 16);
+      }
+      uint32_t h[4];
+      float hsum = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        h[e] = bf16_rne(v[e]);
+        hsum = __builtin_fmaf(s.hw[ch0 + e], bf16_f(h[e]), hsum);
+      }
+      if (pos.ok) *reinterpret_cast<uint2*>(a.fout + pc * AN_C + ch0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      if (a.head) {
+        hsum += __shfl_xor(hsum, 32, 64);
+        if (hi == 0) s_head[wave * 32 + col] = hsum;
+      }
+    }
+    if (a.head) {  // uniform
+      __syncthreads();
+      if (wave == 0 && hi == 0 && pos.ok) {
+        float y = 0.0f;
+#pragma unroll
+        for (int w = 0; w < AN_BW; ++w) y += s_head[w * 32 + col];
+        a.y[(size_t)pos.img * a.n_lat + a.loff + pos.i * a.wo + pos.j] = y + a.head[AN_C];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 // positions are counted in 32 bits on the device: n H W < 2^31
@@ -745,6 +946,12 @@ int coolchic_analysis_forward(int32_t H, int32_t W, int32_t n, const float* x, c
       const unsigned grid = (unsigned)std::min<long long>((tiles + 3) / 4, AN_MAX_GRID);
       if (hipLaunchKernel((const void*)ana_mlp16_kernel, dim3(grid), dim3(AN_THREADS), argv, 0, st) != hipSuccess)
         return CC_EHIP;
+    } else if (a.ho * a.wo <= AN_TEAM_MAX_POSITIONS) {
+      // chosen by the size per image only, so a batch of images runs every
+      // block with the same kernel as single images
+      const void* k = B.stride == 2 ? (const void*)ana_block_team_kernel<2> : (const void*)ana_block_team_kernel<1>;
+      const unsigned grid = (unsigned)std::min<long long>(tiles, AN_BLOCK_GRID);
+      if (hipLaunchKernel(k, dim3(grid), dim3(AN_BT), argv, 0, st) != hipSuccess) return CC_EHIP;
     } else {
       const bool rowseg = a.wo % 32 == 0;
       const void* k = B.stride == 2 ? (rowseg ? (const void*)ana_block_kernel<2, true> : (const void*)ana_block_kernel<2, false>)
