@@ -135,6 +135,26 @@ def test_analysis_full_size_windows(B, level):
         _check(g.ravel(), [ref], [(s_rel, s_elem)], f"768x512 level {level} window ({i0}, {j0})")
 
 
+def test_analysis_full_size_level3_corner(B):
+    """768x512, grid 3 (the coarse levels' work-group-per-tile kernel): the
+    8x8 corner window against the oracle on the image region it depends on
+    (the oracle's own sensitivity from the larger of two draws)."""
+    H, W = 512, 768
+    theta = WL.analysis_params(31)
+    img = WL.image(10, H, W, 200)
+    got = _run(B, img[None], theta)[0]
+    th64, x64 = theta.astype(np.float64), img.astype(np.float64)
+    rng = np.random.default_rng(8)
+    ref = A.window_latents(x64, th64, 3, 0, 0, 8)
+    s_rel = s_elem = 0.0
+    for _ in range(2):
+        ref2 = A.window_latents(x64 * (1.0 + PERTURB * rng.normal(size=x64.shape)), th64, 3, 0, 0, 8)
+        s_rel = max(s_rel, np.linalg.norm(ref - ref2) / np.linalg.norm(ref))
+        s_elem = max(s_elem, np.abs(ref - ref2).max() / np.abs(ref).max())
+    g = _grid(got, H, W, 3)[:8, :8]
+    _check(g.ravel(), [ref], [(s_rel, s_elem)], "768x512 level 3 corner")
+
+
 def test_analysis_full_size_eight_images_per_call(B):
     """The benchmark's batched launch (eight 768x512 images per call) gives
     every image exactly its single-image result; every latent is finite."""
