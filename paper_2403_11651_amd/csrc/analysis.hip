@@ -9,9 +9,11 @@
 // block's 1x1 convolutions on the bfloat16 matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation), GELU between them, the
 // identity branch, the bfloat16 block output and, for a level's last block,
-// its latent head.  The first block (3 image channels) runs as
-// ana_dw3_kernel (depth-wise conv + norm, T with 16 channels in global
-// memory) and ana_mlp16_kernel.
+// its latent head.  Blocks of at most AN_TEAM_MAX_POSITIONS positions per
+// image (the coarse levels) run as ana_block_team_kernel instead, a whole
+// work-group on one 32-position tile.  The first block (3 image channels)
+// runs as ana_dw3_kernel (depth-wise conv + norm, T with 16 channels in
+// global memory) and ana_mlp16_kernel.
 // The MLP works transposed: with the weights as the A operand and 32
 // positions as the columns, the hidden layer's accumulators (rows = hidden
 // units) feed the second product as its B operand without leaving the
