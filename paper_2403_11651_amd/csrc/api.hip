@@ -45,6 +45,9 @@ struct Plan {
   int red_blocks_arm, red_blocks_ups[MAXL], red_blocks_syn;
   int ups_grid[MAXL];
   int ups_cpb[MAXL], ups_chunks[MAXL];  // channels per upsampling-adjoint block, blocks per tile
+  // one image's coarse adjoint steps composed (separable, L >= 5, LDS fits):
+  // work-groups of each composed step s (prefix sums from s = 3)
+  int coarse, comp_first[MAXL + 1];
   // workspace offsets, in floats
   size_t up[MAXL];       // U_s output, s = 1..L-2
   size_t gb[MAXL];       // adjoint buffers, s = 1..L-2
@@ -130,6 +133,12 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     // tile in one block; the small levels keep one channel per block
     P->ups_cpb[s] = P->ups_grid[s] >= 256 ? L - 1 - s : 1;
     P->ups_chunks[s] = cdiv(L - 1 - s, P->ups_cpb[s]);
+  }
+  P->coarse = !P->shared && L >= 5;
+  for (int s = 3; s + 1 < L; ++s) P->coarse = P->coarse && ups_compose_lds(g, s) <= UC_POOL;
+  if (P->coarse) {
+    P->comp_first[3] = 0;
+    for (int s = 3; s + 1 < L; ++s) P->comp_first[s + 1] = P->comp_first[s] + (L - 1 - s) * cdiv(g.lh[s], UC_R);
   }
   // the ARM context fold of the side combine takes the first side_levels
   // levels (level 0 is final once the head backward has run, level 1 after
@@ -617,10 +626,41 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   // level 0 of g_y is final: the side combine may start
   if (!one_stream && (rc = side_waits(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, side))) return rc;
-  for (int s = 0; s + 1 < L; ++s) {
+  // the upsampling adjoint: step by step, or for L >= 5 step 0, then step 1
+  // beside the composed inputs of steps 3 .. L-2, then steps 2 .. L-2 at once
+  // (three launches instead of L - 1 latency-bound ones)
+  for (int s = 0; s + 1 < L && (s == 0 || !P.coarse); ++s) {
     void* argv[] = {&b.upb[s]};
     if (hipLaunchKernel(ups_bwd_kernel_for(P.shared, false), dim3(P.ups_grid[s], P.ups_chunks[s]), dim3(256), argv, 0,
                         st) !=
+        hipSuccess)
+      return CC_EHIP;
+  }
+  if (P.coarse) {
+    UpsComposeArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.geo = P.geo;
+    ca.taps = b.upb[0].taps;  // the separable taps from step 0 on
+    ca.g1 = b.upb[1].g_in;
+    for (int s = 3; s + 1 < L; ++s) ca.gs[s] = b.upb[s - 1].g_out;
+    std::memcpy(ca.first, P.comp_first, sizeof(ca.first));
+    int st1_tiles = P.ups_grid[1], st1_wgs = P.ups_grid[1] * P.ups_chunks[1];
+    void* argc[] = {&b.upb[1], &st1_tiles, &st1_wgs, &ca};
+    if (hipLaunchKernel((const void*)ups_bwd_coarse_kernel, dim3(st1_wgs + P.comp_first[L - 1]), dim3(256), argc, 0,
+                        st) != hipSuccess)
+      return CC_EHIP;
+    static thread_local UpsBwdSteps ms;
+    std::memset(&ms, 0, sizeof(ms));
+    ms.n = L - 3;
+    for (int k = 0; k < ms.n; ++k) {
+      const int s = k + 2;
+      ms.st[k] = b.upb[s];
+      ms.st[k].g_out = nullptr;
+      ms.tiles[k] = P.ups_grid[s];
+      ms.first[k + 1] = ms.first[k] + P.ups_grid[s] * P.ups_chunks[s];
+    }
+    void* argm[] = {&ms};
+    if (hipLaunchKernel((const void*)ups_bwd_steps_kernel, dim3(ms.first[ms.n]), dim3(256), argm, 0, st) !=
         hipSuccess)
       return CC_EHIP;
   }

@@ -91,6 +91,38 @@ struct UpsBwdArgs {
   int cpb;             // channels of stack_{s+1} per block: block (tile, chunk) takes [chunk cpb, chunk cpb + cpb)
 };
 const void* ups_bwd_kernel_for(bool shared, bool batch);
+// Coarse steps of the adjoint of one image without the step-by-step chain
+// (separable kernels, L >= 5): the gradient at U_s's output for 3 <= s <= L-2
+// is the composed adjoint of steps 1 .. s-1 applied to the gradient at U_1's
+// output, G_s = Cv^T G_1 Ch with the 1-D products Cv = V_1 ... V_{s-1} and
+// Ch = H_1 ... H_{s-1}.  ups_bwd_coarse_kernel runs step 1 (work-groups
+// [0, st1_wgs)) beside the composed G_s (the rest); ups_bwd_steps_kernel then
+// runs steps 2 .. L-2 at once, each reading its G_s and writing its g_y level
+// and tap partials (g_out null: the next step's input is already there).
+constexpr int UC_R = 2;        // rows of G_s per composing work-group
+constexpr int UC_POOL = 3072;  // LDS floats of a composing work-group
+struct UpsComposeArgs {
+  Geo geo;
+  const float* taps;    // separable taps [L-1][2][8]
+  const float* g1;      // gradient at U_1's output: [(L-2)][h_1][w_1], levels 2 .. L-1
+  float* gs[MAXL];      // gs[s], 3 <= s <= L-2: gradient at U_s's output, [(L-1-s)][h_s][w_s]
+  int first[MAXL + 1];  // composing work-groups of step s: [first[s], first[s + 1]), first[3] = 0
+};
+// LDS floats a composing work-group of step s needs (the row windows while
+// they are built, the vertical pass and the horizontal steps' rows)
+inline int ups_compose_lds(const Geo& g, int s) {
+  const int m = s - 1, bm = 7 * ((1 << m) - 1) + 1, bp = 7 * ((1 << (m - 1)) - 1) + 1;
+  const int umax = (UC_R - 1) * (1 << m) + bm;
+  return ((UC_R * (bm + bp + umax) + 3) & ~3) + UC_R * (g.lw[1] + g.lw[1] / 2);
+}
+struct UpsBwdSteps {
+  UpsBwdArgs st[MAXL];
+  int first[MAXL + 1];  // work-groups of st[k]: [first[k], first[k + 1])
+  int tiles[MAXL];
+  int n;
+};
+__global__ void ups_bwd_coarse_kernel(UpsBwdArgs st1, int st1_tiles, int st1_wgs, UpsComposeArgs c);
+__global__ void ups_bwd_steps_kernel(UpsBwdSteps m);
 // 4-tap parameters (separable [L-1][2][4] or shared [4][4]) as 8-tap ones
 // with two zero taps on each side; one thread per output tap
 __global__ void ups_expand_kernel(const float* src, float* dst, int n_steps, int shared);

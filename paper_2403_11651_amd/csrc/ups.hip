@@ -293,7 +293,7 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
         }
       }
       if (ch == 0) a.g_y[idx] = gsum;
-      else a.g_out[(size_t)(ch - 1) * hi * wi + idx] = gsum;
+      else if (a.g_out) a.g_out[(size_t)(ch - 1) * hi * wi + idx] = gsum;
     }
     __syncthreads();
   }
@@ -319,6 +319,153 @@ __device__ __forceinline__ void ups_bwd_body(const UpsBwdArgs& a, const int bid,
     for (int wv = 0; wv < 4; ++wv) acc += s_red[wv][tid];
     a.part[((size_t)chunk * ntiles + bid) * ncol + tid] = acc;
   }
+}
+
+// ---- composed coarse adjoint (separable kernels)
+// Column q of the 1-D product P_m of m steps (input length n at the coarse
+// end) is nonzero only on rows [2^m q - 3 (2^m - 1), 2^m q + 4 (2^m - 1)]:
+// one step maps a window at offset o and width B to offset 2 o - 3 and width
+// 2 B + 6 (output x takes tap t of input (x + 3 - t) / 2 for the t with
+// x + 3 - t even, clamped to the grid; clamped indices of border outputs fall
+// in the same windows).  uc_step applies step j (1-based, after j - 1 steps
+// already applied; j = 1 starts from the unit vector) to columns q0 ..
+// q0 + nq - 1, reading windows of width B_{j-1} from src and writing width B_j
+// to dst; entries on rows outside [0, n_out) are zero.
+__device__ __forceinline__ int uc_width(int j) { return 7 * ((1 << j) - 1) + 1; }
+__device__ __forceinline__ int uc_offset(int j, int q) { return (1 << j) * q - 3 * ((1 << j) - 1); }
+__device__ __forceinline__ void uc_step(const float* tp, int n_in, int n_out, int j, int q0, int nq,
+                                        const float* src, float* dst) {
+  const int bs = uc_width(j - 1), bd = uc_width(j);
+  for (int p = threadIdx.x; p < nq * bd; p += 256) {
+    const int c = p / bd, e = p % bd, q = q0 + c;
+    const int os = uc_offset(j - 1, q), x = uc_offset(j, q) + e;
+    float acc = 0.0f;
+    if (x >= 0 && x < n_out) {
+      const int par = (x + 3) & 1;
+#pragma unroll
+      for (int u = 0; u < UPS_K / 2; ++u) {
+        const int t = 2 * u + par;
+        const float w = tp[t];
+        const int i = clampi((x + 3 - t) >> 1, 0, n_in - 1) - os;
+        const float v = j == 1 ? (i == 0 ? 1.0f : 0.0f) : ((i >= 0 && i < bs) ? src[c * bs + i] : 0.0f);
+        acc = __builtin_fmaf(w, v, acc);
+      }
+    }
+    dst[p] = acc;
+  }
+}
+
+// Work-group b of the composing part: step s (3 <= s <= L-2), one latent level
+// above it and UC_R rows of G_s.  Builds the windows of Cv for its rows, runs
+// the vertical pass Vt[r][x] = sum_i Cv[i][r] G_1[i][x] over the union of the
+// rows' windows (G_1 read once, four columns per lane, the two halves of a
+// wave taking alternate rows), then the horizontal part as the adjoints of
+// the steps' horizontal passes one after the other on its UC_R rows (1-D, in
+// LDS): an input j takes sum_t h[t] g[2 m' - 3 + t] over the padded indices
+// m' that clamp to it (j, and the two beyond the border for border inputs).
+__device__ __forceinline__ void ups_compose_body(const UpsComposeArgs& a, const int b) {
+  __shared__ __align__(16) float pool[UC_POOL];
+  __shared__ float s_tap[MAXL][2 * UPS_K];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int s = 3;
+  while (b >= a.first[s + 1]) ++s;
+  const int m = s - 1, h1 = a.geo.lh[1], w1 = a.geo.lw[1], hs = a.geo.lh[s];
+  const int nrb = (hs + UC_R - 1) / UC_R, local = b - a.first[s];
+  const int ch = local / nrb, r0 = (local % nrb) * UC_R, nr = min(UC_R, hs - r0);
+  const int bm = uc_width(m), bp = uc_width(m - 1), umax = (UC_R - 1) * (1 << m) + bm;
+  float* cv0 = pool;                    // Cv windows [UC_R][bm]
+  float* cv1 = cv0 + UC_R * bm;         // [UC_R][bp]
+  float* cvu = cv1 + UC_R * bp;         // [UC_R][umax]: Cv over the union of rows
+  float* va = pool + ((cvu - pool + UC_R * umax + 3) & ~3);  // [UC_R][w1], 16-byte aligned
+  float* vb = va + UC_R * w1;           // [UC_R][w1 / 2]
+  if (tid < m * 2 * UPS_K) s_tap[1 + tid / (2 * UPS_K)][tid % (2 * UPS_K)] = a.taps[2 * UPS_K + tid];
+  __syncthreads();
+  // step j of the recursion is forward step k = s - j; the last (j = m)
+  // lands in cv0
+  for (int j = 1; j <= m; ++j) {
+    const int k = s - j;
+    const bool to0 = ((m - j) & 1) == 0;
+    uc_step(s_tap[k], a.geo.lh[k + 1], a.geo.lh[k], j, r0, nr, to0 ? cv1 : cv0, to0 ? cv0 : cv1);
+    __syncthreads();
+  }
+  const int ilo = max(0, uc_offset(m, r0)), ihi = min(h1 - 1, uc_offset(m, r0 + nr - 1) + bm - 1);
+  for (int p = tid; p < UC_R * umax; p += 256) {
+    const int r = p / umax, i = ilo + p % umax, e = i - uc_offset(m, r0 + r);
+    cvu[p] = (r < nr && i <= ihi && e >= 0 && e < bm) ? cv0[r * bm + e] : 0.0f;
+  }
+  __syncthreads();
+  const float* g1 = a.g1 + (size_t)(s - 1 + ch) * h1 * w1;
+  const int nxg = w1 >> 2, half = lane >> 5;
+  for (int base = wave * 32; base < nxg; base += 128) {
+    const int xg = base + (lane & 31);
+    const bool ok = xg < nxg;
+    float4 acc[UC_R];
+#pragma unroll
+    for (int r = 0; r < UC_R; ++r) acc[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ok) {
+#pragma unroll 8
+      for (int i = ilo + half; i <= ihi; i += 2) {
+        const float4 g = *reinterpret_cast<const float4*>(g1 + (size_t)i * w1 + 4 * xg);
+#pragma unroll
+        for (int r = 0; r < UC_R; ++r) {
+          const float c = cvu[r * umax + i - ilo];
+          acc[r].x = __builtin_fmaf(c, g.x, acc[r].x);
+          acc[r].y = __builtin_fmaf(c, g.y, acc[r].y);
+          acc[r].z = __builtin_fmaf(c, g.z, acc[r].z);
+          acc[r].w = __builtin_fmaf(c, g.w, acc[r].w);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < UC_R; ++r) {
+      acc[r].x += __shfl_xor(acc[r].x, 32);
+      acc[r].y += __shfl_xor(acc[r].y, 32);
+      acc[r].z += __shfl_xor(acc[r].z, 32);
+      acc[r].w += __shfl_xor(acc[r].w, 32);
+      if (ok && half == 0) *reinterpret_cast<float4*>(va + r * w1 + 4 * xg) = acc[r];
+    }
+  }
+  __syncthreads();
+  // horizontal: adjoints of steps 1 .. s-1 in turn; the last writes G_s
+  float* out = a.gs[s] + (size_t)ch * hs * a.geo.lw[s] + (size_t)r0 * a.geo.lw[s];
+  for (int k = 1; k <= m; ++k) {
+    const int n_out = a.geo.lw[k], n_in = a.geo.lw[k + 1];
+    const float* src = (k & 1) ? va : vb;
+    float* dst = k == m ? out : ((k & 1) ? vb : va);
+    const float* h = s_tap[k] + UPS_K;
+    for (int p = tid; p < nr * n_in; p += 256) {
+      const int r = p / n_in, j = p % n_in;
+      const float* g = src + r * n_out;
+      float acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const int mp = q == 0 ? j : (q == 1 ? -1 : (q == 2 ? -2 : (q == 3 ? n_in : n_in + 1)));
+        const bool use = q == 0 || (q <= 2 ? j == 0 : j == n_in - 1);
+        if (!use) continue;
+#pragma unroll
+        for (int t = 0; t < UPS_K; ++t) {
+          const int x = 2 * mp - 3 + t;
+          if (x >= 0 && x < n_out) acc = __builtin_fmaf(h[t], g[x], acc);
+        }
+      }
+      dst[r * n_in + j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void ups_bwd_coarse_kernel(UpsBwdArgs st1, int st1_tiles, int st1_wgs,
+                                                             UpsComposeArgs c) {
+  const int b = blockIdx.x;
+  if (b < st1_wgs) ups_bwd_body<false>(st1, b % st1_tiles, st1_tiles, b / st1_tiles);
+  else ups_compose_body(c, b - st1_wgs);
+}
+
+__global__ __launch_bounds__(256) void ups_bwd_steps_kernel(UpsBwdSteps m) {
+  int k = 0;
+  while (k + 1 < m.n && (int)blockIdx.x >= m.first[k + 1]) ++k;
+  const int local = blockIdx.x - m.first[k];
+  ups_bwd_body<false>(m.st[k], local % m.tiles[k], m.tiles[k], local / m.tiles[k]);
 }
 
 __global__ void ups_expand_kernel(const float* __restrict__ src, float* __restrict__ dst, int n_steps, int shared) {

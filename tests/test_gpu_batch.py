@@ -61,12 +61,31 @@ def check_vs_oracle(c, loss4, grads):
         assert_grad_close(f"{c.name}.{name}", g, ref[name])
 
 
+def coarse_masks(c):
+    """Masks of g_y and g_ups over what a single image's coarse upsampling
+    adjoint sums in another order than the batch's step-by-step chain: with
+    a separable upsampler and L >= 5 levels, coolchic_backward takes the
+    gradients at the outputs of steps 3 .. L-2 from the composed adjoint of
+    steps 1 .. s-1, so latent levels >= 4 and the taps of steps >= 3 differ
+    by rounding only."""
+    L, taps = c.arch[0], c.arch[3]
+    my = np.zeros(c.y.size, bool)
+    mu = np.zeros(CS.sizes(c.arch)[1], bool)
+    if L >= 5:
+        off = sum((c.H >> l) * (c.W >> l) for l in range(4))
+        my[off:] = True
+        mu[3 * 2 * taps:] = True
+    return my, mu
+
+
 @pytest.mark.parametrize("arch,tile", [(CS.LOW, 0), (CS.FULL, 0), (CS.LOW, 16)], ids=["low", "full", "low_tile16"])
 def test_batch_default_equals_single_calls(B, BT, arch, tile):
     """With the default launch shape the batched pass runs the same blocks
-    over the same tiles as one coolchic_backward per image: bit-identical.
-    The upsampling forward's tile side only changes which work-group
-    computes an output, not its arithmetic: bit-identical too."""
+    over the same tiles as one coolchic_backward per image: bit-identical,
+    except where the single image's composed coarse adjoint sums in another
+    order (coarse_masks): there within 1e-5 of the gradient's 2-norm.  The
+    upsampling forward's tile side only changes which work-group computes
+    an output, not its arithmetic: bit-identical too."""
     cs = batch_cases(arch, SMALL_SIZES)
     enc = make_encoder(B, BT, cs, tune=(0, 0, 0, tile))
     enc.backward()
@@ -75,8 +94,15 @@ def test_batch_default_equals_single_calls(B, BT, arch, tile):
     for k, c in enumerate(cs):
         l4, g = single(B, c)
         assert np.array_equal(L[k], l4), (k, L[k], l4)
-        for a, b in zip(enc.grads(k), g):
-            assert np.array_equal(a, b), k
+        my, mu = coarse_masks(c)
+        for name, a, b, msk in zip(("g_y", "g_arm", "g_ups", "g_syn"), enc.grads(k), g,
+                                   (my, None, mu, None)):
+            if msk is None:
+                assert np.array_equal(a, b), (k, name)
+                continue
+            assert np.array_equal(a[~msk], b[~msk]), (k, name)
+            d = np.linalg.norm((a - b)[msk].astype(np.float64))
+            assert d <= 1e-5 * np.linalg.norm(b[msk].astype(np.float64)), (k, name, d)
 
 
 @pytest.mark.parametrize("tune", [(0, 0, 0), (7, 5, 0), (4096, 4096, 0), (0, 0, 1), (512, 2048, 1), (0, 0, 2),
