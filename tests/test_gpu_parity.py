@@ -143,6 +143,16 @@ def test_small_variants(B, idx):
     check_backward(B, c)
 
 
+@pytest.mark.parametrize("W", [1664, 1728])
+def test_wide_images_at_the_composed_adjoint_bound(B, W):
+    """One image's coarse upsampling adjoint is composed while its work-groups'
+    LDS fits (at L = 7 up to 1664 pixels wide, the largest such width, with
+    every buffer at its fullest) and step by step beyond (1728): both against
+    the oracle at the usual bars, every latent level separately."""
+    c = CS.make(f"wide64x{W}", 64, W, CS.LOW, seeds=(30, 31, 32, 33), n_blobs=20)
+    check_backward(B, c)
+
+
 def test_low_768x512(B):
     c = CS.low()
     check_forward(B, c)
