@@ -188,7 +188,7 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
     } else {
       for (int s = 0; s + 1 < L; ++s) P->upart[s] = take(cur, (size_t)P->up_rows[s] * 2 * UPS_K);
     }
-    P->tslot = take(cur, 1);  // the fused Adam's step number, passed from the side combine to the final one
+    P->tslot = take(cur, 1);  // the fused Adam's step number, stored by syn_t0_kernel for both combines
   }
   // 4-tap kernels run as 8-tap ones with zero taps on each side
   P->tapx = take(cur, P->K == 4 && L > 1 ? (P->shared ? UPS_SHARED_TAPS : (size_t)(L - 1) * 2 * UPS_K) : 0);
@@ -244,7 +244,7 @@ struct Side {
   int dev = -1;
   hipStream_t main = nullptr;  // the caller's stream this set serves
   hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, head = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, head = nullptr, armdone = nullptr;
   std::mutex mu;
 };
 constexpr int MAX_DEVICES = 64;  // devices with a static-scratch address (coolchic_train_step_noalloc)
@@ -278,7 +278,7 @@ int side_for(hipStream_t main, Side** out) {
   // cache fence when they are recorded (1-2 % of the training iteration)
   const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipEventCreateWithFlags(&sd.fork, fl) != hipSuccess || hipEventCreateWithFlags(&sd.join, fl) != hipSuccess ||
-      hipEventCreateWithFlags(&sd.head, fl) != hipSuccess)
+      hipEventCreateWithFlags(&sd.head, fl) != hipSuccess || hipEventCreateWithFlags(&sd.armdone, fl) != hipSuccess)
     return CC_EHIP;
   sd.dev = dev;
   sd.main = main;
@@ -517,9 +517,8 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
     ca.fold.y = y; ca.fold.u = u; ca.fold.quant = kmode(p->quant);
     if (final_part) {
       ca.fold.q0 = P.fold_split; ca.fold.q1 = P.geo.n_lat;
-      // at least one block: with a single level (no taps, every latent
-      // folded by the side combine) block 0 still stores the fused Adam's
-      // step count, its fold range being empty
+      // at least one block (a launch needs one): with a single level there
+      // are no taps and every latent is folded by the side combine
       blk += std::max(P.fold_grid1, blk == 0 ? 1 : 0);
     } else {
       ca.fold.q0 = 0; ca.fold.q1 = P.fold_split;
@@ -549,9 +548,9 @@ struct FusedAdam {
   float lr, beta1, beta2, eps;
 };
 
-void fuse_adam(const FusedAdam& f, CombineArgs& ca, bool last, int32_t* t_slot) {
+void fuse_adam(const FusedAdam& f, CombineArgs& ca, bool store_step, int32_t* t_slot) {
   ca.adam.on = 1;
-  ca.adam.last = last ? 1 : 0;
+  ca.adam.store_step = store_step ? 1 : 0;
   ca.adam.step = f.step;
   ca.adam.t_slot = t_slot;
   ca.adam.lr = f.lr; ca.adam.beta1 = f.beta1; ca.adam.beta2 = f.beta2; ca.adam.eps = f.eps;
@@ -590,8 +589,10 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
   build_backward(p, P, (float*)ws, img, y, u, arm_w, ups_w, syn_w, dloss, loss4, g_y, g_arm, g_ups, g_syn, &b);
   if (fused) {
     int32_t* t_slot = (int32_t*)((float*)ws + P.tslot);
-    fuse_adam(*fused, b.comb_side, false, t_slot);
-    fuse_adam(*fused, b.comb_main, true, t_slot);
+    fuse_adam(*fused, b.comb_side, true, t_slot);
+    fuse_adam(*fused, b.comb_main, false, t_slot);
+    b.syn.step = fused->step;
+    b.syn.t_slot = t_slot;
   }
   Side* sd = nullptr;
   if (!one_stream && (rc = side_for(st, &sd))) return rc;
@@ -623,6 +624,15 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
     if (!one_stream && (rc = fork_to(sd, st))) return rc;
     if ((rc = launch_stage(CC_STAGE_ARM, armk, P.arm_grid, ARM_THREADS, &b.arm, side))) return rc;
   }
+  // The final combine needs the ARM's context gradients but nothing of the
+  // side combine.  Where the ARM and the side combine are the longer stream
+  // (the 24-wide ARM, enqueued eagerly), it waits for the ARM alone so that
+  // the two combines overlap, and the side combine is joined at the end of
+  // the call (768x512: 4621 against 4504 iterations/s); otherwise it waits
+  // for both (low decoder: 6330 against 6249 eager; graph replays, which fork
+  // the ARM late: 4557 against 4487 and 6397 against 6162).
+  const bool overlap = !one_stream && !late_fork && P.C == 24;
+  if (overlap && hipEventRecord(sd->armdone, side) != hipSuccess) return CC_EHIP;
   // level 0 of g_y is final: the side combine may start
   if (!one_stream && (rc = side_waits(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_side_grid, 256, &b.comb_side, side))) return rc;
@@ -664,8 +674,10 @@ int backward_impl(const cc_problem* p, const float* img, const float* y, const f
         hipSuccess)
       return CC_EHIP;
   }
-  if (!one_stream && (rc = join_from(sd, st))) return rc;
+  if (overlap && hipStreamWaitEvent(st, sd->armdone, 0) != hipSuccess) return CC_EHIP;
+  if (!overlap && !one_stream && (rc = join_from(sd, st))) return rc;
   if ((rc = launch((const void*)combine_kernel, b.comb_main_grid, 256, &b.comb_main, st))) return rc;
+  if (overlap && (rc = join_from(sd, st))) return rc;
   return hipGetLastError() == hipSuccess ? CC_OK : CC_EHIP;
 }
 

@@ -163,6 +163,8 @@ struct SynArgs {
   float* hpart;        // backward: [head tiles][Hs L + 4 Hs + 3] 1x1-layer weight-gradient partials
   float* spart;        // [gridDim] squared-error partial sums
   float* flag_clear;   // optional: block 0 of syn_t0_kernel stores 0 here (the non-finite flag of the pass)
+  const int32_t* step; // optional (Adam fused into the combines): block 0 of syn_t0_kernel stores
+  int32_t* t_slot;     //   step[0] + 1 in *t_slot, the step number both combine launches use
   int n_tiles_x, n_tiles;
 };
 const void* syn_t0_kernel_for(int Hs, int nres, bool batch);
@@ -204,12 +206,13 @@ struct CombineArgs {
   int loss_block;
   FinalArgs fin;
   // Adam fused into the launch (on = 1): each final gradient value is
-  // applied to its parameter at once.  The first of the pass's two launches
-  // (last = 0) takes t = step[0] + 1 and its block 0 stores t in *t_slot; the
-  // last one (last = 1) reads t there and its block 0 stores it in step[0]
-  // (none of its blocks reads step[0], so no completion count is needed)
+  // applied to its parameter at once, with the step number t = *t_slot that
+  // syn_t0_kernel stored at the start of the pass (step[0] + 1).  The launch
+  // with store_step = 1 (the side combine) has its block 0 store t in
+  // step[0]; no kernel of the pass reads step[0] after syn_t0_kernel, so the
+  // two launches may run in either order or together
   struct {
-    int on, last;
+    int on, store_step;
     int32_t* step;
     int32_t* t_slot;
     float lr, beta1, beta2, eps;

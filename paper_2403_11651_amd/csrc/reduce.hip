@@ -120,9 +120,9 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, const int bid
   }
   float k1 = 0.0f, k2 = 0.0f;
   if (a.adam.on) {
-    const int t = a.adam.last ? *a.adam.t_slot : a.adam.step[0] + 1;
+    const int t = *a.adam.t_slot;
     adam_coeffs(a.adam.beta1, a.adam.beta2, t, k1, k2);
-    if (bid == 0 && tid == 0) *(a.adam.last ? a.adam.step : a.adam.t_slot) = t;
+    if (a.adam.store_step && bid == 0 && tid == 0) *a.adam.step = t;
   }
   const int n_red = a.block_start[a.nseg];
   bool bad = false;

@@ -145,6 +145,7 @@ __device__ __forceinline__ void syn_t0_body(const SynArgs& a, const int bid) {
   const int r0 = i0 / 2 - 2, c0 = j0 / 2 - 2;
   const int nch = L - 1;
   if (bid == 0 && tid == 0 && a.flag_clear) *a.flag_clear = 0.0f;
+  if (bid == 0 && tid == 0 && a.t_slot) *a.t_slot = a.step[0] + 1;
   float kv[UPS_K], kh[UPS_K];
   load_taps(shared ? nullptr : a.ups0, kv, kh);
   stage_weights(sw, a.w, L, tid);
