@@ -9,7 +9,11 @@
 // w[ky][kx] = v[ky] h[kx] for the separable per-step kernels (applied as the
 // outer product) or one non-separable kernel shared by every step (Table I).
 // The step s = 0 is fused into the synthesis kernels; these kernels produce
-// the steps s >= 1 and the adjoint of every step.
+// the steps s >= 1 and the adjoint of every step: one launch per step, or,
+// for one image with separable kernels and L >= 5, step 0, then step 1 beside
+// work-groups that compose the inputs of steps 3 .. L-2 from step 1's input
+// (the adjoint is linear, so several steps fold into banded 1-D products),
+// then steps 2 .. L-2 together.
 #include "common.hpp"
 #include "kernels.hpp"
 
