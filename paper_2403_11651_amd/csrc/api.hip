@@ -17,6 +17,10 @@ namespace {
 constexpr size_t ALIGN_FLOATS = 64;  // 256-byte alignment of workspace blocks
 constexpr int MAX_GRID = 1280;
 constexpr int RED_CPB = 16;  // gradient columns per combine work-group (16 row groups each)
+// columns per combine work-group for a segment of `rows` partial rows: tall
+// segments (the synthesis partials of every pixel tile) take four columns
+// and 64 row groups, so that each thread sums a few dozen rows
+inline int red_cpb(long long rows) { return rows >= 1024 ? 4 : RED_CPB; }
 // a batch's side combine starts after the level-0 upsampling adjoint and also
 // folds level 1 (one image: after the head backward, level 0 only)
 constexpr int BATCH_SIDE_LEVELS = 2;
@@ -148,15 +152,18 @@ int make_plan(const cc_problem* p, int which, Plan* P, int arm_grid = 0, int syn
   P->fold_grid1 = cdiv(g.n_lat - P->fold_split, 256);
   // column reductions, one column per block (256 row groups: every column
   // has hundreds to thousands of partial rows)
-  P->red_blocks_arm = cdiv((int)P->n_arm, RED_CPB);
+  P->red_blocks_arm = cdiv((int)P->n_arm, red_cpb(P->arm_grid));
   P->n_head = P->Hs * L + 4 * P->Hs + 3;
   P->head_grid = cdiv(p->H, SYN_HD) * cdiv(p->W, SYN_HD);
-  P->red_blocks_syn = cdiv(P->nres * 84, RED_CPB) + cdiv(P->n_head, RED_CPB);
+  P->red_blocks_syn = cdiv(P->nres * 84, red_cpb(P->syn_grid)) + cdiv(P->n_head, red_cpb(P->head_grid));
   P->red_grid = P->red_blocks_arm + P->red_blocks_syn;
   // tap-gradient reduction blocks (segments as build_backward lays them out)
+  long long ups_rows_all = 0;
+  for (int s = 0; s + 1 < L; ++s) ups_rows_all += (long long)P->ups_grid[s] * P->ups_chunks[s];
   for (int s = 0; s + 1 < L; ++s) {
-    if (P->shared) P->red_blocks_ups[s] = s == 0 ? (P->K == 8 ? cdiv(UPS_SHARED_TAPS, RED_CPB) : 4) : 0;
-    else P->red_blocks_ups[s] = P->K == 8 ? cdiv(2 * UPS_K, RED_CPB) : 2;
+    const int c = red_cpb((long long)P->ups_grid[s] * P->ups_chunks[s]), ca = red_cpb(ups_rows_all);
+    if (P->shared) P->red_blocks_ups[s] = s == 0 ? (P->K == 8 ? cdiv(UPS_SHARED_TAPS, ca) : 4 * cdiv(4, ca)) : 0;
+    else P->red_blocks_ups[s] = P->K == 8 ? cdiv(2 * UPS_K, c) : 2 * cdiv(4, c);
     P->red_grid += P->red_blocks_ups[s];
   }
 
@@ -477,7 +484,7 @@ void build_backward(const cc_problem* p, const Plan& P, float* W, const float* i
   auto build = [&](CombineArgs& ca, int* grid, bool final_part) {
     int ns = 0, blk = 0;
     auto add = [&](const float* src, int rows, int cols, float* dst, int ld = 0) {
-      const int cpb = RED_CPB;
+      const int cpb = red_cpb(rows);
       ca.seg[ns] = RedSeg{src, rows, cols, ld ? ld : cols, cpb, dst};
       ca.block_start[ns] = blk;
       blk += cdiv(cols, cpb);
