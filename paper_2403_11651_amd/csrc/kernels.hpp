@@ -177,7 +177,7 @@ constexpr int RED_MAXSEG = 12;
 struct RedSeg {
   const float* src;    // [rows][ld]
   int rows, cols, ld;
-  int cpb;             // columns per block: 16 (16 row groups) or 1 (256 row groups)
+  int cpb;             // columns per block: 16 or, for 1024 rows or more, 4 (16 or 64 row groups)
   float* dst;          // [cols]
   float *th, *m, *v;   // fused Adam: the parameters of the columns and their moments, or null
 };
